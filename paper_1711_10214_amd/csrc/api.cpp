@@ -1,0 +1,1016 @@
+// Host runtime of libashrt: argument validation, plans (small device tables
+// and work lists), workspace layout, the operator pipelines and the IRLS-CG
+// driver, behind the C ABI declared in include/ashrt.h.
+//
+// Nothing here allocates large buffers: the caller's workspace holds every
+// intermediate spectrum and solver vector.  All launches go to the caller's
+// stream; solver step lengths stay on the device, so a solve needs no host
+// round trip unless a report or an early-stopping tolerance is requested.
+#include "ashrt.h"
+#include "kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ashrt;
+
+// ------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ASHRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------ sizes
+static bool is_fft_len(int n) {
+  if (n < 2) return false;
+  int s = 0;
+  while ((n & 1) == 0) {
+    n >>= 1;
+    ++s;
+  }
+  return n == 1 || n == 3;
+}
+
+static int auto_fft_len(int n) {
+  const long long target = 2LL * n;
+  long long best = -1;
+  for (long long p = 1; p < 4 * target + 8; p *= 2) {
+    for (long long c : {p, 3 * p})
+      if (c >= target && (best < 0 || c < best)) best = c;
+  }
+  return (int)best;
+}
+
+static long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------ C ABI: defaults/validation
+extern "C" void ashrt_desc_default(ashrt_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->half_width = 4;
+}
+
+extern "C" void irls_params_default(irls_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->p = 1;
+  p->q = 2;
+  p->n_outer = 10;
+  p->n_inner = 20;
+  p->b_r = 1.345;
+  p->b_m = 1.0;
+  p->tol = 0.0;
+  p->eps_floor_rel = 1e-6;
+  p->freeze_eps = 0;
+}
+
+struct Resolved {
+  int nt, nx, ntp, nxp, P, R, jlo, jhi, kmax;
+};
+
+static int resolve_desc(const ashrt_desc* d, Resolved* out) {
+  if (!d) return fail(ASHRT_E_INVALID_ARG, "desc is NULL");
+  if (d->nt < 2 || d->nx < 2) return fail(ASHRT_E_INVALID_ARG, "nt and nx must be >= 2");
+  if (!(d->dt > 0.0) || !(d->dx > 0.0) || !std::isfinite(d->dt) || !std::isfinite(d->dx))
+    return fail(ASHRT_E_INVALID_ARG, "dt and dx must be finite and > 0");
+  if (d->npanel < 1) return fail(ASHRT_E_INVALID_ARG, "npanel must be >= 1");
+  if (!d->vel) return fail(ASHRT_E_INVALID_ARG, "vel is NULL");
+  for (int p = 0; p < d->npanel; ++p) {
+    if (!(d->vel[p] >= 0.0) || !std::isfinite(d->vel[p]))
+      return fail(ASHRT_E_INVALID_ARG, "velocities must be finite and >= 0");
+    if (d->tau0_samples && d->tau0_samples[p] < 0)
+      return fail(ASHRT_E_INVALID_ARG, "tau0_samples must be >= 0");
+    if (d->panel_scale && !std::isfinite(d->panel_scale[p]))
+      return fail(ASHRT_E_INVALID_ARG, "panel_scale must be finite");
+  }
+  const int R = d->half_width == 0 ? 4 : d->half_width;
+  if (R < 1 || R > kMaxHalfWidth) return fail(ASHRT_E_INVALID_ARG, "half_width must be 1..8");
+  const int ntp = d->ntp ? d->ntp : auto_fft_len(d->nt);
+  const int nxp = d->nxp ? d->nxp : auto_fft_len(d->nx);
+  if (!is_fft_len(ntp) || !is_fft_len(nxp))
+    return fail(ASHRT_E_UNSUPPORTED_SIZE, "ntp and nxp must be 2^a or 3*2^a");
+  if (ntp < d->nt || nxp < d->nx) return fail(ASHRT_E_INVALID_ARG, "ntp >= nt and nxp >= nx required");
+  if (ntp < 8 || ntp > kRowMaxN) return fail(ASHRT_E_UNSUPPORTED_SIZE, "ntp must be in [8, 4096]");
+  if (nxp < 4 || nxp > 4096) return fail(ASHRT_E_UNSUPPORTED_SIZE, "nxp must be in [4, 4096]");
+  if (!std::isfinite(d->fmin_hz) || !std::isfinite(d->fmax_hz) || d->fmin_hz < 0.0)
+    return fail(ASHRT_E_INVALID_ARG, "fmin_hz must be >= 0 and both band edges finite");
+  int jlo = (int)std::ceil(d->fmin_hz * ntp * d->dt);
+  jlo = std::max(1, jlo);
+  int jhi = ntp / 2 - 1;
+  if (d->fmax_hz > 0.0) jhi = std::min(jhi, (int)std::floor(d->fmax_hz * ntp * d->dt));
+  if (jhi < jlo) return fail(ASHRT_E_INVALID_ARG, "the mapped band is empty");
+  if (d->wavelet_amp) {
+    for (int j = 0; j <= ntp / 2; ++j)
+      if (!std::isfinite(d->wavelet_amp[j])) return fail(ASHRT_E_INVALID_ARG, "wavelet_amp must be finite");
+  }
+  if (out) {
+    out->nt = d->nt;
+    out->nx = d->nx;
+    out->ntp = ntp;
+    out->nxp = nxp;
+    out->P = d->npanel;
+    out->R = R;
+    out->jlo = jlo;
+    out->jhi = jhi;
+    out->kmax = std::min(ntp / 2 - 1, jhi + R);
+  }
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_desc_validate(const ashrt_desc* d) { return resolve_desc(d, nullptr); }
+
+extern "C" int irls_params_validate(const irls_params* p) {
+  if (!p) return fail(ASHRT_E_INVALID_ARG, "params is NULL");
+  if (p->p != 1 && p->p != 2) return fail(ASHRT_E_INVALID_ARG, "p must be 1 or 2");
+  if (p->q != 1 && p->q != 2) return fail(ASHRT_E_INVALID_ARG, "q must be 1 or 2");
+  if (p->n_outer < 1 || p->n_outer > 64) return fail(ASHRT_E_INVALID_ARG, "n_outer must be 1..64");
+  if (p->n_inner < 1 || p->n_inner > 100000) return fail(ASHRT_E_INVALID_ARG, "n_inner must be >= 1");
+  if (!(p->b_r > 0.0) || !std::isfinite(p->b_r)) return fail(ASHRT_E_INVALID_ARG, "b_r must be > 0");
+  if (!(p->b_m > 0.0) || !std::isfinite(p->b_m)) return fail(ASHRT_E_INVALID_ARG, "b_m must be > 0");
+  if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(ASHRT_E_INVALID_ARG, "tol must be >= 0");
+  if (!(p->eps_floor_rel >= 0.0) || !std::isfinite(p->eps_floor_rel))
+    return fail(ASHRT_E_INVALID_ARG, "eps_floor_rel must be >= 0");
+  return ASHRT_OK;
+}
+
+extern "C" const char* ashrt_status_string(int s) {
+  switch (s) {
+    case ASHRT_OK: return "ok";
+    case ASHRT_E_INVALID_ARG: return "invalid argument";
+    case ASHRT_E_UNSUPPORTED_SIZE: return "unsupported size";
+    case ASHRT_E_HIP: return "HIP runtime error";
+    case ASHRT_E_NONFINITE: return "non-finite result";
+    case ASHRT_E_OOM: return "out of memory";
+    case ASHRT_E_NOT_IMPLEMENTED: return "not implemented";
+    case ASHRT_E_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* ashrt_last_error(void) { return g_last_error.c_str(); }
+extern "C" int ashrt_abi_version(void) { return ASHRT_ABI_VERSION; }
+
+// ------------------------------------------------------------ plans
+struct GatherHost {
+  Resolved z;
+  int nrows, tileT, ntiles, nchunk;
+  std::vector<PanelDev> panels;
+  std::vector<float> wav;
+  long long d_off, m_off, mask_off, X_off, H_off, Dp_off;
+  long long nd() const { return (long long)z.nx * z.nt; }
+  long long nm() const { return (long long)z.P * z.nx * z.nt; }
+};
+
+struct WsLayout {
+  size_t X, H, Dp;                                  // operator scratch
+  size_t r, s, q, Wr, pdir, g, u, Wminv;            // solver vectors
+  size_t part, sc, sel, hist, rep;
+  size_t total;
+};
+
+struct PlanImpl {
+  int device = 0;
+  int R = 4;
+  int ngather = 0;
+  std::vector<GatherHost> g;
+  void* dev = nullptr;  // one allocation holding every device table
+  GatherDev* d_gd = nullptr;
+  PanelDev* d_pan = nullptr;
+  float2* d_tw = nullptr;
+  float* d_wav = nullptr;
+  WorkItem *d_xm = nullptr, *d_xd = nullptr, *d_rf = nullptr, *d_rfin = nullptr, *d_ra = nullptr;
+  int n_xm = 0, n_xd = 0, n_rf = 0, n_rfin = 0, n_ra = 0;
+  VecItem *d_vm = nullptr, *d_vd = nullptr;
+  int n_vm = 0, n_vd = 0;
+  size_t lds_x = 0, lds_rf = 0, lds_ra = 0;
+  long long tot_d = 0, tot_m = 0, tot_mask = 0, tot_X = 0, tot_H = 0, tot_Dp = 0;
+
+  WsLayout layout(int op, int q) const {
+    WsLayout L{};
+    long long off = 0;
+    auto take = [&](long long bytes) {
+      const long long o = off;
+      off = align_up(off + std::max(bytes, 0LL), 256);
+      return (size_t)o;
+    };
+    L.X = take(tot_X * 8);
+    L.H = take(tot_H * 8);
+    L.Dp = take(tot_Dp * 8);
+    if (op == ASHRT_OP_INVERT) {
+      L.r = take(tot_d * 4);
+      L.s = take(tot_d * 4);
+      L.q = take(tot_d * 4);
+      L.Wr = take(tot_d * 4);
+      L.pdir = take(tot_m * 4);
+      L.g = take(tot_m * 4);
+      if (q == 1) {
+        L.u = take(tot_m * 4);
+        L.Wminv = take(tot_m * 4);
+      }
+      L.part = take((long long)2 * std::max(n_vm, n_vd) * 8);
+      L.sc = take((long long)ngather * kNScal * 8);
+      L.sel = take((long long)ngather * sizeof(SelState));
+      L.hist = take((long long)ngather * 2 * kSelBins * 4);
+      L.rep = take((long long)ngather * sizeof(RepDev));
+    }
+    L.total = (size_t)off;
+    return L;
+  }
+};
+
+struct ashrt_plan {
+  PlanImpl impl;
+};
+struct ashrt_batch_plan {
+  PlanImpl impl;
+};
+
+static int build_gather(const ashrt_desc* d, GatherHost* gh) {
+  int st = resolve_desc(d, &gh->z);
+  if (st) return st;
+  const Resolved& z = gh->z;
+  gh->nrows = z.nxp / 2;
+  int T = std::min(64, 2 * (kXfftMaxTotal / z.nxp));
+  T = std::max(2, T & ~1);
+  gh->tileT = T;
+  gh->ntiles = (z.nt + T - 1) / T;
+  gh->panels.resize(z.P);
+  const double bin = (double)z.ntp * d->dt / ((double)z.nxp * d->dx);
+  for (int p = 0; p < z.P; ++p) {
+    const double c = d->vel[p] * bin;
+    gh->panels[p].c2 = c * c;
+    gh->panels[p].scale = d->panel_scale ? (float)d->panel_scale[p] : 1.0f;
+    gh->panels[p].n0 = d->tau0_samples ? d->tau0_samples[p] : 0;
+  }
+  gh->wav.clear();
+  if (d->wavelet_amp) {
+    gh->wav.resize(z.ntp / 2 + 1);
+    for (int j = 0; j <= z.ntp / 2; ++j) gh->wav[j] = (float)d->wavelet_amp[j];
+  }
+  return ASHRT_OK;
+}
+
+static void destroy_impl(PlanImpl& P) {
+  if (P.dev) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != P.device) {
+      (void)hipSetDevice(P.device);
+      (void)hipFree(P.dev);
+      (void)hipSetDevice(cur);
+    } else {
+      (void)hipFree(P.dev);
+    }
+    P.dev = nullptr;
+  }
+}
+
+// Build work lists and device tables for a set of gathers.
+static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImpl& P) {
+  if (!descs || ngather < 1) return fail(ASHRT_E_INVALID_ARG, "no gathers");
+  P.device = device;
+  P.ngather = ngather;
+  P.g.resize(ngather);
+  for (int i = 0; i < ngather; ++i) {
+    int st = build_gather(&descs[i], &P.g[i]);
+    if (st) return st;
+  }
+  P.R = P.g[0].z.R;
+  for (auto& gh : P.g)
+    if (gh.z.R != P.R) return fail(ASHRT_E_INVALID_ARG, "all gathers of a batch must share half_width");
+
+  // panel chunks so that the row passes have enough workgroups
+  long long total_rows = 0;
+  for (auto& gh : P.g) total_rows += gh.nrows;
+  for (auto& gh : P.g) {
+    long long want = (1024 + total_rows - 1) / total_rows;
+    gh.nchunk = (int)std::max(1LL, std::min<long long>(want, gh.z.P));
+  }
+
+  // packed offsets
+  long long od = 0, om = 0, omask = 0, oX = 0, oH = 0, oDp = 0;
+  for (auto& gh : P.g) {
+    gh.d_off = od;
+    gh.m_off = om;
+    gh.mask_off = omask;
+    gh.X_off = oX;
+    gh.H_off = oH;
+    gh.Dp_off = oDp;
+    od += gh.nd();
+    om += gh.nm();
+    omask += gh.z.nx;
+    oX += (long long)gh.z.P * gh.nrows * gh.z.nt;
+    oH += (long long)gh.nrows * gh.z.nt;
+    oDp += (long long)gh.nchunk * gh.nrows * 2 * (gh.z.jhi - gh.z.jlo + 1);
+  }
+  P.tot_d = od;
+  P.tot_m = om;
+  P.tot_mask = omask;
+  P.tot_X = oX;
+  P.tot_H = oH;
+  P.tot_Dp = oDp;
+
+  // twiddle pool (one table per distinct length)
+  std::vector<int> lens;
+  for (auto& gh : P.g) {
+    lens.push_back(gh.z.ntp);
+    lens.push_back(gh.z.nxp);
+  }
+  std::sort(lens.begin(), lens.end());
+  lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+  std::vector<float2> tw;
+  std::vector<int> tw_off(lens.size());
+  for (size_t i = 0; i < lens.size(); ++i) {
+    tw_off[i] = (int)tw.size();
+    const int N = lens[i];
+    for (int m = 0; m < N; ++m) {
+      const double a = -2.0 * M_PI * (double)m / (double)N;
+      tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+    }
+  }
+  auto tw_of = [&](int N) {
+    return tw_off[std::lower_bound(lens.begin(), lens.end(), N) - lens.begin()];
+  };
+
+  std::vector<PanelDev> pan;
+  std::vector<float> wav;
+  std::vector<GatherDev> gd(ngather);
+  std::vector<WorkItem> xm, xd, rf, rfin, ra;
+  std::vector<VecItem> vm, vd;
+  for (int gi = 0; gi < ngather; ++gi) {
+    GatherHost& gh = P.g[gi];
+    GatherDev& G = gd[gi];
+    std::memset(&G, 0, sizeof(G));
+    G.nt = gh.z.nt;
+    G.nx = gh.z.nx;
+    G.ntp = gh.z.ntp;
+    G.nxp = gh.z.nxp;
+    G.nrows = gh.nrows;
+    G.jlo = gh.z.jlo;
+    G.jhi = gh.z.jhi;
+    G.kmax = gh.z.kmax;
+    G.npanel = gh.z.P;
+    G.panel_off = (int)pan.size();
+    pan.insert(pan.end(), gh.panels.begin(), gh.panels.end());
+    G.tw_t_off = tw_of(gh.z.ntp);
+    G.tw_x_off = tw_of(gh.z.nxp);
+    if (!gh.wav.empty()) {
+      G.wav_off = (int)wav.size();
+      wav.insert(wav.end(), gh.wav.begin(), gh.wav.end());
+    } else {
+      G.wav_off = -1;
+    }
+    G.tileT = gh.tileT;
+    G.ntiles = gh.ntiles;
+    G.nchunk = gh.nchunk;
+    G.d_off = gh.d_off;
+    G.m_off = gh.m_off;
+    G.mask_off = gh.mask_off;
+    G.X_off = gh.X_off;
+    G.H_off = gh.H_off;
+    G.Dp_off = gh.Dp_off;
+    for (int p = 0; p < gh.z.P; ++p)
+      for (int t = 0; t < gh.ntiles; ++t) xm.push_back(WorkItem{gi, p, t, 0});
+    for (int t = 0; t < gh.ntiles; ++t) xd.push_back(WorkItem{gi, 0, t, 0});
+    for (int r = 0; r < gh.nrows; ++r) {
+      for (int c = 0; c < gh.nchunk; ++c) {
+        rf.push_back(WorkItem{gi, r, c, 0});
+        ra.push_back(WorkItem{gi, r, c, 0});
+      }
+      rfin.push_back(WorkItem{gi, r, 0, 0});
+    }
+    G.mit_lo = (int)vm.size();
+    for (long long s = 0; s < gh.nm(); s += kVecChunk)
+      vm.push_back(VecItem{gi, 0, gh.m_off + s, std::min(kVecChunk, gh.nm() - s)});
+    G.mit_hi = (int)vm.size();
+    G.dit_lo = (int)vd.size();
+    for (long long s = 0; s < gh.nd(); s += kVecChunk)
+      vd.push_back(VecItem{gi, 0, gh.d_off + s, std::min(kVecChunk, gh.nd() - s)});
+    G.dit_hi = (int)vd.size();
+  }
+  if (wav.empty()) wav.push_back(0.f);
+
+  // LDS per kernel family (max over gathers)
+  for (auto& gh : P.g) {
+    const int nband = gh.z.jhi - gh.z.jlo + 1;
+    P.lds_x = std::max(P.lds_x, (size_t)(gh.tileT / 2) * (gh.z.nxp + 1) * 8);
+    P.lds_rf = std::max(P.lds_rf, (size_t)gh.z.ntp * 8);
+    P.lds_ra = std::max(P.lds_ra, (size_t)gh.z.ntp * 16 + (size_t)nband * 20);
+  }
+  if (P.lds_x > 160 * 1024 || P.lds_ra > 160 * 1024)
+    return fail(ASHRT_E_UNSUPPORTED_SIZE, "LDS requirement exceeds 160 KB");
+
+  // one device allocation for all tables
+  struct Part {
+    const void* src;
+    size_t bytes;
+    void** dst;
+  };
+  P.n_xm = (int)xm.size();
+  P.n_xd = (int)xd.size();
+  P.n_rf = (int)rf.size();
+  P.n_rfin = (int)rfin.size();
+  P.n_ra = (int)ra.size();
+  P.n_vm = (int)vm.size();
+  P.n_vd = (int)vd.size();
+  std::vector<Part> parts = {
+      {gd.data(), gd.size() * sizeof(GatherDev), (void**)&P.d_gd},
+      {pan.data(), pan.size() * sizeof(PanelDev), (void**)&P.d_pan},
+      {tw.data(), tw.size() * sizeof(float2), (void**)&P.d_tw},
+      {wav.data(), wav.size() * sizeof(float), (void**)&P.d_wav},
+      {xm.data(), xm.size() * sizeof(WorkItem), (void**)&P.d_xm},
+      {xd.data(), xd.size() * sizeof(WorkItem), (void**)&P.d_xd},
+      {rf.data(), rf.size() * sizeof(WorkItem), (void**)&P.d_rf},
+      {rfin.data(), rfin.size() * sizeof(WorkItem), (void**)&P.d_rfin},
+      {ra.data(), ra.size() * sizeof(WorkItem), (void**)&P.d_ra},
+      {vm.data(), vm.size() * sizeof(VecItem), (void**)&P.d_vm},
+      {vd.data(), vd.size() * sizeof(VecItem), (void**)&P.d_vd},
+  };
+  size_t total = 0;
+  std::vector<size_t> offs;
+  for (auto& pt : parts) {
+    offs.push_back(total);
+    total = (size_t)align_up((long long)(total + pt.bytes), 256);
+  }
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  HIP_TRY(hipSetDevice(device));
+  std::vector<unsigned char> host(total, 0);
+  for (size_t i = 0; i < parts.size(); ++i)
+    if (parts[i].bytes) std::memcpy(host.data() + offs[i], parts[i].src, parts[i].bytes);
+  hipError_t e = hipMalloc(&P.dev, total);
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    P.dev = nullptr;
+    return fail(ASHRT_E_OOM, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(P.dev, host.data(), total, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = op_kernels_set_lds(P.lds_x, P.lds_rf, P.lds_ra);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    destroy_impl(P);
+    return fail(ASHRT_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
+  for (size_t i = 0; i < parts.size(); ++i) *parts[i].dst = (unsigned char*)P.dev + offs[i];
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_plan_create(const ashrt_desc* desc, int device, ashrt_plan** out) {
+  if (!out) return fail(ASHRT_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ashrt_plan* p = new (std::nothrow) ashrt_plan();
+  if (!p) return fail(ASHRT_E_OOM, "host allocation failed");
+  int st = create_impl(desc, 1, device, p->impl);
+  if (st) {
+    destroy_impl(p->impl);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return ASHRT_OK;
+}
+
+extern "C" void ashrt_plan_destroy(ashrt_plan* p) {
+  if (!p) return;
+  destroy_impl(p->impl);
+  delete p;
+}
+
+extern "C" int ashrt_batch_plan_create(const ashrt_desc* descs, int32_t ngather, int device,
+                                       ashrt_batch_plan** out) {
+  if (!out) return fail(ASHRT_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ashrt_batch_plan* p = new (std::nothrow) ashrt_batch_plan();
+  if (!p) return fail(ASHRT_E_OOM, "host allocation failed");
+  int st = create_impl(descs, ngather, device, p->impl);
+  if (st) {
+    destroy_impl(p->impl);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return ASHRT_OK;
+}
+
+extern "C" void ashrt_batch_plan_destroy(ashrt_batch_plan* p) {
+  if (!p) return;
+  destroy_impl(p->impl);
+  delete p;
+}
+
+extern "C" int ashrt_plan_get_info(const ashrt_plan* plan, ashrt_plan_info* info) {
+  if (!plan || !info) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  const PlanImpl& P = plan->impl;
+  const GatherHost& g = P.g[0];
+  std::memset(info, 0, sizeof(*info));
+  info->nt = g.z.nt;
+  info->nx = g.z.nx;
+  info->ntp = g.z.ntp;
+  info->nxp = g.z.nxp;
+  info->npanel = g.z.P;
+  info->half_width = g.z.R;
+  info->jlo = g.z.jlo;
+  info->jhi = g.z.jhi;
+  info->kmax = g.z.kmax;
+  info->nchunk = g.nchunk;
+  info->ws_forward = P.layout(ASHRT_OP_FORWARD, 2).total;
+  info->ws_adjoint = P.layout(ASHRT_OP_ADJOINT, 2).total;
+  info->ws_invert_q2 = P.layout(ASHRT_OP_INVERT, 2).total;
+  info->ws_invert_q1 = P.layout(ASHRT_OP_INVERT, 1).total;
+  return ASHRT_OK;
+}
+
+static int ws_bytes_impl(const PlanImpl& P, int op, const irls_params* prm, size_t* bytes) {
+  if (!bytes) return fail(ASHRT_E_INVALID_ARG, "bytes is NULL");
+  if (op < ASHRT_OP_FORWARD || op > ASHRT_OP_INVERT) return fail(ASHRT_E_INVALID_ARG, "unknown op");
+  int q = 2;
+  if (op == ASHRT_OP_INVERT) {
+    if (!prm) return fail(ASHRT_E_INVALID_ARG, "params needed for ASHRT_OP_INVERT");
+    int st = irls_params_validate(prm);
+    if (st) return st;
+    q = prm->q;
+  }
+  *bytes = P.layout(op, q).total;
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_workspace_bytes(const ashrt_plan* plan, int op, const irls_params* prm, size_t* bytes) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return ws_bytes_impl(plan->impl, op, prm, bytes);
+}
+
+extern "C" int ashrt_batch_workspace_bytes(const ashrt_batch_plan* plan, int op, const irls_params* prm,
+                                           size_t* bytes) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return ws_bytes_impl(plan->impl, op, prm, bytes);
+}
+
+extern "C" int ashrt_batch_layout(const ashrt_batch_plan* plan, int64_t* data_off, int64_t* model_off,
+                                  int64_t* mask_off, int64_t* data_total, int64_t* model_total,
+                                  int64_t* mask_total) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  const PlanImpl& P = plan->impl;
+  for (int i = 0; i < P.ngather; ++i) {
+    if (data_off) data_off[i] = P.g[i].d_off;
+    if (model_off) model_off[i] = P.g[i].m_off;
+    if (mask_off) mask_off[i] = P.g[i].mask_off;
+  }
+  if (data_total) *data_total = P.tot_d;
+  if (model_total) *model_total = P.tot_m;
+  if (mask_total) *mask_total = P.tot_mask;
+  return ASHRT_OK;
+}
+
+// ------------------------------------------------------------ operator pipelines
+namespace {
+
+struct Ctx {
+  const PlanImpl* P;
+  unsigned char* ws;
+  WsLayout L;
+  hipStream_t s;
+  float2* X() const { return (float2*)(ws + L.X); }
+  float2* H() const { return (float2*)(ws + L.H); }
+  float2* Dp() const { return (float2*)(ws + L.Dp); }
+};
+
+RowsArgs rows_args(const Ctx& c, const WorkItem* items, int n) {
+  RowsArgs a{};
+  a.gd = c.P->d_gd;
+  a.items = items;
+  a.nitems = n;
+  a.panels = c.P->d_pan;
+  a.tw = c.P->d_tw;
+  a.wav = c.P->d_wav;
+  a.X = c.X();
+  a.H = c.H();
+  a.Dp = c.Dp();
+  return a;
+}
+
+// d_out = epilogue(L (mul_m * m)); the epilogue is: raw_out = y; y = sub - y;
+// y *= mask; y *= wmul.
+hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* d_out, const float* sub,
+                       const float* wmul, float* raw_out, const uint8_t* tmask) {
+  const PlanImpl& P = *c.P;
+  XfwdArgs xa{};
+  xa.gd = P.d_gd;
+  xa.items = P.d_xm;
+  xa.nitems = P.n_xm;
+  xa.is_model = 1;
+  xa.src = m;
+  xa.mul = mul_m;
+  xa.tmask = nullptr;
+  xa.dst = c.X();
+  xa.tw = P.d_tw;
+  hipError_t e = launch_xfft_fwd(xa, P.lds_x, c.s);
+  if (e != hipSuccess) return e;
+  e = launch_rows_fwd(P.R, rows_args(c, P.d_rf, P.n_rf), P.lds_rf, c.s);
+  if (e != hipSuccess) return e;
+  e = launch_rows_fwd_fin(rows_args(c, P.d_rfin, P.n_rfin), P.lds_rf, c.s);
+  if (e != hipSuccess) return e;
+  XinvArgs ia{};
+  ia.gd = P.d_gd;
+  ia.items = P.d_xd;
+  ia.nitems = P.n_xd;
+  ia.is_model = 0;
+  ia.src = c.H();
+  ia.out = d_out;
+  ia.sub = sub;
+  ia.wmul = wmul;
+  ia.raw_out = raw_out;
+  ia.tmask = tmask;
+  ia.tw = P.d_tw;
+  return launch_xfft_inv(ia, P.lds_x, c.s);
+}
+
+// m_out = wmul * L' (mask * mul_d * d)
+hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const uint8_t* tmask, float* m_out,
+                       const float* wmul) {
+  const PlanImpl& P = *c.P;
+  XfwdArgs xa{};
+  xa.gd = P.d_gd;
+  xa.items = P.d_xd;
+  xa.nitems = P.n_xd;
+  xa.is_model = 0;
+  xa.src = d;
+  xa.mul = mul_d;
+  xa.tmask = tmask;
+  xa.dst = c.H();
+  xa.tw = P.d_tw;
+  hipError_t e = launch_xfft_fwd(xa, P.lds_x, c.s);
+  if (e != hipSuccess) return e;
+  e = launch_rows_adj(P.R, rows_args(c, P.d_ra, P.n_ra), P.lds_ra, c.s);
+  if (e != hipSuccess) return e;
+  XinvArgs ia{};
+  ia.gd = P.d_gd;
+  ia.items = P.d_xm;
+  ia.nitems = P.n_xm;
+  ia.is_model = 1;
+  ia.src = c.X();
+  ia.out = m_out;
+  ia.wmul = wmul;
+  ia.tw = P.d_tw;
+  return launch_xfft_inv(ia, P.lds_x, c.s);
+}
+
+int check_ws(const PlanImpl& P, int op, int q, void* ws, size_t ws_bytes, Ctx* c, void* stream) {
+  c->P = &P;
+  c->L = P.layout(op, q);
+  if (!ws || ((uintptr_t)ws & 255u) != 0) return fail(ASHRT_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (ws_bytes < c->L.total)
+    return fail(ASHRT_E_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                       std::to_string(c->L.total));
+  c->ws = (unsigned char*)ws;
+  c->s = (hipStream_t)stream;
+  return ASHRT_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess) ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int forward_impl(const PlanImpl& P, const float* m, float* d, const uint8_t* mask, void* ws, size_t wsb,
+                 void* stream) {
+  if (!m || !d) return fail(ASHRT_E_INVALID_ARG, "m and d must be non-NULL");
+  Ctx c;
+  int st = check_ws(P, ASHRT_OP_FORWARD, 2, ws, wsb, &c, stream);
+  if (st) return st;
+  DeviceGuard dg(P.device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
+  HIP_TRY(run_forward(c, m, nullptr, d, nullptr, nullptr, nullptr, mask));
+  return ASHRT_OK;
+}
+
+int adjoint_impl(const PlanImpl& P, const float* d, float* m, const uint8_t* mask, void* ws, size_t wsb,
+                 void* stream) {
+  if (!m || !d) return fail(ASHRT_E_INVALID_ARG, "m and d must be non-NULL");
+  Ctx c;
+  int st = check_ws(P, ASHRT_OP_ADJOINT, 2, ws, wsb, &c, stream);
+  if (st) return st;
+  DeviceGuard dg(P.device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
+  HIP_TRY(run_adjoint(c, d, nullptr, mask, m, nullptr));
+  return ASHRT_OK;
+}
+
+// ------------------------------------------------------------ IRLS-CG driver
+struct Solver {
+  const Ctx& c;
+  const PlanImpl& P;
+  const irls_params& prm;
+  float* r;
+  float* s;
+  float* q;
+  float* Wr;
+  float* pdir;
+  float* g;
+  float* u;
+  float* Wminv;
+  double* part;
+  double* sc;
+  SelState* sel;
+  unsigned* hist;
+  RepDev* rep;
+
+  EwArgs ew(int op, bool model) const {
+    EwArgs a{};
+    a.gd = P.d_gd;
+    a.items = model ? P.d_vm : P.d_vd;
+    a.nitems = model ? P.n_vm : P.n_vd;
+    a.op = op;
+    a.sc = sc;
+    a.sign = 1.f;
+    return a;
+  }
+  hipError_t reduce(int op, bool model, const float* x, const uint8_t* tmask, int dst0, int dst1, bool is_max,
+                    RepDev* rp, int outer) const {
+    RedArgs a{};
+    a.gd = P.d_gd;
+    a.items = model ? P.d_vm : P.d_vd;
+    a.nitems = model ? P.n_vm : P.n_vd;
+    a.op = op;
+    a.is_model = model;
+    a.x = x;
+    a.tmask = tmask;
+    a.sc = sc;
+    a.p = prm.p;
+    a.part = part;
+    hipError_t e = launch_reduce_part(a, c.s);
+    if (e != hipSuccess) return e;
+    FinArgs f{};
+    f.gd = P.d_gd;
+    f.ngather = P.ngather;
+    f.is_model = model;
+    f.is_max = is_max;
+    f.part = part;
+    f.sc = sc;
+    f.dst0 = dst0;
+    f.dst1 = dst1;
+    f.rep = rp;
+    f.outer = outer;
+    return launch_reduce_fin(f, c.s);
+  }
+  hipError_t scalar(int step, int outer) const {
+    ScalArgs a{};
+    a.ngather = P.ngather;
+    a.step = step;
+    a.sc = sc;
+    a.rep = rep;
+    a.outer = outer;
+    a.b_r = prm.b_r;
+    a.b_m = prm.b_m;
+    a.floor_rel = prm.eps_floor_rel;
+    a.freeze = prm.freeze_eps;
+    return launch_scalar(a, c.s);
+  }
+  hipError_t median(const float* x, const uint8_t* tmask, int stage, int dst) const {
+    SelArgs a{};
+    a.gd = P.d_gd;
+    a.items = P.d_vd;
+    a.nitems = P.n_vd;
+    a.ngather = P.ngather;
+    a.x = x;
+    a.tmask = tmask;
+    a.sc = sc;
+    a.st = sel;
+    a.hist = hist;
+    a.stage = stage;
+    return launch_select_median(a, sc, dst, c.s);
+  }
+};
+
+#define E_TRY(expr)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(ASHRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const uint8_t* mask, float* m,
+                const float* w0, float* d_rec, irls_report* reps, void* ws, size_t wsb, void* stream,
+                bool batched) {
+  if (!d || !m) return fail(ASHRT_E_INVALID_ARG, "d and m must be non-NULL");
+  int st = irls_params_validate(prm);
+  if (st) return st;
+  if (batched && prm->tol > 0.0)
+    return fail(ASHRT_E_INVALID_ARG, "batched solves run fixed iteration counts (tol must be 0)");
+  Ctx c;
+  st = check_ws(P, ASHRT_OP_INVERT, prm->q, ws, wsb, &c, stream);
+  if (st) return st;
+  DeviceGuard dg(P.device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
+  const WsLayout& L = c.L;
+  unsigned char* W = c.ws;
+  Solver S{c, P, *prm,
+           (float*)(W + L.r), (float*)(W + L.s), (float*)(W + L.q), (float*)(W + L.Wr),
+           (float*)(W + L.pdir), (float*)(W + L.g),
+           prm->q == 1 ? (float*)(W + L.u) : m,
+           prm->q == 1 ? (float*)(W + L.Wminv) : nullptr,
+           (double*)(W + L.part), (double*)(W + L.sc), (SelState*)(W + L.sel), (unsigned*)(W + L.hist),
+           (RepDev*)(W + L.rep)};
+  const hipStream_t s = c.s;
+  const bool q1 = prm->q == 1, p1 = prm->p == 1;
+
+  // clear scalars, selection histograms and the report
+  E_TRY(launch_zero_words(S.sc, (long long)P.ngather * kNScal * 2, s));
+  E_TRY(launch_zero_words(S.hist, (long long)P.ngather * 2 * kSelBins, s));
+  E_TRY(launch_zero_words(S.rep, (long long)P.ngather * sizeof(RepDev) / 4, s));
+  E_TRY(launch_count_live(P.d_gd, P.ngather, mask, S.sc, s));
+  E_TRY(S.reduce(RED_ABSMAX_LIVE, false, d, mask, SC_DMAX, -1, true, nullptr, 0));
+  // r = S (d - L m)
+  E_TRY(run_forward(c, m, nullptr, S.r, d, nullptr, nullptr, mask));
+
+  std::vector<RepDev> host_rep;
+  int outer_done = 0;
+  for (int k = 0; k < prm->n_outer; ++k) {
+    // weights of this outer iteration
+    if (k == 0) {
+      EwArgs a = S.ew(EW_WR_INIT, false);
+      a.y = S.Wr;
+      a.x = w0;
+      a.tmask = mask;
+      E_TRY(launch_elementwise(a, s));
+      if (q1) {
+        EwArgs f = S.ew(EW_FILL, true);
+        f.y = S.Wminv;
+        f.value = 1.0f;
+        E_TRY(launch_elementwise(f, s));
+        EwArgs cp = S.ew(EW_COPY, true);
+        cp.y = S.u;
+        cp.x = m;
+        E_TRY(launch_elementwise(cp, s));
+      }
+    } else {
+      EwArgs a = S.ew(p1 ? EW_WR_UPDATE : EW_WR_MASK, false);
+      a.y = S.Wr;
+      a.x = S.r;
+      a.coef = SC_EPS_R;
+      a.tmask = mask;
+      E_TRY(launch_elementwise(a, s));
+      if (q1) {
+        E_TRY(S.reduce(RED_ABSMAX, true, m, nullptr, SC_MMAX, -1, true, nullptr, 0));
+        E_TRY(S.scalar(ST_EPS_M, k));
+        EwArgs w = S.ew(EW_WM_UPDATE, true);
+        w.y = S.Wminv;
+        w.x = m;
+        w.z_out = S.u;
+        w.coef = SC_EPS_M;
+        E_TRY(launch_elementwise(w, s));
+      }
+    }
+    // CGLS on A = W_r S L W_m^-1 from u = W_m m:  s = W_r r ; g = A' s
+    {
+      EwArgs a = S.ew(EW_MUL, false);
+      a.y = S.s;
+      a.x = S.Wr;
+      a.z = S.r;
+      E_TRY(launch_elementwise(a, s));
+    }
+    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv));
+    E_TRY(S.reduce(RED_SUMSQ, true, S.g, nullptr, SC_GAMMA_NEW, -1, false, nullptr, 0));
+    E_TRY(S.scalar(ST_CG_RESET, k));
+    {
+      EwArgs a = S.ew(EW_COPY, true);
+      a.y = S.pdir;
+      a.x = S.g;
+      E_TRY(launch_elementwise(a, s));
+    }
+    for (int i = 0; i < prm->n_inner; ++i) {
+      E_TRY(run_forward(c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask));
+      E_TRY(S.reduce(RED_SUMSQ, false, S.q, nullptr, SC_DELTA, -1, false, nullptr, 0));
+      E_TRY(S.scalar(ST_CG_ALPHA, k));
+      EwArgs a = S.ew(EW_AXPY, true);
+      a.y = S.u;
+      a.x = S.pdir;
+      a.coef = SC_ALPHA;
+      a.sign = 1.f;
+      E_TRY(launch_elementwise(a, s));
+      EwArgs b = S.ew(EW_AXPY, false);
+      b.y = S.s;
+      b.x = S.q;
+      b.coef = SC_ALPHA;
+      b.sign = -1.f;
+      E_TRY(launch_elementwise(b, s));
+      E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv));
+      E_TRY(S.reduce(RED_SUMSQ, true, S.g, nullptr, SC_GAMMA_NEW, -1, false, nullptr, 0));
+      E_TRY(S.scalar(ST_CG_BETA, k));
+      EwArgs pb = S.ew(EW_XPBY, true);
+      pb.y = S.pdir;
+      pb.x = S.g;
+      pb.coef = SC_BETA;
+      E_TRY(launch_elementwise(pb, s));
+    }
+    E_TRY(S.scalar(ST_REPORT_INNER, k));
+    if (q1) {
+      EwArgs a = S.ew(EW_MUL, true);
+      a.y = m;
+      a.x = S.Wminv;
+      a.z = S.u;
+      E_TRY(launch_elementwise(a, s));
+    }
+    // residual, separated gather, clip and misfit
+    E_TRY(run_forward(c, m, nullptr, S.r, d, nullptr, d_rec, mask));
+    if (p1) {
+      E_TRY(S.median(S.r, mask, 0, SC_MED));
+      E_TRY(S.median(S.r, mask, 1, SC_MAD));
+      E_TRY(S.scalar(ST_EPS_R, k));
+    }
+    E_TRY(S.reduce(RED_MISFIT, false, S.r, mask, SC_MISFIT, SC_HUBER, false, S.rep, k));
+    outer_done = k + 1;
+    if (prm->tol > 0.0 && k >= 1) {
+      host_rep.resize(P.ngather);
+      E_TRY(hipMemcpyAsync(host_rep.data(), S.rep, sizeof(RepDev) * P.ngather, hipMemcpyDeviceToHost, s));
+      E_TRY(hipStreamSynchronize(s));
+      const double a = host_rep[0].misfit[k - 1], b = host_rep[0].misfit[k];
+      if (a > 0.0 && std::fabs(b - a) / a < prm->tol) break;
+    }
+  }
+
+  if (reps || prm->tol > 0.0) {
+    host_rep.resize(P.ngather);
+    std::vector<double> hsc((size_t)P.ngather * kNScal);
+    E_TRY(hipMemcpyAsync(host_rep.data(), S.rep, sizeof(RepDev) * P.ngather, hipMemcpyDeviceToHost, s));
+    E_TRY(hipMemcpyAsync(hsc.data(), S.sc, hsc.size() * 8, hipMemcpyDeviceToHost, s));
+    E_TRY(hipStreamSynchronize(s));
+    bool nonfinite = false;
+    for (int gi = 0; gi < P.ngather; ++gi) {
+      const bool bad = hsc[(size_t)gi * kNScal + SC_NONFINITE] != 0.0;
+      nonfinite |= bad;
+      if (reps) {
+        irls_report& R = reps[gi];
+        std::memset(&R, 0, sizeof(R));
+        R.status = bad ? ASHRT_E_NONFINITE : ASHRT_OK;
+        R.outer_done = outer_done;
+        for (int k = 0; k < outer_done; ++k) {
+          R.inner[k] = (int32_t)host_rep[gi].inner[k];
+          R.misfit[k] = host_rep[gi].misfit[k];
+          R.huber[k] = host_rep[gi].huber[k];
+          R.eps_r[k] = host_rep[gi].eps_r[k];
+          R.eps_m[k] = host_rep[gi].eps_m[k];
+        }
+      }
+    }
+    if (nonfinite) return fail(ASHRT_E_NONFINITE, "the solve produced a non-finite misfit");
+  }
+  return ASHRT_OK;
+}
+
+}  // namespace
+
+extern "C" int ashrt_forward(const ashrt_plan* plan, const float* m, float* d, const uint8_t* mask, void* ws,
+                             size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return forward_impl(plan->impl, m, d, mask, ws, wsb, stream);
+}
+
+extern "C" int ashrt_adjoint(const ashrt_plan* plan, const float* d, float* m, const uint8_t* mask, void* ws,
+                             size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return adjoint_impl(plan->impl, d, m, mask, ws, wsb, stream);
+}
+
+extern "C" int ashrt_forward_batched(const ashrt_batch_plan* plan, const float* m, float* d,
+                                     const uint8_t* mask, void* ws, size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return forward_impl(plan->impl, m, d, mask, ws, wsb, stream);
+}
+
+extern "C" int ashrt_adjoint_batched(const ashrt_batch_plan* plan, const float* d, float* m,
+                                     const uint8_t* mask, void* ws, size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return adjoint_impl(plan->impl, d, m, mask, ws, wsb, stream);
+}
+
+extern "C" int robust_invert(const ashrt_plan* plan, const irls_params* prm, const float* d,
+                             const uint8_t* mask, float* m, const float* w0, float* d_rec, irls_report* rep,
+                             void* ws, size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return invert_impl(plan->impl, prm, d, mask, m, w0, d_rec, rep, ws, wsb, stream, false);
+}
+
+extern "C" int robust_invert_batched(const ashrt_batch_plan* plan, const irls_params* prm, const float* d,
+                                     const uint8_t* mask, float* m, const float* w0, float* d_rec,
+                                     irls_report* reps, void* ws, size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return invert_impl(plan->impl, prm, d, mask, m, w0, d_rec, reps, ws, wsb, stream, true);
+}

@@ -1,0 +1,90 @@
+// Internal types shared by the host runtime and the HIP kernels of libashrt.
+//
+// Every pipeline stage is one launch over a flattened work list, so the same
+// kernels serve one gather and a batch of gathers of uneven size: a work item
+// names its gather and the tile / row / chunk it covers, and the gather's
+// geometry and buffer offsets come from a small device table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ashrt {
+
+constexpr int kThreads = 256;          // threads per workgroup of every kernel
+constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
+constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
+constexpr int kXfftMaxTotal = 8192;    // complex points of one batched x-FFT tile
+constexpr int kMaxSlots = (kRowMaxN / 2 + kThreads - 1) / kThreads;  // per-thread bins
+constexpr long long kVecChunk = 65536; // elements per vector-kernel work item
+constexpr int kSelBins = 2048;         // radix-select histogram bins (11 bits)
+
+// One gather's geometry and its offsets into packed buffers.
+struct GatherDev {
+  int nt, nx, ntp, nxp;
+  int nrows;        // nxp / 2: wavenumber rows (row 0 packs kx = 0 and kx = Nyquist)
+  int jlo, jhi;     // mapped data band, inclusive
+  int kmax;         // highest model bin the map reads or writes: min(ntp/2-1, jhi+R)
+  int npanel;
+  int panel_off;    // first panel in the panel table
+  int tw_t_off;     // float2 offset of the ntp twiddles in the twiddle pool
+  int tw_x_off;     // float2 offset of the nxp twiddles
+  int wav_off;      // float offset of the W_j table, -1 = none
+  int tileT;        // time columns per x-FFT tile (even)
+  int ntiles;       // ceil(nt / tileT)
+  int nchunk;       // panel chunks of the forward row pass
+  int mit_lo, mit_hi;   // model-vector work items of this gather
+  int dit_lo, dit_hi;   // data-vector work items of this gather
+  int pad_;
+  long long d_off;      // float offset of the gather in packed data arrays
+  long long m_off;      // float offset in packed model arrays
+  long long mask_off;   // byte offset in packed trace masks
+  long long X_off;      // float2 offset of the model-side x-spectra [P][nrows][nt]
+  long long H_off;      // float2 offset of the data-side x-spectrum [nrows][nt]
+  long long Dp_off;     // float2 offset of forward partials [nchunk][nrows][2][nband]
+};
+
+// One model panel: velocity as the squared bin scale, asymptote shift, scale.
+struct PanelDev {
+  double c2;     // (v * ntp * dt / (nxp * dx))^2, so a^2 = c2 * l'^2
+  float scale;   // s_p
+  int n0;        // asymptote shift in samples
+};
+
+// Work item: gather g plus up to three stage-specific indices.
+struct WorkItem {
+  int g, a, b, c;
+};
+
+// Vector work item for model/data-sized element-wise kernels and reductions.
+struct VecItem {
+  int g;
+  int pad_;
+  long long start;  // absolute element offset in the packed array
+  long long len;
+};
+
+// Device-side solver scalars, one block of kNScal doubles per gather.
+enum ScalIdx {
+  SC_GAMMA = 0, SC_GAMMA_NEW, SC_DELTA, SC_ALPHA, SC_BETA, SC_DONE, SC_NINNER,
+  SC_DMAX, SC_MMAX, SC_EPS_R, SC_EPS_M, SC_EPS_FROZEN, SC_FROZEN_SET, SC_MED, SC_MAD,
+  SC_NLIVE, SC_MISFIT, SC_HUBER, SC_NONFINITE,
+  kNScal = 24
+};
+
+// Radix-select state per gather: two order statistics (the two middle ranks).
+struct SelState {
+  unsigned prefix[2];
+  unsigned kk[2];
+};
+
+// Device-side report accumulated per gather (copied to irls_report on the host).
+struct RepDev {
+  double misfit[64];
+  double huber[64];
+  double eps_r[64];
+  double eps_m[64];
+  double inner[64];
+};
+
+}  // namespace ashrt

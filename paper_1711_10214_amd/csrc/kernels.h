@@ -1,0 +1,153 @@
+// Kernel argument blocks and launchers of libashrt (shared by the HIP
+// kernel sources and the host runtime).
+#pragma once
+
+#include "ashrt_internal.h"
+
+namespace ashrt {
+
+struct XfwdArgs {
+  const GatherDev* gd;
+  const WorkItem* items;  // (g, panel, tile)
+  int nitems;
+  int is_model;           // 1: model panels -> X ; 0: data -> H
+  const float* src;
+  const float* mul;       // optional element-wise factor, same layout as src
+  const uint8_t* tmask;   // optional trace mask (data only)
+  float2* dst;
+  const float2* tw;
+};
+
+struct XinvArgs {
+  const GatherDev* gd;
+  const WorkItem* items;  // (g, panel, tile)
+  int nitems;
+  int is_model;           // 1: G_p (X region) -> model ; 0: H -> data
+  const float2* src;
+  float* out;             // result (after the epilogue)
+  const float* sub;       // data: out = sub - y (residual) when set
+  const float* wmul;      // out *= wmul (element-wise) when set
+  float* raw_out;         // data: y before the epilogue when set
+  const uint8_t* tmask;   // data: out *= mask
+  const float2* tw;
+};
+
+struct RowsArgs {
+  const GatherDev* gd;
+  const WorkItem* items;  // (g, row, chunk)
+  int nitems;
+  const PanelDev* panels;
+  const float2* tw;
+  const float* wav;
+  float2* X;              // model-side x-spectra / adjoint output G
+  float2* H;              // data-side x-spectrum
+  float2* Dp;             // forward partials
+};
+
+enum RedOp { RED_SUMSQ = 0, RED_ABSMAX_LIVE = 1, RED_ABSMAX = 2, RED_MISFIT = 3 };
+
+struct RedArgs {
+  const GatherDev* gd;
+  const VecItem* items;
+  int nitems;
+  int op;
+  int is_model;
+  const float* x;
+  const uint8_t* tmask;   // data ops: skip dead traces
+  const double* sc;       // per-gather scalars (RED_MISFIT reads eps_r)
+  int p;                  // misfit exponent
+  double* part;           // [nitems][2]
+};
+
+struct FinArgs {
+  const GatherDev* gd;
+  int ngather;
+  int is_model;
+  int is_max;
+  const double* part;
+  double* sc;
+  int dst0, dst1;
+  RepDev* rep;       // optional: also store into the report at outer index `outer`
+  int outer;
+};
+
+enum EwOp {
+  EW_AXPY = 0,        // y += sign * sc[g][coef] * x
+  EW_XPBY = 1,        // y = x + sc[g][coef] * y
+  EW_MUL = 2,         // y = x * z
+  EW_COPY = 3,        // y = x
+  EW_FILL = 4,        // y = value
+  EW_WR_INIT = 5,     // y = live ? (x ? x : 1) : 0           (x = w0 or null)
+  EW_WR_UPDATE = 6,   // y = live ? (eps > 0 ? max(|x|, eps)^-1/2 : 1) : 0   (p = 1)
+  EW_WM_UPDATE = 7,   // y = max(|x|, eps_m)^1/2 (or 1), z_out = x / y        (q = 1)
+  EW_WR_MASK = 8      // y = live ? 1 : 0                     (p = 2)
+};
+
+struct EwArgs {
+  const GatherDev* gd;
+  const VecItem* items;
+  int nitems;
+  int op;
+  float* y;
+  const float* x;
+  const float* z;
+  float* z_out;
+  const double* sc;
+  int coef;
+  float sign;
+  float value;
+  const uint8_t* tmask;
+};
+
+enum ScalStep {
+  ST_CG_RESET = 0,     // done = 0, ninner = 0, gamma = gamma_new
+  ST_CG_ALPHA = 1,     // alpha = gamma/delta, or stop on an exact zero
+  ST_CG_BETA = 2,      // beta = gamma_new/gamma; gamma = gamma_new
+  ST_EPS_M = 3,        // eps_m = b_m * mmax / 100
+  ST_EPS_R = 4,        // eps_r = max(b_r * MAD / 0.6745, floor * dmax) (or frozen)
+  ST_REPORT_INNER = 5  // report.inner[outer] = ninner
+};
+
+struct ScalArgs {
+  int ngather;
+  int step;
+  double* sc;
+  RepDev* rep;
+  int outer;
+  double b_r, b_m, floor_rel;
+  int freeze;
+};
+
+struct SelArgs {
+  const GatherDev* gd;
+  const VecItem* items;
+  int nitems;
+  int ngather;
+  const float* x;
+  const uint8_t* tmask;
+  const double* sc;        // SC_MED for stage 1
+  SelState* st;
+  unsigned* hist;          // [ngather][2][kSelBins]
+  int stage;               // 0: r ; 1: |r - med|
+  int shift, width;        // digit = (key >> shift) & ((1 << width) - 1)
+};
+
+// operator kernels
+hipError_t launch_xfft_fwd(const XfwdArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_xfft_inv(const XinvArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows_fwd(int R, const RowsArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows_fwd_fin(const RowsArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows_adj(int R, const RowsArgs& a, size_t lds, hipStream_t s);
+hipError_t op_kernels_set_lds(size_t xfft, size_t rows_fwd, size_t rows_adj);
+
+// solver kernels
+hipError_t launch_reduce_part(const RedArgs& a, hipStream_t s);
+hipError_t launch_reduce_fin(const FinArgs& a, hipStream_t s);
+hipError_t launch_elementwise(const EwArgs& a, hipStream_t s);
+hipError_t launch_scalar(const ScalArgs& a, hipStream_t s);
+hipError_t launch_zero_words(void* p, long long n, hipStream_t s);
+hipError_t launch_count_live(const GatherDev* gd, int ngather, const uint8_t* tmask, double* sc,
+                             hipStream_t s);
+hipError_t launch_select_median(SelArgs a, double* sc, int dst, hipStream_t s);
+
+}  // namespace ashrt

@@ -1,0 +1,415 @@
+// HIP kernels of the robust inversion (thesis Chapter 4, "Robust Radon
+// transform"): CGLS vector updates in FP32 with FP64 inner products and step
+// scalars kept on the device, the IRLS residual and model weights, and the
+// median absolute deviation by radix selection on float bit patterns.
+//
+// All kernels take per-gather work lists so one launch serves a whole batch.
+// Reductions are deterministic: each work item writes one partial, and the
+// partials of a gather are summed in a fixed tree order.
+#include "kernels.h"
+
+namespace ashrt {
+
+// ------------------------------------------------------------ block reductions
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kThreads / 64; ++i) r = fmax(r, sh[i]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ partial reductions
+
+
+__global__ __launch_bounds__(kThreads) void k_reduce_part(RedArgs A) {
+  __shared__ double sh[kThreads / 64];
+  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    const VecItem w = A.items[it];
+    const GatherDev G = A.gd[w.g];
+    const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
+    double a = 0.0, b = 0.0;
+    const double eps = A.sc ? A.sc[w.g * kNScal + SC_EPS_R] : 0.0;
+    for (long long i = threadIdx.x; i < w.len; i += kThreads) {
+      const long long o = w.start + i;
+      const double v = (double)A.x[o];
+      if (A.op == RED_SUMSQ) {
+        a += v * v;
+      } else if (A.op == RED_ABSMAX) {
+        a = fmax(a, fabs(v));
+      } else {
+        bool live = true;
+        if (tm) {
+          const long long x = (o - G.d_off) / G.nt;
+          live = tm[x] != 0;
+        }
+        if (!live) continue;
+        if (A.op == RED_ABSMAX_LIVE) {
+          a = fmax(a, fabs(v));
+        } else {  // RED_MISFIT: sum |r|^p and the Huber (p = 1) or LS (p = 2) objective
+          const double av = fabs(v);
+          if (A.p == 1) {
+            a += av;
+            b += (eps > 0.0) ? ((av <= eps) ? av * av / (2.0 * eps) : av - 0.5 * eps) : av;
+          } else {
+            a += v * v;
+            b += 0.5 * v * v;
+          }
+        }
+      }
+    }
+    double ra, rb = 0.0;
+    if (A.op == RED_ABSMAX || A.op == RED_ABSMAX_LIVE) {
+      ra = block_max(a, sh);
+    } else {
+      ra = block_sum(a, sh);
+      if (A.op == RED_MISFIT) rb = block_sum(b, sh);
+    }
+    if (threadIdx.x == 0) {
+      A.part[2 * it] = ra;
+      A.part[2 * it + 1] = rb;
+    }
+  }
+}
+
+// One workgroup per gather: combine the partials of its items in a fixed order
+// and store into the scalar slots (dst0, dst1; -1 = skip).  is_max selects max.
+
+__global__ __launch_bounds__(kThreads) void k_reduce_fin(FinArgs A) {
+  __shared__ double sh[kThreads / 64];
+  const int g = blockIdx.x;
+  if (g >= A.ngather) return;
+  const GatherDev G = A.gd[g];
+  const int lo = A.is_model ? G.mit_lo : G.dit_lo;
+  const int hi = A.is_model ? G.mit_hi : G.dit_hi;
+  double a = 0.0, b = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += kThreads) {
+    if (A.is_max) {
+      a = fmax(a, A.part[2 * i]);
+    } else {
+      a += A.part[2 * i];
+      b += A.part[2 * i + 1];
+    }
+  }
+  double ra, rb = 0.0;
+  if (A.is_max) {
+    ra = block_max(a, sh);
+  } else {
+    ra = block_sum(a, sh);
+    rb = block_sum(b, sh);
+  }
+  if (threadIdx.x == 0) {
+    if (A.dst0 >= 0) A.sc[g * kNScal + A.dst0] = ra;
+    if (A.dst1 >= 0) A.sc[g * kNScal + A.dst1] = rb;
+    if (A.rep) {
+      A.rep[g].misfit[A.outer] = ra;
+      A.rep[g].huber[A.outer] = rb;
+      if (!isfinite(ra) || !isfinite(rb)) A.sc[g * kNScal + SC_NONFINITE] = 1.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------ element-wise
+
+
+__global__ __launch_bounds__(kThreads) void k_elementwise(EwArgs A) {
+  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    const VecItem w = A.items[it];
+    const GatherDev G = A.gd[w.g];
+    float c = 0.f;
+    if (A.op == EW_AXPY || A.op == EW_XPBY || A.op == EW_WR_UPDATE || A.op == EW_WM_UPDATE)
+      c = (float)A.sc[w.g * kNScal + A.coef];
+    const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
+    for (long long i = threadIdx.x; i < w.len; i += kThreads) {
+      const long long o = w.start + i;
+      switch (A.op) {
+        case EW_AXPY: A.y[o] = fmaf(A.sign * c, A.x[o], A.y[o]); break;
+        case EW_XPBY: A.y[o] = fmaf(c, A.y[o], A.x[o]); break;
+        case EW_MUL: A.y[o] = A.x[o] * A.z[o]; break;
+        case EW_COPY: A.y[o] = A.x[o]; break;
+        case EW_FILL: A.y[o] = A.value; break;
+        case EW_WR_INIT:
+        case EW_WR_UPDATE:
+        case EW_WR_MASK: {
+          const bool live = tm ? (tm[(o - G.d_off) / G.nt] != 0) : true;
+          float v = 0.f;
+          if (live) {
+            if (A.op == EW_WR_INIT) v = A.x ? A.x[o] : 1.0f;
+            else if (A.op == EW_WR_MASK) v = 1.0f;
+            else v = (c > 0.f) ? 1.0f / sqrtf(fmaxf(fabsf(A.x[o]), c)) : 1.0f;
+          }
+          A.y[o] = v;
+          break;
+        }
+        case EW_WM_UPDATE: {
+          const float wi = (c > 0.f) ? sqrtf(fmaxf(fabsf(A.x[o]), c)) : 1.0f;
+          A.y[o] = wi;
+          A.z_out[o] = A.x[o] / wi;
+          break;
+        }
+        default: break;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ per-gather scalar steps
+
+
+__global__ void k_scalar(ScalArgs A) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= A.ngather) return;
+  double* s = A.sc + g * kNScal;
+  switch (A.step) {
+    case ST_CG_RESET:
+      s[SC_DONE] = 0.0;
+      s[SC_NINNER] = 0.0;
+      s[SC_GAMMA] = s[SC_GAMMA_NEW];
+      break;
+    case ST_CG_ALPHA: {
+      const double gm = s[SC_GAMMA], dl = s[SC_DELTA];
+      if (s[SC_DONE] != 0.0 || gm == 0.0 || dl == 0.0 || !isfinite(gm) || !isfinite(dl)) {
+        s[SC_DONE] = 1.0;
+        s[SC_ALPHA] = 0.0;
+      } else {
+        s[SC_ALPHA] = gm / dl;
+        s[SC_NINNER] += 1.0;
+      }
+      break;
+    }
+    case ST_CG_BETA:
+      if (s[SC_DONE] != 0.0) {
+        s[SC_BETA] = 0.0;
+      } else {
+        s[SC_BETA] = s[SC_GAMMA_NEW] / s[SC_GAMMA];
+        s[SC_GAMMA] = s[SC_GAMMA_NEW];
+      }
+      break;
+    case ST_EPS_M:
+      s[SC_EPS_M] = A.b_m * s[SC_MMAX] / 100.0;
+      if (A.rep) A.rep[g].eps_m[A.outer] = s[SC_EPS_M];
+      break;
+    case ST_EPS_R: {
+      double e;
+      if (A.freeze && s[SC_FROZEN_SET] != 0.0) {
+        e = s[SC_EPS_FROZEN];
+      } else {
+        e = fmax(A.b_r * s[SC_MAD] / 0.6745, A.floor_rel * s[SC_DMAX]);
+        if (A.freeze) {
+          s[SC_EPS_FROZEN] = e;
+          s[SC_FROZEN_SET] = 1.0;
+        }
+      }
+      s[SC_EPS_R] = e;
+      if (A.rep) A.rep[g].eps_r[A.outer] = e;
+      break;
+    }
+    case ST_REPORT_INNER:
+      if (A.rep) A.rep[g].inner[A.outer] = s[SC_NINNER];
+      break;
+    default:
+      break;
+  }
+}
+
+// ------------------------------------------------------------ radix select
+//
+// Order statistics of the live residual samples by three histogram passes
+// over the float bit pattern mapped to an order-preserving unsigned key
+// (11, 11, 10 bits).  The two middle ranks floor((n-1)/2) and floor(n/2) are
+// selected together so the median of an even count is the mean of the two
+// middle values.  Stage 0 selects on r, stage 1 on |r - median(r)|.
+__device__ __forceinline__ unsigned float_key(float f) {
+  const unsigned b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(unsigned k) {
+  const unsigned b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(b);
+}
+
+
+__global__ __launch_bounds__(kThreads) void k_sel_hist(SelArgs A) {
+  __shared__ unsigned h[2][kSelBins];
+  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    for (int i = threadIdx.x; i < 2 * kSelBins; i += kThreads) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    const VecItem w = A.items[it];
+    const GatherDev G = A.gd[w.g];
+    const SelState S = A.st[w.g];
+    const unsigned hmask = (A.shift + A.width >= 32) ? 0u : (0xffffffffu << (A.shift + A.width));
+    const unsigned dmask = (1u << A.width) - 1u;
+    const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
+    const double med = A.stage ? A.sc[w.g * kNScal + SC_MED] : 0.0;
+    for (long long i = threadIdx.x; i < w.len; i += kThreads) {
+      const long long o = w.start + i;
+      if (tm && tm[(o - G.d_off) / G.nt] == 0) continue;
+      float v = A.x[o];
+      if (A.stage) v = (float)fabs((double)v - med);
+      const unsigned key = float_key(v);
+      const unsigned dg = (key >> A.shift) & dmask;
+      if ((key & hmask) == (S.prefix[0] & hmask)) atomicAdd(&h[0][dg], 1u);
+      if ((key & hmask) == (S.prefix[1] & hmask)) atomicAdd(&h[1][dg], 1u);
+    }
+    __syncthreads();
+    unsigned* gh = A.hist + (long long)w.g * 2 * kSelBins;
+    for (int i = threadIdx.x; i < 2 * kSelBins; i += kThreads) {
+      const unsigned c = (&h[0][0])[i];
+      if (c) atomicAdd(&gh[i], c);
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per gather: find the digit holding rank kk, fix it in the
+// prefix, subtract the counts below, and clear the histogram for the next pass.
+__global__ __launch_bounds__(kThreads) void k_sel_pick(SelArgs A) {
+  __shared__ unsigned cnt[kThreads];
+  const int g = blockIdx.x;
+  if (g >= A.ngather) return;
+  unsigned* gh = A.hist + (long long)g * 2 * kSelBins;
+  const int nb = 1 << A.width;
+  const int per = nb / kThreads;  // bins per thread (nb >= kThreads)
+  for (int s = 0; s < 2; ++s) {
+    unsigned* hh = gh + s * kSelBins;
+    const unsigned kk = A.st[g].kk[s];  // read before the scan's barriers; one thread rewrites it below
+    unsigned loc = 0;
+    for (int i = 0; i < per; ++i) loc += hh[threadIdx.x * per + i];
+    cnt[threadIdx.x] = loc;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele)
+    for (int off = 1; off < kThreads; off <<= 1) {
+      const unsigned v = (threadIdx.x >= (unsigned)off) ? cnt[threadIdx.x - off] : 0u;
+      __syncthreads();
+      cnt[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const unsigned before = (threadIdx.x == 0) ? 0u : cnt[threadIdx.x - 1];
+    if (kk >= before && kk < cnt[threadIdx.x]) {
+      unsigned run = before;
+      for (int i = 0; i < per; ++i) {
+        const unsigned c = hh[threadIdx.x * per + i];
+        if (kk < run + c) {
+          const unsigned dg = (unsigned)(threadIdx.x * per + i);
+          A.st[g].prefix[s] |= dg << A.shift;
+          A.st[g].kk[s] = kk - run;
+          break;
+        }
+        run += c;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSelBins; i += kThreads) hh[i] = 0u;
+    __syncthreads();
+  }
+}
+
+// Start a selection: ranks from the live count, empty prefixes.
+__global__ void k_sel_init(SelArgs A) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= A.ngather) return;
+  const double n = A.sc[g * kNScal + SC_NLIVE];
+  const unsigned nn = (unsigned)n;
+  A.st[g].prefix[0] = 0u;
+  A.st[g].prefix[1] = 0u;
+  A.st[g].kk[0] = nn ? (nn - 1u) / 2u : 0u;
+  A.st[g].kk[1] = nn ? nn / 2u : 0u;
+}
+
+// Finish: median = mean of the two selected values (in FP64).
+__global__ void k_sel_final(SelArgs A, double* sc, int dst) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= A.ngather) return;
+  const double v0 = (double)key_float(A.st[g].prefix[0]);
+  const double v1 = (double)key_float(A.st[g].prefix[1]);
+  sc[g * kNScal + dst] = (sc[g * kNScal + SC_NLIVE] > 0.0) ? 0.5 * (v0 + v1) : 0.0;
+}
+
+// Live sample count per gather: (# live traces) * nt.
+__global__ __launch_bounds__(kThreads) void k_count_live(const GatherDev* gd, int ngather,
+                                                         const uint8_t* tmask, double* sc) {
+  __shared__ double sh[kThreads / 64];
+  const int g = blockIdx.x;
+  if (g >= ngather) return;
+  const GatherDev G = gd[g];
+  double c = 0.0;
+  for (int x = threadIdx.x; x < G.nx; x += kThreads) c += (tmask ? (tmask[G.mask_off + x] != 0) : 1) ? 1.0 : 0.0;
+  const double r = block_sum(c, sh);
+  if (threadIdx.x == 0) sc[g * kNScal + SC_NLIVE] = r * (double)G.nt;
+}
+
+// Clear n 32-bit words (a fill kernel rather than a memset, so the call can
+// sit inside a captured graph).
+__global__ void k_zero_words(unsigned* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ------------------------------------------------------------ launchers
+static inline int grid_of(int n) { return n < 1 ? 1 : n; }
+
+hipError_t launch_reduce_part(const RedArgs& a, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_part, dim3(grid_of(a.nitems)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_fin(const FinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_fin, dim3(grid_of(a.ngather)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_elementwise(const EwArgs& a, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_elementwise, dim3(grid_of(a.nitems)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_scalar(const ScalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar, dim3((a.ngather + 63) / 64), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_zero_words(void* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(kThreads), 0, s, (unsigned*)p, n);
+  return hipGetLastError();
+}
+hipError_t launch_count_live(const GatherDev* gd, int ngather, const uint8_t* tmask, double* sc,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_count_live, dim3(grid_of(ngather)), dim3(kThreads), 0, s, gd, ngather, tmask, sc);
+  return hipGetLastError();
+}
+
+// Median of the live samples of x (stage 0) or of |x - median| (stage 1),
+// into sc[g][dst].  The histogram must be zero on entry and is left zero.
+hipError_t launch_select_median(SelArgs a, double* sc, int dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_sel_init, dim3((a.ngather + 63) / 64), dim3(64), 0, s, a);
+  const int shifts[3] = {21, 10, 0};
+  const int widths[3] = {11, 11, 10};
+  for (int pass = 0; pass < 3; ++pass) {
+    a.shift = shifts[pass];
+    a.width = widths[pass];
+    if (a.nitems > 0) hipLaunchKernelGGL(k_sel_hist, dim3(grid_of(a.nitems)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_sel_pick, dim3(grid_of(a.ngather)), dim3(kThreads), 0, s, a);
+  }
+  hipLaunchKernelGGL(k_sel_final, dim3((a.ngather + 63) / 64), dim3(64), 0, s, a, sc, dst);
+  return hipGetLastError();
+}
+
+}  // namespace ashrt

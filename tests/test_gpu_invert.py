@@ -1,0 +1,123 @@
+"""GPU parity of the robust IRLS-CG inversion against the FP64 oracle.
+
+Same seeded blended gather on both sides (FP32-rounded input).  Bar: relative
+L2 <= 1e-4 on the separated gather d_rec = L m after the whole solve, and the
+per-outer-iteration misfit / clip within 1e-4 relative.  Every call goes
+through the C ABI (robust_invert) via the ctypes binding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.irls import IrlsParams
+from synth import make_gather, workload
+from tests.gpu_common import f32, geom_kwargs, oracle_geometry, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    import paper_1711_10214_amd as A
+    assert torch.cuda.is_available()
+    return A
+
+
+def _solve_both(A, kw, d, prm: IrlsParams, mask=None, w0=None):
+    import torch
+    g = oracle_geometry(kw)
+    plan = A.Plan(**kw)
+    dt_ = torch.tensor(d, dtype=torch.float32, device="cuda")
+    mk = None if mask is None else torch.tensor(mask, device="cuda")
+    w0t = None if w0 is None else torch.tensor(w0, dtype=torch.float32, device="cuda")
+    P = A.Params(p=prm.p, q=prm.q, n_outer=prm.n_outer, n_inner=prm.n_inner, b_r=prm.b_r,
+                 b_m=prm.b_m, tol=prm.tol, eps_floor_rel=prm.eps_floor_rel, freeze_eps=prm.freeze_eps)
+    m_gpu, drec_gpu, rep = plan.robust_invert(dt_, P, mask=mk, w0=w0t)
+    m_ref, drec_ref, rep_ref = oracle.robust_invert(g, d, prm, mask=mask, w0=w0)
+    return m_gpu.cpu().numpy(), drec_gpu.cpu().numpy(), rep, m_ref, drec_ref, rep_ref
+
+
+def _cfg1(nt=None, nx=None):
+    w = workload("crg-256x64-nv8")
+    gth = make_gather(w)
+    kw = geom_kwargs(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
+    return w, gth, kw
+
+
+@pytest.mark.parametrize("pq", [(1, 2), (2, 2), (1, 1), (2, 1)])
+def test_small_crg_solve_matches_oracle(A, pq):
+    p, q = pq
+    w, gth, kw = _cfg1()
+    prm = IrlsParams(p=p, q=q, n_outer=w.n_outer, n_inner=w.n_inner)
+    print(f"[gpu] invert parity crg-256x64-nv8 p={p} q={q}", flush=True)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm)
+    e_d = rel_l2(d_g, d_r)
+    e_m = rel_l2(m_g, m_r)
+    print(f"  d_rec rel-L2 {e_d:.2e}  m rel-L2 {e_m:.2e}", flush=True)
+    print(f"  misfit gpu {rep['misfit']}\n  misfit ref {rep_r['misfit']}", flush=True)
+    assert rep["outer_done"] == rep_r["outer_done"]
+    assert rep["inner"] == rep_r["inner"]
+    assert e_d <= 1e-4
+    np.testing.assert_allclose(rep["misfit"], rep_r["misfit"], rtol=1e-4)
+    np.testing.assert_allclose(rep["eps_r"], rep_r["eps_r"], rtol=1e-4, atol=1e-12)
+    np.testing.assert_allclose(rep["huber"], rep_r["huber"], rtol=1e-4)
+    if q == 1:
+        np.testing.assert_allclose(rep["eps_m"][1:], rep_r["eps_m"], rtol=1e-4)
+
+
+def test_separation_quality_matches_oracle(A):
+    w, gth, kw = _cfg1()
+    prm = IrlsParams(p=1, q=2, n_outer=w.n_outer, n_inner=w.n_inner)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm)
+    q_gpu = oracle.q_db(gth.d_clean, d_g)
+    q_ref = oracle.q_db(gth.d_clean, d_r)
+    q_pd = oracle.q_db(gth.d_clean, gth.d_blend)
+    print(f"[gpu] Q_PD {q_pd:.3f} dB  Q_R gpu {q_gpu:.4f}  oracle {q_ref:.4f}", flush=True)
+    assert q_gpu >= q_ref - 0.05
+    assert q_gpu > q_pd
+
+
+def test_decimated_aashrt_interpolation(A):
+    """Masked (decimated) gather with asymptote-shifted panels, p = 2, q = 1."""
+    w = workload("aashrt-1024x256-nv24x16", nt=200, nx=48, vel=(1600.0, 1600.0, 2600.0, 2600.0),
+                 tau0=(0, 10, 0, 10), n_diffractors=4, n_events=(2, 2), tau_range=(0.1, 0.5))
+    gth = make_gather(w)
+    kw = geom_kwargs(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax)
+    prm = IrlsParams(p=2, q=1, n_outer=4, n_inner=8)
+    print("[gpu] invert parity aashrt decimated", flush=True)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm, mask=gth.mask)
+    e_d = rel_l2(d_g, d_r)
+    print(f"  d_rec rel-L2 {e_d:.2e}", flush=True)
+    assert e_d <= 1e-4
+    np.testing.assert_allclose(rep["misfit"], rep_r["misfit"], rtol=1e-4)
+
+
+def test_warm_start_weights_and_frozen_clip(A):
+    w, gth, kw = _cfg1()
+    rng = np.random.default_rng(9)
+    w0 = f32(rng.uniform(0.2, 1.0, gth.d_blend.shape))
+    prm = IrlsParams(p=1, q=2, n_outer=4, n_inner=6, freeze_eps=True)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm, w0=w0)
+    assert rel_l2(d_g, d_r) <= 1e-4
+    assert len(set(np.round(rep["eps_r"], 12))) == 1
+    h = rep["huber"]
+    assert all(b <= a * (1 + 1e-5) for a, b in zip(h, h[1:]))
+
+
+def test_tolerance_early_stop(A):
+    w, gth, kw = _cfg1()
+    prm = IrlsParams(p=1, q=2, n_outer=30, n_inner=10, tol=0.01)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm)
+    assert rep["outer_done"] == rep_r["outer_done"] < 30
+
+
+def test_zero_data_is_finite(A):
+    import torch
+    w, gth, kw = _cfg1()
+    plan = A.Plan(**kw)
+    d = torch.zeros((gth.nx, gth.nt), device="cuda")
+    m, drec, rep = plan.robust_invert(d, A.Params(n_outer=2, n_inner=3))
+    assert float(m.abs().max()) == 0.0
+    assert rep["inner"] == [0, 0]
+    assert all(np.isfinite(rep["misfit"]))

@@ -1,0 +1,121 @@
+"""GPU parity of the Stolt (A)ASHRT forward and adjoint against the FP64 oracle.
+
+Bar: relative L2 <= 1e-5 per application (FP32 FFTs and map, FP64 map
+coordinates).  The GPU dot-product test checks the exact-transpose pairing
+at FP32 level.  Every call goes through the C ABI via the ctypes binding.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_common import f32, geom_kwargs, oracle_geometry, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    import paper_1711_10214_amd as A
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return A
+
+
+def _run_pair(A, kw, seed, mask_frac=0.0):
+    import torch
+    rng = np.random.default_rng(seed)
+    g = oracle_geometry(kw)
+    m = f32(rng.standard_normal((g.npanel, g.nx, g.nt)))
+    d = f32(rng.standard_normal((g.nx, g.nt)))
+    mask = None
+    if mask_frac > 0:
+        mask = (rng.uniform(size=g.nx) >= mask_frac).astype(np.uint8)
+    plan = A.Plan(**kw)
+    assert (plan.info["ntp"], plan.info["nxp"]) == (g.ntp, g.nxp)
+    assert (plan.info["jlo"], plan.info["jhi"]) == oracle.band(g)
+    mt = torch.tensor(m, dtype=torch.float32, device="cuda")
+    dt_ = torch.tensor(d, dtype=torch.float32, device="cuda")
+    mk = None if mask is None else torch.tensor(mask, device="cuda")
+    d_gpu = plan.forward(mt, mask=mk).cpu().numpy()
+    m_gpu = plan.adjoint(dt_, mask=mk).cpu().numpy()
+    d_ref = oracle.forward(g, m, mask)
+    m_ref = oracle.adjoint(g, d, mask)
+    return g, m, d, d_gpu, m_gpu, d_ref, m_ref
+
+
+CASES = {
+    # name: (kwargs, mask fraction)
+    "crg-256x64-nv8": (geom_kwargs(256, 64, 0.004, 12.5, list(np.linspace(1500, 3000, 8)), fmax=100.0), 0.0),
+    "ragged-odd-nt": (geom_kwargs(203, 37, 0.004, 12.5, [1400.0, 2200.0, 3900.0], fmax=90.0), 0.0),
+    "radix3-both": (geom_kwargs(190, 90, 0.004, 12.5, [1600.0, 2500.0], ntp=384, nxp=192, fmax=120.0), 0.0),
+    "full-band-no-pad": (geom_kwargs(128, 32, 0.002, 10.0, [0.0, 1800.0, 5000.0], ntp=128, nxp=32), 0.0),
+    "aashrt-ramp-scale-mask": (geom_kwargs(256, 48, 0.004, 12.5, [1500.0, 1500.0, 2400.0, 2400.0],
+                                           tau0=[0, 7, 0, 23], scale=[1.0, 0.5, 2.0, 1.5],
+                                           fmin=5.0, fmax=80.0), 0.3),
+    "half-width-2": (geom_kwargs(160, 40, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0, half_width=2), 0.0),
+    "half-width-8": (geom_kwargs(160, 40, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0, half_width=8), 0.0),
+    "tiny": (geom_kwargs(2, 2, 0.004, 12.5, [2000.0], ntp=8, nxp=4), 0.0),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_adjoint_match_oracle(A, name):
+    kw, mf = CASES[name]
+    print(f"[gpu] operator parity case={name}", flush=True)
+    g, m, d, d_gpu, m_gpu, d_ref, m_ref = _run_pair(A, kw, seed=zlib.crc32(name.encode()) % 1000, mask_frac=mf)
+    assert np.all(np.isfinite(d_gpu)) and np.all(np.isfinite(m_gpu))
+    ef, ea = rel_l2(d_gpu, d_ref), rel_l2(m_gpu, m_ref)
+    print(f"  rel-L2 forward {ef:.2e} adjoint {ea:.2e}", flush=True)
+    assert ef <= TOL, ef
+    assert ea <= TOL, ea
+
+
+def test_wavelet_weight(A):
+    kw = geom_kwargs(200, 40, 0.004, 12.5, [1500.0, 2500.0], fmax=100.0)
+    H = oracle.fft_len(200) // 2 + 1
+    kw["wavelet"] = np.exp(-((np.arange(H) - 60.0) / 40.0) ** 2)
+    print("[gpu] operator parity case=wavelet", flush=True)
+    _, _, _, d_gpu, m_gpu, d_ref, m_ref = _run_pair(A, kw, seed=5)
+    assert rel_l2(d_gpu, d_ref) <= TOL
+    assert rel_l2(m_gpu, m_ref) <= TOL
+
+
+@pytest.mark.parametrize("name", ["crg-256x64-nv8", "aashrt-ramp-scale-mask", "radix3-both"])
+def test_dot_product_fp32(A, name):
+    kw, mf = CASES[name]
+    print(f"[gpu] dot test case={name}", flush=True)
+    g, m, d, d_gpu, m_gpu, _, _ = _run_pair(A, kw, seed=11, mask_frac=mf)
+    lhs = float(np.sum(d_gpu.astype(np.float64) * d))
+    rhs = float(np.sum(m * m_gpu.astype(np.float64)))
+    rel = abs(lhs - rhs) / (np.linalg.norm(d_gpu) * np.linalg.norm(d))
+    print(f"  dot rel {rel:.2e}", flush=True)
+    assert rel < 1e-6
+
+
+def test_production_size_sampled(A):
+    """Production geometry (1024 x 256, 32 velocities): full forward/adjoint
+    parity against the oracle (the oracle runs it in a few seconds)."""
+    kw = geom_kwargs(1024, 256, 0.004, 12.5, list(np.linspace(1400, 4000, 32)), fmax=100.0)
+    print("[gpu] operator parity case=crg-1024x256-nv32", flush=True)
+    _, _, _, d_gpu, m_gpu, d_ref, m_ref = _run_pair(A, kw, seed=2)
+    ef, ea = rel_l2(d_gpu, d_ref), rel_l2(m_gpu, m_ref)
+    print(f"  rel-L2 forward {ef:.2e} adjoint {ea:.2e}", flush=True)
+    assert ef <= TOL and ea <= TOL
+
+
+def test_linearity_and_zero(A):
+    import torch
+    kw = geom_kwargs(128, 32, 0.004, 12.5, [1500.0, 2500.0], fmax=100.0)
+    plan = A.Plan(**kw)
+    z = torch.zeros((2, 32, 128), device="cuda")
+    assert float(plan.forward(z).abs().max()) == 0.0
+    rng = np.random.default_rng(3)
+    a = torch.tensor(rng.standard_normal((2, 32, 128)), dtype=torch.float32, device="cuda")
+    b = torch.tensor(rng.standard_normal((2, 32, 128)), dtype=torch.float32, device="cuda")
+    lhs = plan.forward(a + 2 * b).cpu().numpy()
+    rhs = (plan.forward(a) + 2 * plan.forward(b)).cpu().numpy()
+    assert rel_l2(lhs, rhs) < 1e-6
