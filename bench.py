@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Benchmark of the robust Stolt-ASHRT separation on one MI355X.
+
+A step is one whole IRLS-CG solve (10 reweightings x 20 CG iterations, l1
+misfit, l2 model norm) of the production-size blended receiver gather
+(1024 samples x 256 traces, dt 4 ms, dx 12.5 m, 32 velocities over
+1400-4000 m/s), zero start, inputs resident in HBM.  ``value`` is gathers
+solved per second; a solve counts only if its separated-signal SNR Q_R is
+within 0.05 dB of the FP64 oracle's on the same gather and iteration counts
+(stored in tests/golden/oracle_separation.json by a script that calls only
+the oracle).
+
+Also reported: forward+adjoint operator pairs per second, a roofline entry
+for the dominant kernel (average launch time from HIP events recorded
+around that kernel's launches on its stream, during the timed steps), and
+the FP64 oracle timed on the host on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+
+def _geometry_numbers(plan, nx, nt, P, R):
+    """Algorithmic bytes and flops per launch of each kernel family."""
+    import numpy as np
+    info = plan.info
+    ntp, nxp, jlo, jhi, nchunk = info["ntp"], info["nxp"], info["jlo"], info["jhi"], info["nchunk"]
+    nrows = nxp // 2
+    nband = jhi - jlo + 1
+    f4, c8 = 4, 8
+    model_b = P * nx * nt * f4
+    data_b = nx * nt * f4
+    X_b = P * nrows * nt * c8
+    H_b = nrows * nt * c8
+    Dp_b = nchunk * nrows * 2 * nband * c8
+    fft_t = 5.0 * ntp * math.log2(ntp)          # one complex time FFT
+    fft_x = 5.0 * nxp * math.log2(nxp)          # one complex x FFT (two real columns)
+    # in-cone map outputs: for each panel, row and band bin with j >= a (up and lo rows)
+    vel = plan.vel
+    bin_ = ntp * plan.dt / (nxp * plan.dx)
+    j = np.arange(jlo, jhi + 1, dtype=np.float64)
+    l = np.arange(nrows, dtype=np.float64)
+    cone = 0
+    for v in vel:
+        a_up = v * bin_ * l
+        a_lo = v * bin_ * np.where(l == 0, nrows, l)
+        cone += int(np.sum(j[None, :] >= a_up[:, None])) + int(np.sum(j[None, :] >= a_lo[:, None]))
+    map_flops = cone * 2 * R * 4            # one complex x real multiply-add per tap
+    return {
+        "k_xfft_fwd(model)": (model_b + X_b, P * math.ceil(nt / 2) * fft_x),
+        "k_xfft_fwd(data)": (data_b + H_b, math.ceil(nt / 2) * fft_x),
+        "k_rows_fwd": (X_b + Dp_b, P * nrows * fft_t + map_flops),
+        "k_rows_fwd_fin": (Dp_b + H_b, nrows * fft_t),
+        "k_xfft_inv(data)": (H_b + data_b, math.ceil(nt / 2) * fft_x),
+        "k_rows_adj": (nchunk * H_b + X_b, (nchunk + P) * nrows * fft_t + map_flops),
+        "k_xfft_inv(model)": (X_b + model_b, P * math.ceil(nt / 2) * fft_x),
+    }
+
+
+def cpu_baseline(w, gth, budget_s=25.0):
+    """The FP64 oracle on the host: a short solve of the same gather, scaled
+    to a full solve by counting operator applications."""
+    import numpy as np
+    import oracle
+    from oracle.irls import IrlsParams
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    g = oracle.geometry(gth.nt, gth.nx, w.dt, w.dx, w.vel, tau0=w.tau0, fmax=w.fmax, R=w.half_width)
+    d = gth.d_blend.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    for p in range(g.npanel):
+        oracle.stolt_matrix(g, p)
+    t_setup = time.perf_counter() - t0
+    n_outer, n_inner = 1, 3
+    t1 = time.perf_counter()
+    oracle.robust_invert(g, d, IrlsParams(p=w.p, q=w.q, n_outer=n_outer, n_inner=n_inner))
+    t_sample = time.perf_counter() - t1
+    apps_sample = 1 + n_outer * (2 * n_inner + 2)
+    apps_full = 1 + w.n_outer * (2 * w.n_inner + 2)
+    t_full = t_setup + t_sample * apps_full / apps_sample
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    return {
+        "value": 1.0 / t_full, "unit": "gathers/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 numpy/scipy oracle, one thread: stolt-map setup {t_setup:.2f} s plus a "
+                   f"{n_outer}x{n_inner} IRLS-CG solve of the same gather ({apps_sample} operator "
+                   f"applications, {t_sample:.2f} s), scaled to the {w.n_outer}x{w.n_inner} solve "
+                   f"({apps_full} applications): {t_full:.1f} s per gather"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="crg-1024x256-nv32")
+    ap.add_argument("--pairs", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 512 MiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs one gather solve per GPU and has no "
+              "multi-GPU path (gathers are independent; see the sharding notes). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1711_10214_amd as A
+    from paper_1711_10214_amd import _lib as L
+    from synth import make_gather, workload
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    dev = torch.device("cuda", 0)
+    w = workload(args.workload)
+    gth = make_gather(w)
+    print(f"[bench] workload {w.name}: nt={gth.nt} nx={gth.nx} P={w.npanel} "
+          f"{w.n_outer}x{w.n_inner} p={w.p} q={w.q}", file=sys.stderr, flush=True)
+    plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
+                  half_width=w.half_width, device=0)
+    d = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
+    mask = None if w.decimate_frac == 0 else torch.tensor(gth.mask, device=dev)
+    prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
+    lib = L.lib()
+
+    def solve():
+        return plan.robust_invert(d, prm, mask=mask, want_report=False)
+
+    # warm-up, plus one fully profiled solve to find the dominant kernel
+    for _ in range(max(args.warmup, 1)):
+        solve()
+    torch.cuda.synchronize()
+    lib.ashrt_profile_enable((1 << L.K_COUNT) - 1)
+    solve()
+    torch.cuda.synchronize()
+    lib.ashrt_profile_enable(0)
+    per_kernel = {}
+    import ctypes as C
+    for k in range(L.K_COUNT):
+        tot, n = C.c_double(), C.c_int64()
+        L.check(lib.ashrt_profile_read(k, C.byref(tot), C.byref(n), 1), "ashrt_profile_read")
+        per_kernel[lib.ashrt_kernel_name(k).decode()] = {"ms_total_per_solve": tot.value, "launches": n.value,
+                                                        "kid": k}
+    op_kernels = [k for k in per_kernel if k.startswith(("k_xfft", "k_rows"))]
+    dom = max(op_kernels, key=lambda k: per_kernel[k]["ms_total_per_solve"])
+    dom_kid = per_kernel[dom]["kid"]
+    print(f"[bench] per-kernel ms per solve: " +
+          ", ".join(f"{k}={v['ms_total_per_solve']:.2f}" for k, v in per_kernel.items()),
+          file=sys.stderr, flush=True)
+
+    # timed region: K solves; events around the dominant kernel's launches only
+    lib.ashrt_profile_enable(1 << dom_kid)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    out = None
+    for _ in range(args.steps):
+        out = solve()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.ashrt_profile_enable(0)
+    tot, n = C.c_double(), C.c_int64()
+    L.check(lib.ashrt_profile_read(dom_kid, C.byref(tot), C.byref(n), 1), "ashrt_profile_read")
+    dom_avg_s = tot.value / max(n.value, 1) / 1e3
+    ms_per_step = wall / args.steps * 1e3
+    value = args.steps / wall
+
+    # fixed-SNR check against the oracle's separation on this gather
+    import oracle
+    m_out, drec, _ = out
+    q_r = oracle.q_db(gth.d_clean, drec.cpu().numpy())
+    q_pd = oracle.q_db(gth.d_clean, gth.d_blend)
+    snr = {"q_r_db": q_r, "q_pd_db": q_pd}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_separation.json")
+    if os.path.exists(gold):
+        ref = json.load(open(gold)).get(w.name)
+        if ref and ref["n_outer"] == w.n_outer and ref["n_inner"] == w.n_inner:
+            snr["oracle_q_r_db"] = ref["q_r_db"]
+            snr["reached"] = bool(q_r >= ref["q_r_db"] - 0.05)
+
+    # operator pairs per second
+    rng = np.random.default_rng(0)
+    mm = torch.tensor(rng.standard_normal((w.npanel, gth.nx, gth.nt)), dtype=torch.float32, device=dev)
+    dd = torch.empty((gth.nx, gth.nt), dtype=torch.float32, device=dev)
+    m2 = torch.empty_like(mm)
+    for _ in range(3):
+        plan.forward(mm, out=dd)
+        plan.adjoint(dd, out=m2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.pairs):
+        plan.forward(mm, out=dd)
+        plan.adjoint(dd, out=m2)
+    torch.cuda.synchronize()
+    pair_s = (time.perf_counter() - t0) / args.pairs
+
+    # roofline of the dominant kernel
+    nums = _geometry_numbers(plan, gth.nx, gth.nt, w.npanel, w.half_width)
+    bytes_, flops = nums[dom]
+    hbm_frac = (bytes_ / dom_avg_s / 1e9) / HBM_PEAK_GBS
+    alu_frac = (flops / dom_avg_s / 1e12) / FP32_VECTOR_PEAK_TFLOPS
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": bytes_ / dom_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops / dom_avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = dom_avg_s * 1e6
+    roof["launches_timed"] = n.value
+    roof["algorithmic_bytes_per_launch"] = bytes_
+    roof["algorithmic_flops_per_launch"] = flops
+    roof["hbm_frac"] = hbm_frac
+    roof["alu_frac"] = alu_frac
+    pair_bytes = sum(nums[k][0] for k in nums)
+    if args.copy_calibration:
+        x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        x.fill_(1.0)
+        y = x.clone()
+        torch.cuda.synchronize()
+        del x, y
+
+    rec = {
+        "metric": "robust ASHRT gathers solved/s to fixed SNR (IRLS-CG 10x20, l1 misfit); also fwd+adj pairs/s, HBM GB/s",
+        "value": value,
+        "unit": "gathers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nt": gth.nt, "nx": gth.nx, "ntp": plan.info["ntp"],
+                   "nxp": plan.info["nxp"], "npanel": w.npanel, "p": w.p, "q": w.q,
+                   "n_outer": w.n_outer, "n_inner": w.n_inner, "fmax_hz": w.fmax,
+                   "reductions": "f64", "seed": w.seed},
+        "pairs_per_s": 1.0 / pair_s,
+        "pair_ms": pair_s * 1e3,
+        "pair_algorithmic_gbs": pair_bytes / pair_s / 1e9,
+        "snr": snr,
+        "kernels_ms_per_solve": {k: round(v["ms_total_per_solve"], 4) for k, v in per_kernel.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host (bounded sample)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, gth)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,7 +85,7 @@ enum ashrt_op { ASHRT_OP_FORWARD = 0, ASHRT_OP_ADJOINT = 1, ASHRT_OP_INVERT = 2 
 /* Operator description (host memory; copied at plan creation). */
 typedef struct ashrt_desc {
   int32_t nt, nx;              /* samples per trace (>= 2), traces (>= 2)                          */
-  int32_t ntp, nxp;            /* FFT lengths; 0 = auto. Supported: 2^a or 3*2^a, ntp in [8, 8192]
+  int32_t ntp, nxp;            /* FFT lengths; 0 = auto. Supported: 2^a or 3*2^a, ntp in [8, 4096]
                                   with ntp >= nt, nxp in [4, 4096] with nxp >= nx                    */
   double dt, dx;               /* sample interval (s) and trace spacing (m), > 0                    */
   int32_t npanel;              /* P >= 1 model panels                                                */
@@ -171,7 +171,9 @@ int ashrt_adjoint(const ashrt_plan *plan, const float *d, float *m, const uint8_
  *   rep   host report or NULL.  When rep != NULL or tol > 0 the call waits on
  *         the stream (once per outer iteration with tol > 0, once at the end
  *         for the report); otherwise it is asynchronous.
- * Returns ASHRT_E_NONFINITE if the final misfit is not finite. */
+ * When the call waits (rep != NULL or tol > 0) it returns ASHRT_E_NONFINITE
+ * if a misfit came out NaN or Inf; asynchronous calls report that only
+ * through a later report. */
 int robust_invert(const ashrt_plan *plan, const irls_params *params, const float *d,
                   const uint8_t *trace_mask, float *m, const float *w0, float *d_rec,
                   irls_report *rep, void *ws, size_t ws_bytes, void *stream);
@@ -201,6 +203,31 @@ int robust_invert_batched(const ashrt_batch_plan *plan, const irls_params *param
                           const float *d_packed, const uint8_t *mask_packed, float *m_packed,
                           const float *w0_packed, float *drec_packed, irls_report *reps,
                           void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- profiling
+ * Optional HIP-event timing of individual kernel families, for measurement
+ * tools (not for production paths).  ashrt_profile_enable(mask) makes every
+ * later launch of a family whose bit (1u << ASHRT_K_*) is set record a
+ * start/end event pair on the launch stream (0 disables; pairs already
+ * recorded are kept).  ashrt_profile_read() waits for the recorded events of
+ * one family and returns the summed kernel time and launch count, optionally
+ * clearing them.  Process-wide; not thread-safe with concurrent solves. */
+enum ashrt_kernel_id {
+  ASHRT_K_XFFT_MODEL = 0,   /* x-axis real FFT of model panels (forward input)          */
+  ASHRT_K_XFFT_DATA = 1,    /* x-axis real FFT of the data (adjoint input)              */
+  ASHRT_K_ROWS_FWD = 2,     /* time FFT + Stolt map + panel sum per wavenumber row     */
+  ASHRT_K_ROWS_FIN = 3,     /* chunk sum + inverse time FFT per row (forward)          */
+  ASHRT_K_XINV_DATA = 4,    /* x-axis inverse real FFT to the data (+ epilogue)        */
+  ASHRT_K_ROWS_ADJ = 5,     /* time FFT + transposed Stolt map + inverse FFT per panel */
+  ASHRT_K_XINV_MODEL = 6,   /* x-axis inverse real FFT to the model panels             */
+  ASHRT_K_VECTOR = 7,       /* CG vector updates and weights                            */
+  ASHRT_K_REDUCE = 8,       /* FP64 reductions                                          */
+  ASHRT_K_SELECT = 9,       /* radix-select medians                                     */
+  ASHRT_K_COUNT = 10
+};
+int ashrt_profile_enable(uint32_t kernel_mask);
+int ashrt_profile_read(int kernel_id, double *total_ms, int64_t *launches, int reset);
+const char *ashrt_kernel_name(int kernel_id);
 
 /* Messages. */
 const char *ashrt_status_string(int status);

@@ -20,6 +20,11 @@ ASHRT_E_WORKSPACE = -7
 
 OP_FORWARD, OP_ADJOINT, OP_INVERT = 0, 1, 2
 
+# kernel families for ashrt_profile_enable / ashrt_profile_read
+K_XFFT_MODEL, K_XFFT_DATA, K_ROWS_FWD, K_ROWS_FIN, K_XINV_DATA, K_ROWS_ADJ, K_XINV_MODEL, \
+    K_VECTOR, K_REDUCE, K_SELECT = range(10)
+K_COUNT = 10
+
 
 class AshrtDesc(C.Structure):
     _fields_ = [
@@ -99,6 +104,9 @@ def lib():
         "ashrt_status_string": (C.c_char_p, [C.c_int]),
         "ashrt_last_error": (C.c_char_p, []),
         "ashrt_abi_version": (C.c_int, []),
+        "ashrt_profile_enable": (C.c_int, [C.c_uint32]),
+        "ashrt_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
+        "ashrt_kernel_name": (C.c_char_p, [C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -95,6 +95,8 @@ class Plan:
         L.check(L.lib().ashrt_plan_get_info(self._h, C.byref(info)), "ashrt_plan_get_info")
         self.info = {k: getattr(info, k) for k, _ in L.PlanInfo._fields_}
         self.nt, self.nx, self.npanel = int(nt), int(nx), len(self._desc.vel)
+        self.dt, self.dx = float(dt), float(dx)
+        self.vel = self._desc.vel
         self._ws = {}
 
     def __del__(self):

@@ -7,9 +7,12 @@
 // stream; solver step lengths stay on the device, so a solve needs no host
 // round trip unless a report or an early-stopping tolerance is requested.
 #include "ashrt.h"
+#include "fft_tpl.h"
 #include "kernels.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -55,6 +58,10 @@ static int auto_fft_len(int n) {
 }
 
 static long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
+
+// Dynamic LDS a kernel may request (gfx950: 160 KB per workgroup, minus a
+// margin for the kernels' static LDS).
+static constexpr size_t kMaxDynLds = 150 * 1024;
 
 // ------------------------------------------------------------ C ABI: defaults/validation
 extern "C" void ashrt_desc_default(ashrt_desc* d) {
@@ -177,7 +184,7 @@ struct GatherHost {
 struct WsLayout {
   size_t X, H, Dp;                                  // operator scratch
   size_t r, s, q, Wr, pdir, g, u, Wminv;            // solver vectors
-  size_t part, sc, sel, hist, rep;
+  size_t part, pdel, pgam, sc, sel, hist, rep;
   size_t total;
 };
 
@@ -193,9 +200,15 @@ struct PlanImpl {
   float* d_wav = nullptr;
   WorkItem *d_xm = nullptr, *d_xd = nullptr, *d_rf = nullptr, *d_rfin = nullptr, *d_ra = nullptr;
   int n_xm = 0, n_xd = 0, n_rf = 0, n_rfin = 0, n_ra = 0;
+  // Work-list segments: items [first, first + count) share one kernel
+  // instantiation (FFT length class `key`, 0 = generic) and LDS size.
+  struct Seg {
+    int key, first, count;
+    size_t lds;
+  };
+  std::vector<Seg> s_xm, s_xd, s_rf, s_rfin, s_ra;
   VecItem *d_vm = nullptr, *d_vd = nullptr;
   int n_vm = 0, n_vd = 0;
-  size_t lds_x = 0, lds_rf = 0, lds_ra = 0;
   long long tot_d = 0, tot_m = 0, tot_mask = 0, tot_X = 0, tot_H = 0, tot_Dp = 0;
 
   WsLayout layout(int op, int q) const {
@@ -221,6 +234,8 @@ struct PlanImpl {
         L.Wminv = take(tot_m * 4);
       }
       L.part = take((long long)2 * std::max(n_vm, n_vd) * 8);
+      L.pdel = take((long long)n_xd * 8);
+      L.pgam = take((long long)n_xm * 8);
       L.sc = take((long long)ngather * kNScal * 8);
       L.sel = take((long long)ngather * sizeof(SelState));
       L.hist = take((long long)ngather * 2 * kSelBins * 4);
@@ -331,26 +346,58 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   std::sort(lens.begin(), lens.end());
   lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
   std::vector<float2> tw;
-  std::vector<int> tw_off(lens.size());
+  std::vector<int> tw_off(lens.size()), twp_off(lens.size());
   for (size_t i = 0; i < lens.size(); ++i) {
-    tw_off[i] = (int)tw.size();
     const int N = lens[i];
+    tw_off[i] = (int)tw.size();
     for (int m = 0; m < N; ++m) {
       const double a = -2.0 * M_PI * (double)m / (double)N;
       tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
     }
+    // pass table of the compile-time FFT: per pass (radix R, span Ns) the
+    // twiddles exp(-2 pi i r jm / (Ns R)) laid out [r-1][jm]
+    twp_off[i] = (int)tw.size();
+    const int want = fft_tpl_twsize(N);
+    if (want > 0) {
+      std::vector<int> radices;
+      int M = N;
+      if (M % 3 == 0) {
+        radices.push_back(3);
+        M /= 3;
+      }
+      int L2 = 0;
+      while ((1 << L2) < M) ++L2;
+      for (int k = 0; k < L2 / 3; ++k) radices.push_back(8);
+      if (L2 % 3 == 1) radices.push_back(2);
+      if (L2 % 3 == 2) radices.push_back(4);
+      int Ns = 1;
+      const size_t start = tw.size();
+      for (int R : radices) {
+        for (int r = 1; r < R; ++r)
+          for (int jm = 0; jm < Ns; ++jm) {
+            const double a = -2.0 * M_PI * (double)r * (double)jm / ((double)Ns * (double)R);
+            tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+          }
+        Ns *= R;
+      }
+      if ((int)(tw.size() - start) != want || Ns != N)
+        return fail(ASHRT_E_UNSUPPORTED_SIZE, "internal: FFT pass table mismatch");
+    }
   }
-  auto tw_of = [&](int N) {
-    return tw_off[std::lower_bound(lens.begin(), lens.end(), N) - lens.begin()];
-  };
+  auto idx_of = [&](int N) { return std::lower_bound(lens.begin(), lens.end(), N) - lens.begin(); };
+  auto tw_of = [&](int N) { return tw_off[idx_of(N)]; };
+  auto twp_of = [&](int N) { return twp_off[idx_of(N)]; };
 
   std::vector<PanelDev> pan;
   std::vector<float> wav;
   std::vector<GatherDev> gd(ngather);
   std::vector<WorkItem> xm, xd, rf, rfin, ra;
   std::vector<VecItem> vm, vd;
+  std::vector<int> key_x(ngather), key_t(ngather);
   for (int gi = 0; gi < ngather; ++gi) {
     GatherHost& gh = P.g[gi];
+    key_x[gi] = x_size_is_tpl(gh.z.nxp) ? gh.z.nxp : 0;
+    key_t[gi] = rows_size_is_tpl(gh.z.ntp, gh.z.R) ? gh.z.ntp : 0;
     GatherDev& G = gd[gi];
     std::memset(&G, 0, sizeof(G));
     G.nt = gh.z.nt;
@@ -366,6 +413,8 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
     pan.insert(pan.end(), gh.panels.begin(), gh.panels.end());
     G.tw_t_off = tw_of(gh.z.ntp);
     G.tw_x_off = tw_of(gh.z.nxp);
+    G.twp_t_off = twp_of(gh.z.ntp);
+    G.twp_x_off = twp_of(gh.z.nxp);
     if (!gh.wav.empty()) {
       G.wav_off = (int)wav.size();
       wav.insert(wav.end(), gh.wav.begin(), gh.wav.end());
@@ -381,36 +430,68 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
     G.X_off = gh.X_off;
     G.H_off = gh.H_off;
     G.Dp_off = gh.Dp_off;
-    for (int p = 0; p < gh.z.P; ++p)
-      for (int t = 0; t < gh.ntiles; ++t) xm.push_back(WorkItem{gi, p, t, 0});
-    for (int t = 0; t < gh.ntiles; ++t) xd.push_back(WorkItem{gi, 0, t, 0});
-    for (int r = 0; r < gh.nrows; ++r) {
-      for (int c = 0; c < gh.nchunk; ++c) {
-        rf.push_back(WorkItem{gi, r, c, 0});
-        ra.push_back(WorkItem{gi, r, c, 0});
-      }
-      rfin.push_back(WorkItem{gi, r, 0, 0});
-    }
     G.mit_lo = (int)vm.size();
-    for (long long s = 0; s < gh.nm(); s += kVecChunk)
-      vm.push_back(VecItem{gi, 0, gh.m_off + s, std::min(kVecChunk, gh.nm() - s)});
+    for (long long s0 = 0; s0 < gh.nm(); s0 += kVecChunk)
+      vm.push_back(VecItem{gi, 0, gh.m_off + s0, std::min(kVecChunk, gh.nm() - s0)});
     G.mit_hi = (int)vm.size();
     G.dit_lo = (int)vd.size();
-    for (long long s = 0; s < gh.nd(); s += kVecChunk)
-      vd.push_back(VecItem{gi, 0, gh.d_off + s, std::min(kVecChunk, gh.nd() - s)});
+    for (long long s0 = 0; s0 < gh.nd(); s0 += kVecChunk)
+      vd.push_back(VecItem{gi, 0, gh.d_off + s0, std::min(kVecChunk, gh.nd() - s0)});
     G.dit_hi = (int)vd.size();
   }
+  // LDS bytes of each kernel family for one gather
+  auto lds_x_of = [&](const GatherHost& gh) {
+    return (size_t)gh.z.nxp * 8 + (size_t)(gh.tileT / 2) * (gh.z.nxp + 1) * 8;
+  };
+  auto nband_of = [](const GatherHost& gh) { return (size_t)(gh.z.jhi - gh.z.jlo + 1); };
+  auto lds_rf_of = [&](const GatherHost& gh) { return (size_t)gh.z.ntp * 16 + nband_of(gh) * 16; };
+  auto lds_fin_of = [&](const GatherHost& gh) { return (size_t)gh.z.ntp * 16; };
+  auto lds_ra_of = [&](const GatherHost& gh) {
+    const size_t nb = nband_of(gh);
+    return (size_t)gh.z.ntp * 24 + (nb + (nb & 1)) * 8 + nb * 20;
+  };
+  // work lists grouped by kernel instantiation; a gather's items stay contiguous
+  auto build_segments = [&](const std::vector<int>& keys, std::vector<PlanImpl::Seg>& segs,
+                            std::vector<WorkItem>& items, auto&& add_items, auto&& lds_of) {
+    std::map<int, std::vector<int>> by_key;
+    for (int gi = 0; gi < ngather; ++gi) by_key[keys[gi]].push_back(gi);
+    for (auto& kv : by_key) {
+      PlanImpl::Seg sg{kv.first, (int)items.size(), 0, 0};
+      for (int gi : kv.second) {
+        add_items(gi);
+        sg.lds = std::max(sg.lds, (size_t)lds_of(P.g[gi]));
+      }
+      sg.count = (int)items.size() - sg.first;
+      if (sg.count > 0) segs.push_back(sg);
+    }
+  };
+  build_segments(key_x, P.s_xm, xm, [&](int gi) {
+    gd[gi].xm_lo = (int)xm.size();
+    for (int p = 0; p < P.g[gi].z.P; ++p)
+      for (int t = 0; t < P.g[gi].ntiles; ++t) xm.push_back(WorkItem{gi, p, t, 0});
+    gd[gi].xm_hi = (int)xm.size();
+  }, lds_x_of);
+  build_segments(key_x, P.s_xd, xd, [&](int gi) {
+    gd[gi].xd_lo = (int)xd.size();
+    for (int t = 0; t < P.g[gi].ntiles; ++t) xd.push_back(WorkItem{gi, 0, t, 0});
+    gd[gi].xd_hi = (int)xd.size();
+  }, lds_x_of);
+  build_segments(key_t, P.s_rf, rf, [&](int gi) {
+    for (int r = 0; r < P.g[gi].nrows; ++r)
+      for (int c = 0; c < P.g[gi].nchunk; ++c) rf.push_back(WorkItem{gi, r, c, 0});
+  }, lds_rf_of);
+  build_segments(key_t, P.s_ra, ra, [&](int gi) {
+    for (int r = 0; r < P.g[gi].nrows; ++r)
+      for (int c = 0; c < P.g[gi].nchunk; ++c) ra.push_back(WorkItem{gi, r, c, 0});
+  }, lds_ra_of);
+  build_segments(key_t, P.s_rfin, rfin, [&](int gi) {
+    for (int r = 0; r < P.g[gi].nrows; ++r) rfin.push_back(WorkItem{gi, r, 0, 0});
+  }, lds_fin_of);
   if (wav.empty()) wav.push_back(0.f);
 
-  // LDS per kernel family (max over gathers)
-  for (auto& gh : P.g) {
-    const int nband = gh.z.jhi - gh.z.jlo + 1;
-    P.lds_x = std::max(P.lds_x, (size_t)(gh.tileT / 2) * (gh.z.nxp + 1) * 8);
-    P.lds_rf = std::max(P.lds_rf, (size_t)gh.z.ntp * 8);
-    P.lds_ra = std::max(P.lds_ra, (size_t)gh.z.ntp * 16 + (size_t)nband * 20);
-  }
-  if (P.lds_x > 160 * 1024 || P.lds_ra > 160 * 1024)
-    return fail(ASHRT_E_UNSUPPORTED_SIZE, "LDS requirement exceeds 160 KB");
+  for (auto* segs : {&P.s_xm, &P.s_xd, &P.s_rf, &P.s_rfin, &P.s_ra})
+    for (auto& sg : *segs)
+      if (sg.lds > kMaxDynLds) return fail(ASHRT_E_UNSUPPORTED_SIZE, "LDS requirement exceeds the per-workgroup limit");
 
   // one device allocation for all tables
   struct Part {
@@ -457,7 +538,12 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
     return fail(ASHRT_E_OOM, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
   }
   e = hipMemcpy(P.dev, host.data(), total, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = op_kernels_set_lds(P.lds_x, P.lds_rf, P.lds_ra);
+  if (e == hipSuccess) {
+    static std::once_flag once;
+    static hipError_t init_err = hipSuccess;
+    std::call_once(once, [] { init_err = op_kernels_init(kMaxDynLds); });
+    e = init_err;
+  }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     destroy_impl(P);
@@ -573,6 +659,82 @@ extern "C" int ashrt_batch_layout(const ashrt_batch_plan* plan, int64_t* data_of
   return ASHRT_OK;
 }
 
+// ------------------------------------------------------------ profiling
+namespace {
+
+struct Prof {
+  unsigned mask = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[ASHRT_K_COUNT];
+  std::vector<hipEvent_t> pool;
+};
+Prof g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` (returning hipError_t) between two recorded events when the
+// family is enabled.
+template <class F>
+hipError_t timed(int kid, hipStream_t s, F&& launch) {
+  if (!(g_prof.mask & (1u << kid))) return launch();
+  hipEvent_t a = prof_event(), b = prof_event();
+  if (!a || !b) return launch();
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  g_prof.rec[kid].push_back({a, b});
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int ashrt_profile_enable(uint32_t mask) {
+  g_prof.mask = mask;
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_profile_read(int kid, double* total_ms, int64_t* launches, int reset) {
+  if (kid < 0 || kid >= ASHRT_K_COUNT) return fail(ASHRT_E_INVALID_ARG, "unknown kernel id");
+  double tot = 0.0;
+  auto& v = g_prof.rec[kid];
+  for (auto& pr : v) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)v.size();
+  if (reset) {
+    for (auto& pr : v) {
+      g_prof.pool.push_back(pr.first);
+      g_prof.pool.push_back(pr.second);
+    }
+    v.clear();
+  }
+  return ASHRT_OK;
+}
+
+extern "C" const char* ashrt_kernel_name(int kid) {
+  static const char* names[ASHRT_K_COUNT] = {"k_xfft_fwd(model)", "k_xfft_fwd(data)", "k_rows_fwd",
+                                             "k_rows_fwd_fin",    "k_xfft_inv(data)", "k_rows_adj",
+                                             "k_xfft_inv(model)", "k_elementwise",    "k_reduce",
+                                             "k_sel"};
+  if (kid < 0 || kid >= ASHRT_K_COUNT) return "unknown";
+  return names[kid];
+}
+
 // ------------------------------------------------------------ operator pipelines
 namespace {
 
@@ -597,73 +759,119 @@ RowsArgs rows_args(const Ctx& c, const WorkItem* items, int n) {
   a.X = c.X();
   a.H = c.H();
   a.Dp = c.Dp();
+  a.R = c.P->R;
   return a;
 }
 
 // d_out = epilogue(L (mul_m * m)); the epilogue is: raw_out = y; y = sub - y;
 // y *= mask; y *= wmul.
 hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* d_out, const float* sub,
-                       const float* wmul, float* raw_out, const uint8_t* tmask) {
+                       const float* wmul, float* raw_out, const uint8_t* tmask, double* part = nullptr) {
   const PlanImpl& P = *c.P;
-  XfwdArgs xa{};
-  xa.gd = P.d_gd;
-  xa.items = P.d_xm;
-  xa.nitems = P.n_xm;
-  xa.is_model = 1;
-  xa.src = m;
-  xa.mul = mul_m;
-  xa.tmask = nullptr;
-  xa.dst = c.X();
-  xa.tw = P.d_tw;
-  hipError_t e = launch_xfft_fwd(xa, P.lds_x, c.s);
-  if (e != hipSuccess) return e;
-  e = launch_rows_fwd(P.R, rows_args(c, P.d_rf, P.n_rf), P.lds_rf, c.s);
-  if (e != hipSuccess) return e;
-  e = launch_rows_fwd_fin(rows_args(c, P.d_rfin, P.n_rfin), P.lds_rf, c.s);
-  if (e != hipSuccess) return e;
-  XinvArgs ia{};
-  ia.gd = P.d_gd;
-  ia.items = P.d_xd;
-  ia.nitems = P.n_xd;
-  ia.is_model = 0;
-  ia.src = c.H();
-  ia.out = d_out;
-  ia.sub = sub;
-  ia.wmul = wmul;
-  ia.raw_out = raw_out;
-  ia.tmask = tmask;
-  ia.tw = P.d_tw;
-  return launch_xfft_inv(ia, P.lds_x, c.s);
+  hipError_t e = hipSuccess;
+  for (const auto& sg : P.s_xm) {
+    XfwdArgs xa{};
+    xa.gd = P.d_gd;
+    xa.items = P.d_xm + sg.first;
+    xa.nitems = sg.count;
+    xa.item_base = sg.first;
+    xa.is_model = 1;
+    xa.src = m;
+    xa.mul = mul_m;
+    xa.dst = c.X();
+    xa.tw = P.d_tw;
+    e = timed(ASHRT_K_XFFT_MODEL, c.s, [&] { return launch_xfft_fwd(sg.key, xa, sg.lds, c.s); });
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& sg : P.s_rf) {
+    e = timed(ASHRT_K_ROWS_FWD, c.s,
+              [&] { return launch_rows_fwd(sg.key, rows_args(c, P.d_rf + sg.first, sg.count), sg.lds, c.s); });
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& sg : P.s_rfin) {
+    e = timed(ASHRT_K_ROWS_FIN, c.s, [&] {
+      return launch_rows_fwd_fin(sg.key, rows_args(c, P.d_rfin + sg.first, sg.count), sg.lds, c.s);
+    });
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& sg : P.s_xd) {
+    XinvArgs ia{};
+    ia.gd = P.d_gd;
+    ia.items = P.d_xd + sg.first;
+    ia.nitems = sg.count;
+    ia.item_base = sg.first;
+    ia.is_model = 0;
+    ia.src = c.H();
+    ia.out = d_out;
+    ia.sub = sub;
+    ia.wmul = wmul;
+    ia.raw_out = raw_out;
+    ia.tmask = tmask;
+    ia.tw = P.d_tw;
+    ia.part = part;
+    e = timed(ASHRT_K_XINV_DATA, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-// m_out = wmul * L' (mask * mul_d * d)
+// CG step folded into the adjoint's first pass (s -= alpha q first).
+struct CgStep {
+  float* s_inout = nullptr;
+  const float* qv = nullptr;
+  const double* part_delta = nullptr;
+  double* sc = nullptr;
+  int par = 0;
+};
+
+// m_out = wmul * L' (mask * mul_d * d); part: per-tile sums of m_out^2
 hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const uint8_t* tmask, float* m_out,
-                       const float* wmul) {
+                       const float* wmul, double* part = nullptr, const CgStep* cg = nullptr) {
   const PlanImpl& P = *c.P;
-  XfwdArgs xa{};
-  xa.gd = P.d_gd;
-  xa.items = P.d_xd;
-  xa.nitems = P.n_xd;
-  xa.is_model = 0;
-  xa.src = d;
-  xa.mul = mul_d;
-  xa.tmask = tmask;
-  xa.dst = c.H();
-  xa.tw = P.d_tw;
-  hipError_t e = launch_xfft_fwd(xa, P.lds_x, c.s);
-  if (e != hipSuccess) return e;
-  e = launch_rows_adj(P.R, rows_args(c, P.d_ra, P.n_ra), P.lds_ra, c.s);
-  if (e != hipSuccess) return e;
-  XinvArgs ia{};
-  ia.gd = P.d_gd;
-  ia.items = P.d_xm;
-  ia.nitems = P.n_xm;
-  ia.is_model = 1;
-  ia.src = c.X();
-  ia.out = m_out;
-  ia.wmul = wmul;
-  ia.tw = P.d_tw;
-  return launch_xfft_inv(ia, P.lds_x, c.s);
+  hipError_t e = hipSuccess;
+  for (const auto& sg : P.s_xd) {
+    XfwdArgs xa{};
+    xa.gd = P.d_gd;
+    xa.items = P.d_xd + sg.first;
+    xa.nitems = sg.count;
+    xa.item_base = sg.first;
+    xa.is_model = 0;
+    xa.src = d;
+    xa.mul = mul_d;
+    xa.tmask = tmask;
+    xa.dst = c.H();
+    xa.tw = P.d_tw;
+    if (cg) {
+      xa.s_inout = cg->s_inout;
+      xa.qv = cg->qv;
+      xa.part_delta = cg->part_delta;
+      xa.sc = cg->sc;
+      xa.par = cg->par;
+    }
+    e = timed(ASHRT_K_XFFT_DATA, c.s, [&] { return launch_xfft_fwd(sg.key, xa, sg.lds, c.s); });
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& sg : P.s_ra) {
+    e = timed(ASHRT_K_ROWS_ADJ, c.s,
+              [&] { return launch_rows_adj(sg.key, rows_args(c, P.d_ra + sg.first, sg.count), sg.lds, c.s); });
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& sg : P.s_xm) {
+    XinvArgs ia{};
+    ia.gd = P.d_gd;
+    ia.items = P.d_xm + sg.first;
+    ia.nitems = sg.count;
+    ia.item_base = sg.first;
+    ia.is_model = 1;
+    ia.src = c.X();
+    ia.out = m_out;
+    ia.wmul = wmul;
+    ia.tw = P.d_tw;
+    ia.part = part;
+    e = timed(ASHRT_K_XINV_MODEL, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 int check_ws(const PlanImpl& P, int op, int q, void* ws, size_t ws_bytes, Ctx* c, void* stream) {
@@ -728,6 +936,8 @@ struct Solver {
   float* u;
   float* Wminv;
   double* part;
+  double* pdel;
+  double* pgam;
   double* sc;
   SelState* sel;
   unsigned* hist;
@@ -756,7 +966,7 @@ struct Solver {
     a.sc = sc;
     a.p = prm.p;
     a.part = part;
-    hipError_t e = launch_reduce_part(a, c.s);
+    hipError_t e = timed(ASHRT_K_REDUCE, c.s, [&] { return launch_reduce_part(a, c.s); });
     if (e != hipSuccess) return e;
     FinArgs f{};
     f.gd = P.d_gd;
@@ -769,7 +979,7 @@ struct Solver {
     f.dst1 = dst1;
     f.rep = rp;
     f.outer = outer;
-    return launch_reduce_fin(f, c.s);
+    return timed(ASHRT_K_REDUCE, c.s, [&] { return launch_reduce_fin(f, c.s); });
   }
   hipError_t scalar(int step, int outer) const {
     ScalArgs a{};
@@ -784,6 +994,20 @@ struct Solver {
     a.freeze = prm.freeze_eps;
     return launch_scalar(a, c.s);
   }
+  hipError_t cg(int init, int par) const {
+    CgArgs a{};
+    a.gd = P.d_gd;
+    a.items = P.d_vm;
+    a.nitems = P.n_vm;
+    a.init = init;
+    a.par = par;
+    a.u = u;
+    a.pdir = pdir;
+    a.g = g;
+    a.part_gamma = pgam;
+    a.sc = sc;
+    return timed(ASHRT_K_VECTOR, c.s, [&] { return launch_cg(a, c.s); });
+  }
   hipError_t median(const float* x, const uint8_t* tmask, int stage, int dst) const {
     SelArgs a{};
     a.gd = P.d_gd;
@@ -796,7 +1020,7 @@ struct Solver {
     a.st = sel;
     a.hist = hist;
     a.stage = stage;
-    return launch_select_median(a, sc, dst, c.s);
+    return timed(ASHRT_K_SELECT, c.s, [&] { return launch_select_median(a, sc, dst, c.s); });
   }
 };
 
@@ -826,7 +1050,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
            (float*)(W + L.pdir), (float*)(W + L.g),
            prm->q == 1 ? (float*)(W + L.u) : m,
            prm->q == 1 ? (float*)(W + L.Wminv) : nullptr,
-           (double*)(W + L.part), (double*)(W + L.sc), (SelState*)(W + L.sel), (unsigned*)(W + L.hist),
+           (double*)(W + L.part), (double*)(W + L.pdel), (double*)(W + L.pgam), (double*)(W + L.sc), (SelState*)(W + L.sel), (unsigned*)(W + L.hist),
            (RepDev*)(W + L.rep)};
   const hipStream_t s = c.s;
   const bool q1 = prm->q == 1, p1 = prm->p == 1;
@@ -849,16 +1073,16 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       a.y = S.Wr;
       a.x = w0;
       a.tmask = mask;
-      E_TRY(launch_elementwise(a, s));
+      E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
       if (q1) {
         EwArgs f = S.ew(EW_FILL, true);
         f.y = S.Wminv;
         f.value = 1.0f;
-        E_TRY(launch_elementwise(f, s));
+        E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(f, s); }));
         EwArgs cp = S.ew(EW_COPY, true);
         cp.y = S.u;
         cp.x = m;
-        E_TRY(launch_elementwise(cp, s));
+        E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(cp, s); }));
       }
     } else {
       EwArgs a = S.ew(p1 ? EW_WR_UPDATE : EW_WR_MASK, false);
@@ -866,7 +1090,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       a.x = S.r;
       a.coef = SC_EPS_R;
       a.tmask = mask;
-      E_TRY(launch_elementwise(a, s));
+      E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
       if (q1) {
         E_TRY(S.reduce(RED_ABSMAX, true, m, nullptr, SC_MMAX, -1, true, nullptr, 0));
         E_TRY(S.scalar(ST_EPS_M, k));
@@ -875,50 +1099,33 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
         w.x = m;
         w.z_out = S.u;
         w.coef = SC_EPS_M;
-        E_TRY(launch_elementwise(w, s));
+        E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(w, s); }));
       }
     }
-    // CGLS on A = W_r S L W_m^-1 from u = W_m m:  s = W_r r ; g = A' s
+    // CGLS on A = W_r S L W_m^-1 from u = W_m m:  s = W_r r ; g = A' s ; pdir = g
     {
       EwArgs a = S.ew(EW_MUL, false);
       a.y = S.s;
       a.x = S.Wr;
       a.z = S.r;
-      E_TRY(launch_elementwise(a, s));
+      E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
     }
-    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv));
-    E_TRY(S.reduce(RED_SUMSQ, true, S.g, nullptr, SC_GAMMA_NEW, -1, false, nullptr, 0));
-    E_TRY(S.scalar(ST_CG_RESET, k));
-    {
-      EwArgs a = S.ew(EW_COPY, true);
-      a.y = S.pdir;
-      a.x = S.g;
-      E_TRY(launch_elementwise(a, s));
-    }
+    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam));
+    E_TRY(S.cg(1, 0));
     for (int i = 0; i < prm->n_inner; ++i) {
-      E_TRY(run_forward(c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask));
-      E_TRY(S.reduce(RED_SUMSQ, false, S.q, nullptr, SC_DELTA, -1, false, nullptr, 0));
-      E_TRY(S.scalar(ST_CG_ALPHA, k));
-      EwArgs a = S.ew(EW_AXPY, true);
-      a.y = S.u;
-      a.x = S.pdir;
-      a.coef = SC_ALPHA;
-      a.sign = 1.f;
-      E_TRY(launch_elementwise(a, s));
-      EwArgs b = S.ew(EW_AXPY, false);
-      b.y = S.s;
-      b.x = S.q;
-      b.coef = SC_ALPHA;
-      b.sign = -1.f;
-      E_TRY(launch_elementwise(b, s));
-      E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv));
-      E_TRY(S.reduce(RED_SUMSQ, true, S.g, nullptr, SC_GAMMA_NEW, -1, false, nullptr, 0));
-      E_TRY(S.scalar(ST_CG_BETA, k));
-      EwArgs pb = S.ew(EW_XPBY, true);
-      pb.y = S.pdir;
-      pb.x = S.g;
-      pb.coef = SC_BETA;
-      E_TRY(launch_elementwise(pb, s));
+      const int par = i & 1;
+      // q = W_r S L W_m^-1 pdir, with per-tile partials of |q|^2
+      E_TRY(run_forward(c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel));
+      // alpha = gamma / |q|^2 ; s -= alpha q ; g = W_m^-1 L' S W_r s (partials of |g|^2)
+      CgStep st;
+      st.s_inout = S.s;
+      st.qv = S.q;
+      st.part_delta = S.pdel;
+      st.sc = S.sc;
+      st.par = par;
+      E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st));
+      // beta ; u += alpha pdir ; pdir = g + beta pdir
+      E_TRY(S.cg(0, par));
     }
     E_TRY(S.scalar(ST_REPORT_INNER, k));
     if (q1) {
@@ -926,7 +1133,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       a.y = m;
       a.x = S.Wminv;
       a.z = S.u;
-      E_TRY(launch_elementwise(a, s));
+      E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
     }
     // residual, separated gather, clip and misfit
     E_TRY(run_forward(c, m, nullptr, S.r, d, nullptr, d_rec, mask));

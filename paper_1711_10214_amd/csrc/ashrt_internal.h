@@ -14,9 +14,11 @@ namespace ashrt {
 constexpr int kThreads = 256;          // threads per workgroup of every kernel
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
-constexpr int kXfftMaxTotal = 8192;    // complex points of one batched x-FFT tile
+constexpr int kXfftMaxTotal = 8192;    // complex points of one x-FFT tile in LDS
+constexpr int kXfftBatch = 2048;       // complex points per compile-time x-FFT call (register bound)
+constexpr int kXfftGenericBatch = 4096;  // complex points per generic x-FFT call (nxp <= 4096)
 constexpr int kMaxSlots = (kRowMaxN / 2 + kThreads - 1) / kThreads;  // per-thread bins
-constexpr long long kVecChunk = 65536; // elements per vector-kernel work item
+constexpr long long kVecChunk = 8192;  // elements per vector-kernel work item
 constexpr int kSelBins = 2048;         // radix-select histogram bins (11 bits)
 
 // One gather's geometry and its offsets into packed buffers.
@@ -27,14 +29,18 @@ struct GatherDev {
   int kmax;         // highest model bin the map reads or writes: min(ntp/2-1, jhi+R)
   int npanel;
   int panel_off;    // first panel in the panel table
-  int tw_t_off;     // float2 offset of the ntp twiddles in the twiddle pool
-  int tw_x_off;     // float2 offset of the nxp twiddles
+  int tw_t_off;     // float2 offset of the plain ntp twiddles exp(-2 pi i m / ntp) in the pool
+  int tw_x_off;     // float2 offset of the plain nxp twiddles
+  int twp_t_off;    // float2 offset of the ntp pass table (compile-time FFT lengths)
+  int twp_x_off;    // float2 offset of the nxp pass table
   int wav_off;      // float offset of the W_j table, -1 = none
   int tileT;        // time columns per x-FFT tile (even)
   int ntiles;       // ceil(nt / tileT)
   int nchunk;       // panel chunks of the forward row pass
   int mit_lo, mit_hi;   // model-vector work items of this gather
   int dit_lo, dit_hi;   // data-vector work items of this gather
+  int xm_lo, xm_hi;     // model x-FFT tile items of this gather (partial sums)
+  int xd_lo, xd_hi;     // data x-FFT tile items of this gather
   int pad_;
   long long d_off;      // float offset of the gather in packed data arrays
   long long m_off;      // float offset in packed model arrays
@@ -66,7 +72,7 @@ struct VecItem {
 
 // Device-side solver scalars, one block of kNScal doubles per gather.
 enum ScalIdx {
-  SC_GAMMA = 0, SC_GAMMA_NEW, SC_DELTA, SC_ALPHA, SC_BETA, SC_DONE, SC_NINNER,
+  SC_GAMMA0 = 0, SC_GAMMA1, SC_DELTA, SC_ALPHA, SC_BETA, SC_DONE, SC_NINNER,
   SC_DMAX, SC_MMAX, SC_EPS_R, SC_EPS_M, SC_EPS_FROZEN, SC_FROZEN_SET, SC_MED, SC_MAD,
   SC_NLIVE, SC_MISFIT, SC_HUBER, SC_NONFINITE,
   kNScal = 24

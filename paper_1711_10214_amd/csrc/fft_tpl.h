@@ -1,0 +1,161 @@
+// Compile-time-length Stockham FFT in LDS for 256-thread workgroups.
+//
+// N = 2^a or 3*2^a.  Passes: one radix-3 pass if 3 | N, then radix-8 passes,
+// then one radix-4 or radix-2 pass for the leftover power of two.  Pass i
+// with radix R and span Ns (product of the earlier radices) maps
+//   v_r = x[j + r N/R] * w^(r (j mod Ns)),  w = exp(-+2 pi i / (Ns R)),
+//   y[(j div Ns) Ns R + (j mod Ns) + r Ns] = DFT_R(v)_r .
+// Its twiddles w^(r jm), r = 1..R-1, jm = 0..Ns-1, are stored [r-1][jm]
+// (consecutive jm for a fixed r, so a wave reads consecutive LDS words) at
+// FftPlan<N>::twoff(i) in a per-length "pass table" built in FP64 on the
+// host.  Each pass reads its butterflies into registers, waits at a barrier,
+// and writes the outputs in place.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ashrt_internal.h"
+#include "fft_lds.h"
+
+namespace ashrt {
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+template <int N>
+struct FftPlan {
+  static constexpr bool three = (N % 3) == 0;
+  static constexpr int M = three ? N / 3 : N;
+  static constexpr int L = ilog2c(M);
+  static constexpr int n8 = L / 3;
+  static constexpr int rem = L % 3;
+  static constexpr int npass = (three ? 1 : 0) + n8 + (rem ? 1 : 0);
+  static constexpr int radix(int i) {
+    return (three && i == 0) ? 3 : (i < (three ? 1 : 0) + n8 ? 8 : (rem == 1 ? 2 : 4));
+  }
+  static constexpr int ns(int i) {
+    int s = 1;
+    for (int k = 0; k < i; ++k) s *= radix(k);
+    return s;
+  }
+  static constexpr int twoff(int i) {
+    int o = 0;
+    for (int k = 0; k < i; ++k) o += ns(k) * (radix(k) - 1);
+    return o;
+  }
+  static constexpr int twsize() { return twoff(npass); }
+};
+
+// Host and device: pass-table length for a runtime N of a supported size
+// (0 for lengths handled by the generic runtime FFT).
+// Lengths with a compile-time FFT (others use the runtime-generic fft_lds).
+#define ASHRT_TPL_SIZES(X) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+
+inline __host__ __device__ int fft_tpl_twsize(int n) {
+#define ASHRT_TW_CASE(S) \
+  if (n == S) return FftPlan<S>::twsize();
+  ASHRT_TPL_SIZES(ASHRT_TW_CASE)
+#undef ASHRT_TW_CASE
+  return 0;
+}
+
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  constexpr float h = 0.70710678118654752440f;
+  float2 b[4], c[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    b[n] = cadd(v[n], v[n + 4]);
+    c[n] = csub(v[n], v[n + 4]);
+  }
+  // c_n *= W^n, W = exp(-+2 pi i / 8)
+  {
+    const float2 x = c[1];
+    c[1] = INV ? make_float2(h * (x.x - x.y), h * (x.x + x.y)) : make_float2(h * (x.x + x.y), h * (x.y - x.x));
+    const float2 y = c[2];
+    c[2] = INV ? make_float2(-y.y, y.x) : make_float2(y.y, -y.x);
+    const float2 z = c[3];
+    c[3] = INV ? make_float2(-h * (z.x + z.y), h * (z.x - z.y)) : make_float2(h * (z.y - z.x), -h * (z.x + z.y));
+  }
+  float2 B[4] = {b[0], b[1], b[2], b[3]};
+  float2 C[4] = {c[0], c[1], c[2], c[3]};
+  butterfly<4, INV>(B);
+  butterfly<4, INV>(C);
+  v[0] = B[0];
+  v[2] = B[1];
+  v[4] = B[2];
+  v[6] = B[3];
+  v[1] = C[0];
+  v[3] = C[1];
+  v[5] = C[2];
+  v[7] = C[3];
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_r(float2 (&v)[R]) {
+  if constexpr (R == 8) dft8<INV>(v);
+  else butterfly<R, INV>(v);
+}
+
+// One pass of a batch of nb transforms (nb * N <= NBN) at buf + b*bstride.
+template <int N, int PASS, int NBN, bool INV>
+__device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const float2* twp) {
+  using P = FftPlan<N>;
+  constexpr int R = P::radix(PASS);
+  constexpr int Ns = P::ns(PASS);
+  constexpr int B = N / R;
+  constexpr int TW = P::twoff(PASS);
+  constexpr int MAXB = (NBN / R + kThreads - 1) / kThreads;
+  float2 v[MAXB][R];
+  int dst[MAXB];
+  const int total = B * nb;
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int id = (int)threadIdx.x + i * kThreads;
+    dst[i] = -1;
+    if (id < total) {
+      const int b = id / B;
+      const int j = id - b * B;
+      const int jq = j / Ns;
+      const int jm = j - jq * Ns;
+      const float2* src = buf + b * bstride + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = src[r * B];
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = twp[TW + (r - 1) * Ns + jm];
+          if (INV) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dft_r<R, INV>(v[i]);
+      dst[i] = b * bstride + jq * Ns * R + jm;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    if (dst[i] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int PASS, int NBN, bool INV>
+__device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, const float2* twp) {
+  if constexpr (PASS < FftPlan<N>::npass) {
+    tpl_pass<N, PASS, NBN, INV>(buf, nb, bstride, twp);
+    tpl_passes<N, PASS + 1, NBN, INV>(buf, nb, bstride, twp);
+  }
+}
+
+// Full transform(s); the caller places a barrier after filling buf.
+template <int N, int NBN, bool INV>
+__device__ __forceinline__ void fft_tpl(float2* buf, int nb, int bstride, const float2* twp) {
+  tpl_passes<N, 0, NBN, INV>(buf, nb, bstride, twp);
+}
+
+}  // namespace ashrt

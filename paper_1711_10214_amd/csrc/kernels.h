@@ -16,6 +16,15 @@ struct XfwdArgs {
   const uint8_t* tmask;   // optional trace mask (data only)
   float2* dst;
   const float2* tw;
+  // CG step (data input only): before the transform, s -= alpha q with
+  // alpha = gamma[par] / delta, delta summed from the forward's partials
+  // (every workgroup sums them in the same order; the first one stores it).
+  float* s_inout;
+  const float* qv;
+  const double* part_delta;
+  double* sc;
+  int par;
+  int item_base;          // index of items[0] in the plan's full list (partials, first-item checks)
 };
 
 struct XinvArgs {
@@ -30,6 +39,8 @@ struct XinvArgs {
   float* raw_out;         // data: y before the epilogue when set
   const uint8_t* tmask;   // data: out *= mask
   const float2* tw;
+  double* part;           // per work item: sum of out^2 (or NULL)
+  int item_base;          // index of items[0] in the plan's full list
 };
 
 struct RowsArgs {
@@ -42,6 +53,7 @@ struct RowsArgs {
   float2* X;              // model-side x-spectra / adjoint output G
   float2* H;              // data-side x-spectrum
   float2* Dp;             // forward partials
+  int R;                  // interpolation half-width (generic kernels)
 };
 
 enum RedOp { RED_SUMSQ = 0, RED_ABSMAX_LIVE = 1, RED_ABSMAX = 2, RED_MISFIT = 3 };
@@ -100,9 +112,6 @@ struct EwArgs {
 };
 
 enum ScalStep {
-  ST_CG_RESET = 0,     // done = 0, ninner = 0, gamma = gamma_new
-  ST_CG_ALPHA = 1,     // alpha = gamma/delta, or stop on an exact zero
-  ST_CG_BETA = 2,      // beta = gamma_new/gamma; gamma = gamma_new
   ST_EPS_M = 3,        // eps_m = b_m * mmax / 100
   ST_EPS_R = 4,        // eps_r = max(b_r * MAD / 0.6745, floor * dmax) (or frozen)
   ST_REPORT_INNER = 5  // report.inner[outer] = ninner
@@ -132,13 +141,34 @@ struct SelArgs {
   int shift, width;        // digit = (key >> shift) & ((1 << width) - 1)
 };
 
-// operator kernels
-hipError_t launch_xfft_fwd(const XfwdArgs& a, size_t lds, hipStream_t s);
-hipError_t launch_xfft_inv(const XinvArgs& a, size_t lds, hipStream_t s);
-hipError_t launch_rows_fwd(int R, const RowsArgs& a, size_t lds, hipStream_t s);
-hipError_t launch_rows_fwd_fin(const RowsArgs& a, size_t lds, hipStream_t s);
-hipError_t launch_rows_adj(int R, const RowsArgs& a, size_t lds, hipStream_t s);
-hipError_t op_kernels_set_lds(size_t xfft, size_t rows_fwd, size_t rows_adj);
+// CG initialisation and update over model-vector items.  Both reduce the
+// adjoint's per-tile partials of |g|^2 (each workgroup in the same order).
+//   init:   pdir = g ; gamma[0] = |g|^2, done = 0, ninner = 0
+//   update: beta = gamma_new / gamma[par] ; u += alpha pdir ; pdir = g + beta pdir ;
+//           gamma[par ^ 1] = gamma_new
+struct CgArgs {
+  const GatherDev* gd;
+  const VecItem* items;
+  int nitems;
+  int init;
+  int par;
+  float* u;
+  float* pdir;
+  const float* g;
+  const double* part_gamma;
+  double* sc;
+};
+
+// operator kernels; `key` is the FFT length class (see rows_size_is_tpl /
+// x_size_is_tpl; 0 = generic)
+bool rows_size_is_tpl(int n, int R);
+bool x_size_is_tpl(int n);
+hipError_t launch_xfft_fwd(int key, const XfwdArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_xfft_inv(int key, const XinvArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows_fwd(int key, const RowsArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows_fwd_fin(int key, const RowsArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows_adj(int key, const RowsArgs& a, size_t lds, hipStream_t s);
+hipError_t op_kernels_init(size_t max_lds);
 
 // solver kernels
 hipError_t launch_reduce_part(const RedArgs& a, hipStream_t s);
@@ -149,5 +179,6 @@ hipError_t launch_zero_words(void* p, long long n, hipStream_t s);
 hipError_t launch_count_live(const GatherDev* gd, int ngather, const uint8_t* tmask, double* sc,
                              hipStream_t s);
 hipError_t launch_select_median(SelArgs a, double* sc, int dst, hipStream_t s);
+hipError_t launch_cg(const CgArgs& a, hipStream_t s);
 
 }  // namespace ashrt

@@ -7,7 +7,7 @@
 //   forward  m_p[x][t] --(x-RFFT, per time column)--> X_p[l][t]     (HBM)
 //            per wavenumber row l (+ its mirror -l): time FFT of X_p[l][:]
 //            in LDS, Stolt map (gather over 2R taps) + phase ramp + scale,
-//            accumulated over the panels in registers --> partial D (HBM)
+//            accumulated over the panels in LDS --> partial D (HBM)
 //            sum of partials, Hermitian completion, inverse time FFT --> H[l][t]
 //            x-C2R per time column --> d[x][t] (+ mask, residual, weights)
 //   adjoint  the transposes in reverse: x-RFFT of the data, per row a time
@@ -21,25 +21,52 @@
 // spectra of +l (bins j) and -l (conjugated bins ntp - j) from one complex
 // time FFT.  Only interior bins 1..ntp/2-1 are mapped (Chapter 5: positive
 // frequencies, the negative ones by symmetry).
+//
+// FFT lengths in ASHRT_TPL_SIZES use the compile-time radix-8 Stockham FFT
+// with its pass twiddle table staged in LDS; other lengths use the generic
+// runtime FFT with the plain table exp(-2 pi i m / N).
+#include "block_reduce.h"
+#include "fft_tpl.h"
 #include "kernels.h"
-#include "fft_lds.h"
 
 namespace ashrt {
 
 // ------------------------------------------------------------ interpolation taps
 //
 // Hann-windowed sinc h(x) = sinc(x) (1/2 + 1/2 cos(pi x / R)), |x| < R, at
-// x = delta - t for the 2R taps t = -R+1..R around floor(u).  Using
-// sin(pi (delta - t)) = (-1)^t sin(pi delta) and the angle-difference formula,
-// one sincos pair per output bin gives all 2R weights.
+// x = delta - t for the 2R taps t = -R+1..R around floor(u).  With
+// theta = pi delta / R, sin(pi (delta - t)) = (-1)^t sin(R theta) and
+// cos(pi (delta - t) / R) = cos(theta) cos(pi t/R) + sin(theta) sin(pi t/R),
+// so one sine/cosine pair of theta per output bin gives all 2R weights.
 struct Taps {
   int k0;       // floor(u), or a large negative sentinel outside the cone
-  float4 trig;  // (delta, sin(pi delta)/pi, cos(pi delta/R), sin(pi delta/R))
+  float4 trig;  // (delta, sin(pi delta)/pi, cos(theta), sin(theta))
 };
 
 constexpr int kNoTap = -(1 << 28);
 
-// u = sqrt(j^2 - a^2) in FP64 (the coordinate decides the phase of the
+// sin and cos on [0, pi/2] by their Taylor series to the x^13 / x^12 terms
+// (truncation below 1e-8 there).
+__device__ __forceinline__ void sincos_quadrant(float x, float* s, float* c) {
+  const float z = x * x;
+  float ps = 1.0f / 6227020800.0f;
+  ps = fmaf(ps, -z, 1.0f / 39916800.0f);
+  ps = fmaf(ps, -z, 1.0f / 362880.0f);
+  ps = fmaf(ps, -z, 1.0f / 5040.0f);
+  ps = fmaf(ps, -z, 1.0f / 120.0f);
+  ps = fmaf(ps, -z, 1.0f / 6.0f);
+  ps = fmaf(ps, -z, 1.0f);       // sin x / x
+  *s = x * ps;
+  float pc = 1.0f / 479001600.0f;
+  pc = fmaf(pc, -z, 1.0f / 3628800.0f);
+  pc = fmaf(pc, -z, 1.0f / 40320.0f);
+  pc = fmaf(pc, -z, 1.0f / 720.0f);
+  pc = fmaf(pc, -z, 1.0f / 24.0f);
+  pc = fmaf(pc, -z, 0.5f);
+  *c = fmaf(pc, -z, 1.0f);
+}
+
+// u = sqrt(j^2 - a^2) in FP64 (the coordinate sets the phase of the
 // interpolated spectrum, so it must be exact to ~1e-7 bins).
 template <int R>
 __device__ __forceinline__ Taps make_taps(int j, double a2) {
@@ -54,10 +81,43 @@ __device__ __forceinline__ Taps make_taps(int j, double a2) {
   const double f = floor(u);
   T.k0 = (int)f;
   const float dl = (float)(u - f);
-  float s1, c1, s2, c2;
+  constexpr float kPi = 3.14159265358979323846f;
+  float st, ct, sR;
+  if constexpr (R == 1) {
+    sincospif(dl, &st, &ct);
+    sR = st;
+  } else {
+    // window angle theta = pi delta / R <= pi / 2
+    sincos_quadrant(dl * (kPi / (float)R), &st, &ct);
+    // sin(pi delta) = sin(pi min(delta, 1 - delta)): the reflection is exact
+    // in FP32 and keeps the relative accuracy where the sine is small (the
+    // sinc divides it by delta - t, which is small there too)
+    float s2, c2;
+    sincos_quadrant(kPi * fminf(dl, 1.0f - dl), &s2, &c2);
+    sR = s2;
+  }
+  T.trig = make_float4(dl, sR * 0.31830988618379067154f, ct, st);
+  return T;
+}
+
+// Runtime half-width (generic kernels): same quantities, R not known at
+// compile time.
+__device__ __forceinline__ Taps make_taps_rt(int j, double a2, int R) {
+  Taps T;
+  const double jj = (double)j * (double)j;
+  if (jj < a2) {
+    T.k0 = kNoTap;
+    T.trig = make_float4(0.f, 0.f, 1.f, 0.f);
+    return T;
+  }
+  const double u = sqrt(jj - a2);
+  const double f = floor(u);
+  T.k0 = (int)f;
+  const float dl = (float)(u - f);
+  float s1, c1, st, ct;
   sincospif(dl, &s1, &c1);
-  sincospif(dl * (1.0f / (float)R), &s2, &c2);
-  T.trig = make_float4(dl, s1 * 0.31830988618379067154f, c2, s2);
+  sincospif(dl / (float)R, &st, &ct);
+  T.trig = make_float4(dl, s1 * 0.31830988618379067154f, ct, st);
   return T;
 }
 
@@ -66,42 +126,107 @@ __device__ __forceinline__ float tap_weight(float4 tr, int t, float ct, float st
   const float x = tr.x - (float)t;
   if (x == 0.0f) return 1.0f;
   const float sg = (t & 1) ? -tr.y : tr.y;
-  const float win = 0.5f + 0.5f * (tr.z * ct + tr.w * st);
-  return sg / x * win;
+  const float win = fmaf(0.5f, fmaf(tr.z, ct, tr.w * st), 0.5f);
+  return sg * __builtin_amdgcn_rcpf(x) * win;
 }
 
-template <int R>
-__device__ __forceinline__ void init_tap_trig(float* ct, float* st) {
-  if (threadIdx.x < 2 * R) {
+__device__ __forceinline__ void init_tap_trig(float* ct, float* st, int R) {
+  if ((int)threadIdx.x < 2 * R) {
     const int t = (int)threadIdx.x - R + 1;
     ct[threadIdx.x] = (float)cospi((double)t / (double)R);
     st[threadIdx.x] = (float)sinpi((double)t / (double)R);
   }
 }
 
+template <int R>
+__device__ __forceinline__ Taps taps_of(int j, double a2, int Rrt) {
+  if constexpr (R > 0) return make_taps<R>(j, a2);
+  else return make_taps_rt(j, a2, Rrt);
+}
+
 // Per data bin j of panel p: W_j s_p exp(-2 pi i j n0 / ntp), from the exact
-// FFT twiddle table (the ramp index is reduced with integer arithmetic).
+// FFT twiddle table in global memory (the ramp index is reduced with integer
+// arithmetic).
 __device__ __forceinline__ float2 bin_factor(const GatherDev& G, const PanelDev& P,
-                                             const float2* __restrict__ twt,
+                                             const float2* __restrict__ tw,
                                              const float* __restrict__ wav, int j) {
   float2 e = make_float2(1.0f, 0.0f);
-  if (P.n0 != 0) e = twt[(int)(((long long)j * P.n0) % G.ntp)];
+  if (P.n0 != 0) e = tw[G.tw_t_off + (int)(((long long)j * P.n0) % G.ntp)];
   float s = P.scale;
   if (G.wav_off >= 0) s *= wav[G.wav_off + j];
   return cscale(e, s);
 }
 
-// ------------------------------------------------------------ x-direction RFFT
+// ------------------------------------------------------------ FFT dispatch
+// Copy the twiddles an FFT of length n needs into LDS (pass table for the
+// compile-time lengths, plain table otherwise).  No barrier.
+template <int N>
+__device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ tw, int plain_off,
+                                               int pass_off, int n) {
+  if constexpr (N > 0) {
+    constexpr int ntw = FftPlan<N>::twsize();
+    for (int i = threadIdx.x; i < ntw; i += kThreads) dst[i] = tw[pass_off + i];
+  } else {
+    for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = tw[plain_off + i];
+  }
+}
 
+// Batched x-axis FFTs of a tile: nb transforms of length n at stride
+// bstride, run in groups of at most kXfftBatch points per call (bounded
+// registers).  N > 0: compile-time length; N == 0: generic runtime FFT.
+template <int N, bool INV>
+__device__ __forceinline__ void xfft_tile(float2* buf, int n, int nb, int bstride, const float2* twl) {
+  if constexpr (N > 0) {
+    static_assert(N <= kXfftBatch, "compile-time x-FFT longer than one batch");
+    constexpr int per = kXfftBatch / N;
+    for (int b0 = 0; b0 < nb; b0 += per)
+      fft_tpl<N, kXfftBatch, INV>(buf + b0 * bstride, min(per, nb - b0), bstride, twl);
+  } else {
+    // generic: n <= 4096 = kXfftGenericBatch, so per >= 1
+    const int per = max(1, kXfftGenericBatch / n);
+    for (int b0 = 0; b0 < nb; b0 += per)
+      fft_lds<kThreads, kXfftGenericBatch, INV>(buf + b0 * bstride, n, min(per, nb - b0), bstride, twl);
+  }
+}
+
+// ------------------------------------------------------------ x-direction RFFT
+template <int NX>
 __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
   extern __shared__ float2 lds[];
+  __shared__ float s_alpha;
+  __shared__ double s_red[kThreads / 64];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
+    float alpha = 0.f;
+    if (A.s_inout) {
+      double part = 0.0;
+      for (int i = G.xd_lo + (int)threadIdx.x; i < G.xd_hi; i += kThreads) part += A.part_delta[i];
+      const double dsum = block_sum(part, s_red);
+      if (threadIdx.x == 0) {
+        double* sc = A.sc + (long long)w.g * kNScal;
+        const double delta = dsum;
+        const double gm = sc[SC_GAMMA0 + A.par];
+        const bool stop = sc[SC_DONE] != 0.0 || gm == 0.0 || delta == 0.0 || !isfinite(gm) || !isfinite(delta);
+        const double al = stop ? 0.0 : gm / delta;
+        s_alpha = (float)al;
+        if (A.item_base + it == G.xd_lo) {
+          sc[SC_DELTA] = delta;
+          sc[SC_ALPHA] = al;
+          if (stop) sc[SC_DONE] = 1.0;
+          else sc[SC_NINNER] += 1.0;
+        }
+      }
+      __syncthreads();
+      alpha = s_alpha;
+    }
     const int p = w.a;
     const int nx = G.nx, nt = G.nt, nxp = G.nxp, nrows = G.nrows;
     const int T = G.tileT, half = T >> 1, bs = nxp + 1;
     const int t0 = w.b * T;
+    float2* twl = lds;          // x twiddles (at most nxp entries)
+    float2* buf = lds + nxp;    // T/2 packed column pairs, stride nxp + 1
+    stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
     const float* __restrict__ src = A.src + fbase;
     const float* __restrict__ mul = A.mul ? A.mul + fbase : nullptr;
@@ -113,27 +238,44 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       const int t = t0 + 2 * i;
       const long long o = (long long)x * nt + t;
       float a = 0.f, b = 0.f;
-      if (t < nt) {
-        a = src[o];
-        if (mul) a *= mul[o];
-      }
-      if (t + 1 < nt) {
-        b = src[o + 1];
-        if (mul) b *= mul[o + 1];
+      if (A.s_inout) {
+        float* sv = A.s_inout + fbase;
+        const float* qv = A.qv + fbase;
+        if (t < nt) {
+          a = fmaf(-alpha, qv[o], sv[o]);
+          sv[o] = a;
+        }
+        if (t + 1 < nt) {
+          b = fmaf(-alpha, qv[o + 1], sv[o + 1]);
+          sv[o + 1] = b;
+        }
+        if (mul) {
+          a *= (t < nt) ? mul[o] : 0.f;
+          b *= (t + 1 < nt) ? mul[o + 1] : 0.f;
+        }
+      } else {
+        if (t < nt) {
+          a = src[o];
+          if (mul) a *= mul[o];
+        }
+        if (t + 1 < nt) {
+          b = src[o + 1];
+          if (mul) b *= mul[o + 1];
+        }
       }
       if (tm && tm[x] == 0) {
         a = 0.f;
         b = 0.f;
       }
-      lds[i * bs + x] = make_float2(a, b);
+      buf[i * bs + x] = make_float2(a, b);
     }
     for (int idx = threadIdx.x; idx < (nxp - nx) * half; idx += kThreads) {
       const int xx = idx / half;
       const int i = idx - xx * half;
-      lds[i * bs + nx + xx] = make_float2(0.f, 0.f);
+      buf[i * bs + nx + xx] = make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft_lds<kThreads, kXfftMaxTotal, false>(lds, nxp, half, bs, A.tw + G.tw_x_off);
+    xfft_tile<NX, false>(buf, nxp, half, bs, twl);
 
     float2* __restrict__ dst = A.dst + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
     for (int idx = threadIdx.x; idx < nrows * T; idx += kThreads) {
@@ -141,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       const int c = idx - r * T;
       const int t = t0 + c;
       if (t >= nt) continue;
-      const float2* Z = lds + (c >> 1) * bs;
+      const float2* Z = buf + (c >> 1) * bs;
       float2 out;
       if (r == 0) {
         const float2 z0 = Z[0], zn = Z[nrows];
@@ -159,9 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
 }
 
 // ------------------------------------------------------------ x-direction C2R
-
+template <int NX>
 __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
   extern __shared__ float2 lds[];
+  __shared__ double sh[kThreads / 64];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
@@ -170,6 +313,9 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const int T = G.tileT, half = T >> 1, bs = nxp + 1;
     const int t0 = w.b * T;
     const float2* __restrict__ src = A.src + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
+    float2* twl = lds;
+    float2* buf = lds + nxp;
+    stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
 
     for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
       const int l = idx / half;
@@ -178,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       float2 h1 = make_float2(0.f, 0.f), h2 = make_float2(0.f, 0.f);
       if (t < nt) h1 = src[(long long)l * nt + t];
       if (t + 1 < nt) h2 = src[(long long)l * nt + t + 1];
-      float2* Z = lds + i * bs;
+      float2* Z = buf + i * bs;
       if (l == 0) {
         Z[0] = make_float2(h1.x, h2.x);
         Z[nrows] = make_float2(h1.y, h2.y);
@@ -188,17 +334,18 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       }
     }
     __syncthreads();
-    fft_lds<kThreads, kXfftMaxTotal, true>(lds, nxp, half, bs, A.tw + G.tw_x_off);
+    xfft_tile<NX, true>(buf, nxp, half, bs, twl);
 
     const float inv = 1.0f / (float)nxp;
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
+    double ss = 0.0;
     for (int idx = threadIdx.x; idx < nx * T; idx += kThreads) {
       const int x = idx / T;
       const int c = idx - x * T;
       const int t = t0 + c;
       if (t >= nt) continue;
-      const float2 z = lds[(c >> 1) * bs + x];
+      const float2 z = buf[(c >> 1) * bs + x];
       float v = ((c & 1) ? z.y : z.x) * inv;
       const long long o = fbase + (long long)x * nt + t;
       if (A.raw_out) A.raw_out[o] = v;
@@ -206,22 +353,28 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       if (tm && tm[x] == 0) v = 0.f;
       if (A.wmul) v *= A.wmul[o];
       A.out[o] = v;
+      ss += (double)v * (double)v;
+    }
+    if (A.part) {
+      const double tot = block_sum(ss, sh);
+      if (threadIdx.x == 0) A.part[A.item_base + it] = tot;
     }
     __syncthreads();
   }
 }
 
-// ------------------------------------------------------------ forward rows
-
+// ------------------------------------------------------------ rows: shared steps
 // Load row r of a [nrows][nt] complex field into buf[0..nt), zero to ntp,
 // forward time FFT, and for row 0 separate the packed kx = 0 / Nyquist
 // spectra: slot k gets the kx = 0 spectrum, slot ntp-k the conjugate of the
 // Nyquist one, so that both rows read "up = buf[k], lo = conj(buf[ntp-k])".
-__device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restrict__ src, int r,
-                                             int nt, int ntp, const float2* __restrict__ twt) {
+template <int N>
+__device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restrict__ src, int r, int nt,
+                                             int ntp, const float2* twl) {
   for (int t = threadIdx.x; t < ntp; t += kThreads) buf[t] = (t < nt) ? src[t] : make_float2(0.f, 0.f);
   __syncthreads();
-  fft_lds<kThreads, kRowMaxN, false>(buf, ntp, 1, ntp, twt);
+  if constexpr (N > 0) fft_tpl<N, N, false>(buf, 1, N, twl);
+  else fft_lds<kThreads, kRowMaxN, false>(buf, ntp, 1, ntp, twl);
   if (r == 0) {
     for (int k = 1 + threadIdx.x; k < ntp / 2; k += kThreads) {
       const float2 a = buf[k];
@@ -235,47 +388,62 @@ __device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restri
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
-  extern __shared__ float2 lds[];
-  __shared__ float ctab[2 * R], stab[2 * R];
-  init_tap_trig<R>(ctab, stab);
-  __syncthreads();
-  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
-    const WorkItem w = A.items[it];
-    const GatherDev G = A.gd[w.g];
-    const int r = w.a, chunk = w.b;
-    const int nt = G.nt, ntp = G.ntp, nrows = G.nrows, P = G.npanel;
-    const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
-    const int p0 = (int)((long long)chunk * P / G.nchunk);
-    const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
-    const int hmax = ntp / 2 - 1;
-    const float2* __restrict__ twt = A.tw + G.tw_t_off;
-    const double lup2 = (double)(r == 0 ? 0 : r) * (double)(r == 0 ? 0 : r);
-    const double llo2 = (double)(r == 0 ? nrows : r) * (double)(r == 0 ? nrows : r);
+template <int N>
+__device__ __forceinline__ void row_inverse(float2* buf, int ntp, const float2* twl) {
+  if constexpr (N > 0) fft_tpl<N, N, true>(buf, 1, N, twl);
+  else fft_lds<kThreads, kRowMaxN, true>(buf, ntp, 1, ntp, twl);
+}
 
-    float2 dup[kMaxSlots], dlo[kMaxSlots];
-#pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) {
-      dup[s] = make_float2(0.f, 0.f);
-      dlo[s] = make_float2(0.f, 0.f);
-    }
-    for (int p = p0; p < p1; ++p) {
-      row_spectrum(lds, A.X + G.X_off + ((long long)p * nrows + r) * nt, r, nt, ntp, twt);
-      const PanelDev PD = A.panels[G.panel_off + p];
-#pragma unroll
-      for (int s = 0; s < kMaxSlots; ++s) {
-        const int j = jlo + (int)threadIdx.x + s * kThreads;
-        if (j > jhi) break;
-        const float2 cj = bin_factor(G, PD, twt, A.wav, j);
-        const Taps tu = make_taps<R>(j, PD.c2 * lup2);
-        const Taps tl = (r == 0) ? make_taps<R>(j, PD.c2 * llo2) : tu;
-        float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
+// ------------------------------------------------------------ forward rows
+//
+// LDS: twiddles [ntp], row spectrum [ntp], accumulators D(+l), D(-l) [2 nband].
+template <int N, int RC>
+__device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
+                                              float2* lds, const float* ctab, const float* stab) {
+  const int R = RC > 0 ? RC : A.R;
+  const int r = w.a, chunk = w.b;
+  const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows, P = G.npanel;
+  const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
+  const int p0 = (int)((long long)chunk * P / G.nchunk);
+  const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
+  const int hmax = ntp / 2 - 1;
+  float2* twl = lds;
+  float2* buf = lds + ntp;
+  float2* acc = lds + 2 * ntp;
+  stage_twiddles<N>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
+  for (int i = threadIdx.x; i < 2 * nband; i += kThreads) acc[i] = make_float2(0.f, 0.f);
+  const int lu = (r == 0) ? 0 : r;
+  const int ll = (r == 0) ? nrows : r;
+  const double lup2 = (double)lu * (double)lu;
+  const double llo2 = (double)ll * (double)ll;
+
+  for (int p = p0; p < p1; ++p) {
+    row_spectrum<N>(buf, A.X + G.X_off + ((long long)p * nrows + r) * nt, r, nt, ntp, twl);
+    const PanelDev PD = A.panels[G.panel_off + p];
+    const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
+#pragma unroll 1
+    for (int j = jlo + (int)threadIdx.x; j <= jhi; j += kThreads) {
+      const Taps tu = taps_of<RC>(j, PD.c2 * lup2, R);
+      float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
+      if (r != 0) {
         if (tu.k0 != kNoTap) {
 #pragma unroll
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tu.k0 + t;
-            if (k >= 1 && k <= hmax) au = cfma(tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]), lds[k], au);
+            if (k >= 1 && k <= hmax) {
+              const float wt = tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]);
+              au = cfma(wt, buf[k], au);
+              al = cfma(wt, cconj(buf[ntp - k]), al);
+            }
+          }
+        }
+      } else {
+        const Taps tl = taps_of<RC>(j, PD.c2 * llo2, R);
+        if (tu.k0 != kNoTap) {
+#pragma unroll
+          for (int t = -R + 1; t <= R; ++t) {
+            const int k = tu.k0 + t;
+            if (k >= 1 && k <= hmax) au = cfma(tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]), buf[k], au);
           }
         }
         if (tl.k0 != kNoTap) {
@@ -283,22 +451,38 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tl.k0 + t;
             if (k >= 1 && k <= hmax)
-              al = cfma(tap_weight(tl.trig, t, ctab[t + R - 1], stab[t + R - 1]), cconj(lds[ntp - k]), al);
+              al = cfma(tap_weight(tl.trig, t, ctab[t + R - 1], stab[t + R - 1]), cconj(buf[ntp - k]), al);
           }
         }
-        dup[s] = cadd(dup[s], cmul(cj, au));
-        dlo[s] = cadd(dlo[s], cmul(cj, al));
       }
-      __syncthreads();
+      float2* du = acc + (j - jlo);
+      float2* dl = acc + nband + (j - jlo);
+      if (plain) {
+        *du = cfma(PD.scale, au, *du);
+        *dl = cfma(PD.scale, al, *dl);
+      } else {
+        const float2 cj = bin_factor(G, PD, A.tw, A.wav, j);
+        *du = cadd(*du, cmul(cj, au));
+        *dl = cadd(*dl, cmul(cj, al));
+      }
     }
-    float2* __restrict__ dp = A.Dp + G.Dp_off + ((long long)chunk * nrows + r) * 2 * nband;
-#pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) {
-      const int j = jlo + (int)threadIdx.x + s * kThreads;
-      if (j > jhi) break;
-      dp[j - jlo] = dup[s];
-      dp[nband + j - jlo] = dlo[s];
-    }
+    __syncthreads();
+  }
+  float2* __restrict__ dp = A.Dp + G.Dp_off + ((long long)chunk * nrows + r) * 2 * nband;
+  for (int i = threadIdx.x; i < 2 * nband; i += kThreads) dp[i] = acc[i];
+  __syncthreads();
+}
+
+template <int N, int RC>
+__global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
+  extern __shared__ float2 lds[];
+  __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
+  init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
+  __syncthreads();
+  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    const WorkItem w = A.items[it];
+    const GatherDev G = A.gd[w.g];
+    rows_fwd_item<N, RC>(A, w, G, lds, ctab, stab);
   }
 }
 
@@ -306,211 +490,281 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
 // spectrum (rows >= 1: Q[j] = D(+l,j), Q[ntp-j] = conj D(-l,j); row 0:
 // Q[j] = D(0,j) + i D(N,j), Q[ntp-j] = conj D(0,j) + i conj D(N,j)), inverse
 // time FFT, scale 1/ntp, keep t < nt.
+template <int N>
+__device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
+                                              float2* lds) {
+  const int r = w.a;
+  const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows;
+  const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
+  float2* twl = lds;
+  float2* buf = lds + ntp;
+  stage_twiddles<N>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
+  for (int k = threadIdx.x; k < ntp; k += kThreads) {
+    float2 v = make_float2(0.f, 0.f);
+    const int j = (k >= jlo && k <= jhi) ? k : ((ntp - k >= jlo && ntp - k <= jhi) ? ntp - k : -1);
+    if (j >= 0) {
+      float2 su = make_float2(0.f, 0.f), sl = make_float2(0.f, 0.f);
+      for (int c = 0; c < G.nchunk; ++c) {
+        const float2* dp = A.Dp + G.Dp_off + ((long long)c * nrows + r) * 2 * nband;
+        su = cadd(su, dp[j - jlo]);
+        sl = cadd(sl, dp[nband + j - jlo]);
+      }
+      if (j == k) {
+        v = (r == 0) ? make_float2(su.x - sl.y, su.y + sl.x) : su;
+      } else {
+        v = (r == 0) ? make_float2(su.x + sl.y, -su.y + sl.x) : cconj(sl);
+      }
+    }
+    buf[k] = v;
+  }
+  __syncthreads();
+  row_inverse<N>(buf, ntp, twl);
+  const float inv = 1.0f / (float)ntp;
+  float2* __restrict__ dst = A.H + G.H_off + (long long)r * nt;
+  for (int t = threadIdx.x; t < nt; t += kThreads) dst[t] = cscale(buf[t], inv);
+  __syncthreads();
+}
+
+template <int N>
 __global__ __launch_bounds__(kThreads) void k_rows_fwd_fin(RowsArgs A) {
   extern __shared__ float2 lds[];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    const int r = w.a;
-    const int nt = G.nt, ntp = G.ntp, nrows = G.nrows;
-    const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
-    for (int k = threadIdx.x; k < ntp; k += kThreads) {
-      float2 v = make_float2(0.f, 0.f);
-      const int j = (k >= jlo && k <= jhi) ? k : ((ntp - k >= jlo && ntp - k <= jhi) ? ntp - k : -1);
-      if (j >= 0) {
-        float2 su = make_float2(0.f, 0.f), sl = make_float2(0.f, 0.f);
-        for (int c = 0; c < G.nchunk; ++c) {
-          const float2* dp = A.Dp + G.Dp_off + ((long long)c * nrows + r) * 2 * nband;
-          su = cadd(su, dp[j - jlo]);
-          sl = cadd(sl, dp[nband + j - jlo]);
-        }
-        if (j == k) {
-          v = (r == 0) ? make_float2(su.x - sl.y, su.y + sl.x) : su;
-        } else {
-          v = (r == 0) ? make_float2(su.x + sl.y, -su.y + sl.x) : cconj(sl);
-        }
-      }
-      lds[k] = v;
-    }
-    __syncthreads();
-    fft_lds<kThreads, kRowMaxN, true>(lds, ntp, 1, ntp, A.tw + G.tw_t_off);
-    const float inv = 1.0f / (float)ntp;
-    float2* __restrict__ dst = A.H + G.H_off + (long long)r * nt;
-    for (int t = threadIdx.x; t < nt; t += kThreads) dst[t] = cscale(lds[t], inv);
-    __syncthreads();
+    rows_fin_item<N>(A, w, G, lds);
   }
 }
 
 // ------------------------------------------------------------ adjoint rows
 //
-// LDS: bufD[ntp] (data time spectrum of the row), bufM[ntp] (per panel: first
-// the ramp-weighted data bins E(j) = conj(c_pj) D(j), then the model
-// spectrum), and per-bin tap tables (k0, trig) over the band.
-template <int R>
+// LDS: twiddles [ntp], data row spectrum bufD [ntp], model spectrum bufM
+// [ntp], and per band bin: the data-bin factor c_j (float2, only when a
+// panel has a ramp or a wavelet weight), tap trig (float4) and k0 (int).
+template <int N, int RC>
+__device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
+                                              float2* lds, const float* ctab, const float* stab) {
+  const int R = RC > 0 ? RC : A.R;
+  const int r = w.a, chunk = w.b;
+  const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows, P = G.npanel;
+  const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
+  const int kmax = G.kmax;
+  const int p0 = (int)((long long)chunk * P / G.nchunk);
+  const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
+  float2* twl = lds;
+  float2* bufD = lds + ntp;
+  float2* bufM = lds + 2 * ntp;
+  float2* tab_c = lds + 3 * ntp;
+  float4* tab_tr = reinterpret_cast<float4*>(tab_c + nband + (nband & 1));
+  int* tab_k0 = reinterpret_cast<int*>(tab_tr + nband);
+  stage_twiddles<N>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
+
+  row_spectrum<N>(bufD, A.H + G.H_off + (long long)r * nt, r, nt, ntp, twl);
+
+  const int npass = (r == 0) ? 2 : 1;
+  for (int p = p0; p < p1; ++p) {
+    const PanelDev PD = A.panels[G.panel_off + p];
+    const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
+    for (int k = threadIdx.x; k < ntp; k += kThreads) bufM[k] = make_float2(0.f, 0.f);
+    for (int pass = 0; pass < npass; ++pass) {
+      const int l = (r == 0) ? (pass == 0 ? 0 : nrows) : r;
+      const double a2 = PD.c2 * (double)l * (double)l;
+      // phase 1: taps (and the ramp factor) per band bin
+      for (int j = jlo + threadIdx.x; j <= jhi; j += kThreads) {
+        const Taps T = taps_of<RC>(j, a2, R);
+        tab_k0[j - jlo] = T.k0;
+        tab_tr[j - jlo] = T.trig;
+        if (!plain) tab_c[j - jlo] = bin_factor(G, PD, A.tw, A.wav, j);
+      }
+      __syncthreads();
+      // phase 2: gather over the data bins whose taps reach model bin k
+      const float a2f = (float)a2;
+#pragma unroll 1
+      for (int k = 1 + (int)threadIdx.x; k <= kmax; k += kThreads) {
+        const float lo = (float)max(k - R, 0);
+        const float hi = (float)(k + R);
+        int ja = (int)ceilf(sqrtf(fmaf(lo, lo, a2f))) - 1;
+        int jb = (int)ceilf(sqrtf(fmaf(hi, hi, a2f))) + 1;
+        ja = max(ja, jlo);
+        jb = min(jb, jhi);
+        float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
+        for (int j = ja; j <= jb; ++j) {
+          const int t = k - tab_k0[j - jlo];
+          if (t < -R + 1 || t > R) continue;
+          const float wgt = tap_weight(tab_tr[j - jlo], t, ctab[t + R - 1], stab[t + R - 1]);
+          float2 du = bufD[j];
+          float2 dl = cconj(bufD[ntp - j]);
+          if (!plain) {
+            const float2 c = tab_c[j - jlo];
+            du = cmulconj(du, c);
+            dl = cmulconj(dl, c);
+          }
+          if (r != 0 || pass == 0) au = cfma(wgt, du, au);
+          if (r != 0 || pass == 1) al = cfma(wgt, dl, al);
+        }
+        if (plain) {
+          au = cscale(au, PD.scale);
+          al = cscale(al, PD.scale);
+        }
+        // model time spectrum: rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l);
+        // row 0: Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
+        if (r != 0) {
+          bufM[k] = au;
+          bufM[ntp - k] = cconj(al);
+        } else if (pass == 0) {
+          bufM[k] = au;  // kept until pass 1 (same thread owns k)
+        } else {
+          const float2 u = bufM[k];
+          bufM[k] = make_float2(u.x - al.y, u.y + al.x);
+          bufM[ntp - k] = make_float2(u.x + al.y, -u.y + al.x);
+        }
+      }
+      __syncthreads();
+    }
+    row_inverse<N>(bufM, ntp, twl);
+    const float inv = 1.0f / (float)ntp;
+    float2* __restrict__ dst = A.X + G.X_off + ((long long)p * nrows + r) * nt;
+    for (int t = threadIdx.x; t < nt; t += kThreads) dst[t] = cscale(bufM[t], inv);
+    __syncthreads();
+  }
+}
+
+template <int N, int RC>
 __global__ __launch_bounds__(kThreads) void k_rows_adj(RowsArgs A) {
   extern __shared__ float2 lds[];
-  __shared__ float ctab[2 * R], stab[2 * R];
-  init_tap_trig<R>(ctab, stab);
+  __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
+  init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
   __syncthreads();
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    const int r = w.a, chunk = w.b;
-    const int nt = G.nt, ntp = G.ntp, nrows = G.nrows, P = G.npanel;
-    const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
-    const int kmax = G.kmax;
-    const int p0 = (int)((long long)chunk * P / G.nchunk);
-    const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
-    const float2* __restrict__ twt = A.tw + G.tw_t_off;
-    float2* bufD = lds;
-    float2* bufM = lds + ntp;
-    float4* tab_tr = reinterpret_cast<float4*>(lds + 2 * ntp);
-    int* tab_k0 = reinterpret_cast<int*>(tab_tr + nband);
-
-    row_spectrum(bufD, A.H + G.H_off + (long long)r * nt, r, nt, ntp, twt);
-
-    const int npass = (r == 0) ? 2 : 1;
-    for (int p = p0; p < p1; ++p) {
-      const PanelDev PD = A.panels[G.panel_off + p];
-      float2 mup[kMaxSlots], mlo[kMaxSlots];
-#pragma unroll
-      for (int s = 0; s < kMaxSlots; ++s) {
-        mup[s] = make_float2(0.f, 0.f);
-        mlo[s] = make_float2(0.f, 0.f);
-      }
-      for (int pass = 0; pass < npass; ++pass) {
-        const int l = (r == 0) ? (pass == 0 ? 0 : nrows) : r;
-        const double a2 = PD.c2 * (double)l * (double)l;
-        // phase 1: taps and ramp-weighted data per band bin
-        for (int j = jlo + threadIdx.x; j <= jhi; j += kThreads) {
-          const Taps T = make_taps<R>(j, a2);
-          tab_k0[j - jlo] = T.k0;
-          tab_tr[j - jlo] = T.trig;
-          const float2 cj = bin_factor(G, PD, twt, A.wav, j);
-          bufM[j] = cmulconj(bufD[j], cj);                   // E_up(j) = conj(c) D(+l, j)
-          bufM[ntp - j] = cmulconj(cconj(bufD[ntp - j]), cj);  // E_lo(j) = conj(c) D(-l, j)
-        }
-        __syncthreads();
-        // phase 2: gather, one model bin k per thread slot
-        const float a2f = (float)a2;
-#pragma unroll
-        for (int s = 0; s < kMaxSlots; ++s) {
-          const int k = 1 + (int)threadIdx.x + s * kThreads;
-          if (k > kmax) break;
-          const float lo = (float)max(k - R, 0);
-          const float hi = (float)(k + R);
-          int ja = (int)ceilf(sqrtf(lo * lo + a2f)) - 1;
-          int jb = (int)ceilf(sqrtf(hi * hi + a2f)) + 1;
-          ja = max(ja, jlo);
-          jb = min(jb, jhi);
-          float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
-          for (int j = ja; j <= jb; ++j) {
-            const int t = k - tab_k0[j - jlo];
-            if (t < -R + 1 || t > R) continue;
-            const float wgt = tap_weight(tab_tr[j - jlo], t, ctab[t + R - 1], stab[t + R - 1]);
-            if (r != 0 || pass == 0) au = cfma(wgt, bufM[j], au);
-            if (r != 0 || pass == 1) al = cfma(wgt, bufM[ntp - j], al);
-          }
-          if (r != 0 || pass == 0) mup[s] = au;
-          if (r != 0 || pass == 1) mlo[s] = al;
-        }
-        __syncthreads();
-      }
-      // model time spectrum of panel p, then inverse time FFT
-      for (int k = threadIdx.x; k < ntp; k += kThreads) bufM[k] = make_float2(0.f, 0.f);
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < kMaxSlots; ++s) {
-        const int k = 1 + (int)threadIdx.x + s * kThreads;
-        if (k > kmax) break;
-        const float2 u = mup[s], v = mlo[s];
-        if (r == 0) {
-          bufM[k] = make_float2(u.x - v.y, u.y + v.x);
-          bufM[ntp - k] = make_float2(u.x + v.y, -u.y + v.x);
-        } else {
-          bufM[k] = u;
-          bufM[ntp - k] = cconj(v);
-        }
-      }
-      __syncthreads();
-      fft_lds<kThreads, kRowMaxN, true>(bufM, ntp, 1, ntp, twt);
-      const float inv = 1.0f / (float)ntp;
-      float2* __restrict__ dst = A.X + G.X_off + ((long long)p * nrows + r) * nt;
-      for (int t = threadIdx.x; t < nt; t += kThreads) dst[t] = cscale(bufM[t], inv);
-      __syncthreads();
-    }
+    rows_adj_item<N, RC>(A, w, G, lds, ctab, stab);
   }
 }
 
 // ------------------------------------------------------------ launchers
-template <int R>
-static void launch_rows_fwd_t(const RowsArgs& a, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_rows_fwd<R>, dim3(a.nitems), dim3(kThreads), lds, s, a);
+//
+// One instantiation per compile-time FFT length (time: ASHRT_ROW_SIZES with
+// R = 4; x: ASHRT_X_SIZES); every other length or half-width runs the
+// generic kernels (runtime FFT, runtime R).  The host groups work items by
+// the length class so each launch uses one instantiation.
+#define ASHRT_ROW_SIZES(X) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+#define ASHRT_X_SIZES(X) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+bool rows_size_is_tpl(int n, int R) {
+  if (R != 4) return false;
+#define C_(S) if (n == S) return true;
+  ASHRT_ROW_SIZES(C_)
+#undef C_
+  return false;
 }
-template <int R>
-static void launch_rows_adj_t(const RowsArgs& a, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_rows_adj<R>, dim3(a.nitems), dim3(kThreads), lds, s, a);
+bool x_size_is_tpl(int n) {
+#define C_(S) if (n == S) return true;
+  ASHRT_X_SIZES(C_)
+#undef C_
+  return false;
 }
 
-#define ASHRT_R_SWITCH(R, CALL) \
-  switch (R) {                  \
-    case 1: CALL(1); break;     \
-    case 2: CALL(2); break;     \
-    case 3: CALL(3); break;     \
-    case 4: CALL(4); break;     \
-    case 5: CALL(5); break;     \
-    case 6: CALL(6); break;     \
-    case 7: CALL(7); break;     \
-    case 8: CALL(8); break;     \
-    default: return hipErrorInvalidValue; \
-  }
-
-hipError_t launch_xfft_fwd(const XfwdArgs& a, size_t lds, hipStream_t s) {
-  if (a.nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xfft_fwd, dim3(a.nitems), dim3(kThreads), lds, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_xfft_inv(const XinvArgs& a, size_t lds, hipStream_t s) {
-  if (a.nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xfft_inv, dim3(a.nitems), dim3(kThreads), lds, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_rows_fwd(int R, const RowsArgs& a, size_t lds, hipStream_t s) {
-  if (a.nitems <= 0) return hipSuccess;
-#define CALLF(RR) launch_rows_fwd_t<RR>(a, lds, s)
-  ASHRT_R_SWITCH(R, CALLF)
-#undef CALLF
-  return hipGetLastError();
-}
-hipError_t launch_rows_fwd_fin(const RowsArgs& a, size_t lds, hipStream_t s) {
-  if (a.nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_fwd_fin, dim3(a.nitems), dim3(kThreads), lds, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_rows_adj(int R, const RowsArgs& a, size_t lds, hipStream_t s) {
-  if (a.nitems <= 0) return hipSuccess;
-#define CALLA(RR) launch_rows_adj_t<RR>(a, lds, s)
-  ASHRT_R_SWITCH(R, CALLA)
-#undef CALLA
-  return hipGetLastError();
+template <class F>
+static void set_lds(F* k, size_t b, hipError_t& e) {
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
 }
 
-// Raise the dynamic-LDS limit of every operator kernel (gfx950 has 160 KB per CU).
-hipError_t op_kernels_set_lds(size_t xfft, size_t rows_fwd, size_t rows_adj) {
+// Allow every operator kernel the dynamic LDS a plan may request (the
+// actual amount is given per launch; occupancy follows the launch value).
+hipError_t op_kernels_init(size_t max_lds) {
   hipError_t e = hipSuccess;
-#define SETA(K, B) \
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(K), hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B))
-  SETA(k_xfft_fwd, xfft);
-  SETA(k_xfft_inv, xfft);
-  SETA(k_rows_fwd_fin, rows_fwd);
-  SETA(k_rows_fwd<1>, rows_fwd); SETA(k_rows_fwd<2>, rows_fwd); SETA(k_rows_fwd<3>, rows_fwd);
-  SETA(k_rows_fwd<4>, rows_fwd); SETA(k_rows_fwd<5>, rows_fwd); SETA(k_rows_fwd<6>, rows_fwd);
-  SETA(k_rows_fwd<7>, rows_fwd); SETA(k_rows_fwd<8>, rows_fwd);
-  SETA(k_rows_adj<1>, rows_adj); SETA(k_rows_adj<2>, rows_adj); SETA(k_rows_adj<3>, rows_adj);
-  SETA(k_rows_adj<4>, rows_adj); SETA(k_rows_adj<5>, rows_adj); SETA(k_rows_adj<6>, rows_adj);
-  SETA(k_rows_adj<7>, rows_adj); SETA(k_rows_adj<8>, rows_adj);
-#undef SETA
+#define X_(S) set_lds(k_xfft_fwd<S>, max_lds, e); set_lds(k_xfft_inv<S>, max_lds, e);
+  ASHRT_X_SIZES(X_)
+#undef X_
+  set_lds(k_xfft_fwd<0>, max_lds, e);
+  set_lds(k_xfft_inv<0>, max_lds, e);
+#define R_(S) set_lds(k_rows_fwd<S, 4>, max_lds, e); set_lds(k_rows_adj<S, 4>, max_lds, e); set_lds(k_rows_fwd_fin<S>, max_lds, e);
+  ASHRT_ROW_SIZES(R_)
+#undef R_
+  set_lds(k_rows_fwd<0, 0>, max_lds, e);
+  set_lds(k_rows_adj<0, 0>, max_lds, e);
+  set_lds(k_rows_fwd_fin<0>, max_lds, e);
   return e;
+}
+
+hipError_t launch_xfft_fwd(int key, const XfwdArgs& a, size_t lds, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  switch (key) {
+#define L_(S)                                                                               \
+  case S:                                                                                   \
+    hipLaunchKernelGGL(k_xfft_fwd<S>, dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    break;
+    ASHRT_X_SIZES(L_)
+#undef L_
+    default:
+      hipLaunchKernelGGL(k_xfft_fwd<0>, dim3(a.nitems), dim3(kThreads), lds, s, a);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_xfft_inv(int key, const XinvArgs& a, size_t lds, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  switch (key) {
+#define L_(S)                                                                               \
+  case S:                                                                                   \
+    hipLaunchKernelGGL(k_xfft_inv<S>, dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    break;
+    ASHRT_X_SIZES(L_)
+#undef L_
+    default:
+      hipLaunchKernelGGL(k_xfft_inv<0>, dim3(a.nitems), dim3(kThreads), lds, s, a);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_rows_fwd(int key, const RowsArgs& a, size_t lds, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  switch (key) {
+#define L_(S)                                                                                  \
+  case S:                                                                                      \
+    hipLaunchKernelGGL((k_rows_fwd<S, 4>), dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    break;
+    ASHRT_ROW_SIZES(L_)
+#undef L_
+    default:
+      hipLaunchKernelGGL((k_rows_fwd<0, 0>), dim3(a.nitems), dim3(kThreads), lds, s, a);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_rows_fwd_fin(int key, const RowsArgs& a, size_t lds, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  switch (key) {
+#define L_(S)                                                                               \
+  case S:                                                                                   \
+    hipLaunchKernelGGL(k_rows_fwd_fin<S>, dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    break;
+    ASHRT_ROW_SIZES(L_)
+#undef L_
+    default:
+      hipLaunchKernelGGL(k_rows_fwd_fin<0>, dim3(a.nitems), dim3(kThreads), lds, s, a);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_rows_adj(int key, const RowsArgs& a, size_t lds, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  switch (key) {
+#define L_(S)                                                                                  \
+  case S:                                                                                      \
+    hipLaunchKernelGGL((k_rows_adj<S, 4>), dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    break;
+    ASHRT_ROW_SIZES(L_)
+#undef L_
+    default:
+      hipLaunchKernelGGL((k_rows_adj<0, 0>), dim3(a.nitems), dim3(kThreads), lds, s, a);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace ashrt

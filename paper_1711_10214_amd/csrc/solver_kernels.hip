@@ -6,35 +6,10 @@
 // All kernels take per-gather work lists so one launch serves a whole batch.
 // Reductions are deterministic: each work item writes one partial, and the
 // partials of a gather are summed in a fixed tree order.
+#include "block_reduce.h"
 #include "kernels.h"
 
 namespace ashrt {
-
-// ------------------------------------------------------------ block reductions
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
-  }
-  __syncthreads();
-  return r;  // valid in thread 0
-}
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < kThreads / 64; ++i) r = fmax(r, sh[i]);
-  }
-  __syncthreads();
-  return r;
-}
 
 // ------------------------------------------------------------ partial reductions
 
@@ -47,7 +22,20 @@ __global__ __launch_bounds__(kThreads) void k_reduce_part(RedArgs A) {
     const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     double a = 0.0, b = 0.0;
     const double eps = A.sc ? A.sc[w.g * kNScal + SC_EPS_R] : 0.0;
-    for (long long i = threadIdx.x; i < w.len; i += kThreads) {
+    long long i0 = threadIdx.x;
+    if ((A.op == RED_SUMSQ || A.op == RED_ABSMAX) && ((w.start | w.len) & 3) == 0) {
+      const float4* x4 = reinterpret_cast<const float4*>(A.x + w.start);
+      for (long long i = threadIdx.x; i < (w.len >> 2); i += kThreads) {
+        const float4 v = x4[i];
+        if (A.op == RED_SUMSQ) {
+          a += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        } else {
+          a = fmax(a, (double)fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+      }
+      i0 = w.len;  // done
+    }
+    for (long long i = i0; i < w.len; i += kThreads) {
       const long long o = w.start + i;
       const double v = (double)A.x[o];
       if (A.op == RED_SUMSQ) {
@@ -137,7 +125,33 @@ __global__ __launch_bounds__(kThreads) void k_elementwise(EwArgs A) {
     if (A.op == EW_AXPY || A.op == EW_XPBY || A.op == EW_WR_UPDATE || A.op == EW_WM_UPDATE)
       c = (float)A.sc[w.g * kNScal + A.coef];
     const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
-    for (long long i = threadIdx.x; i < w.len; i += kThreads) {
+    long long i0 = threadIdx.x;
+    if ((A.op <= EW_FILL) && ((w.start | w.len) & 3) == 0) {
+      float4* y4 = reinterpret_cast<float4*>(A.y + w.start);
+      const float4* x4 = reinterpret_cast<const float4*>(A.x + w.start);
+      const float4* z4 = reinterpret_cast<const float4*>(A.z + w.start);
+      const float sc_ = A.sign * c;
+      for (long long i = threadIdx.x; i < (w.len >> 2); i += kThreads) {
+        float4 r;
+        if (A.op == EW_AXPY) {
+          const float4 x = x4[i], y = y4[i];
+          r = make_float4(fmaf(sc_, x.x, y.x), fmaf(sc_, x.y, y.y), fmaf(sc_, x.z, y.z), fmaf(sc_, x.w, y.w));
+        } else if (A.op == EW_XPBY) {
+          const float4 x = x4[i], y = y4[i];
+          r = make_float4(fmaf(c, y.x, x.x), fmaf(c, y.y, x.y), fmaf(c, y.z, x.z), fmaf(c, y.w, x.w));
+        } else if (A.op == EW_MUL) {
+          const float4 x = x4[i], z = z4[i];
+          r = make_float4(x.x * z.x, x.y * z.y, x.z * z.z, x.w * z.w);
+        } else if (A.op == EW_COPY) {
+          r = x4[i];
+        } else {
+          r = make_float4(A.value, A.value, A.value, A.value);
+        }
+        y4[i] = r;
+      }
+      i0 = w.len;
+    }
+    for (long long i = i0; i < w.len; i += kThreads) {
       const long long o = w.start + i;
       switch (A.op) {
         case EW_AXPY: A.y[o] = fmaf(A.sign * c, A.x[o], A.y[o]); break;
@@ -178,30 +192,6 @@ __global__ void k_scalar(ScalArgs A) {
   if (g >= A.ngather) return;
   double* s = A.sc + g * kNScal;
   switch (A.step) {
-    case ST_CG_RESET:
-      s[SC_DONE] = 0.0;
-      s[SC_NINNER] = 0.0;
-      s[SC_GAMMA] = s[SC_GAMMA_NEW];
-      break;
-    case ST_CG_ALPHA: {
-      const double gm = s[SC_GAMMA], dl = s[SC_DELTA];
-      if (s[SC_DONE] != 0.0 || gm == 0.0 || dl == 0.0 || !isfinite(gm) || !isfinite(dl)) {
-        s[SC_DONE] = 1.0;
-        s[SC_ALPHA] = 0.0;
-      } else {
-        s[SC_ALPHA] = gm / dl;
-        s[SC_NINNER] += 1.0;
-      }
-      break;
-    }
-    case ST_CG_BETA:
-      if (s[SC_DONE] != 0.0) {
-        s[SC_BETA] = 0.0;
-      } else {
-        s[SC_BETA] = s[SC_GAMMA_NEW] / s[SC_GAMMA];
-        s[SC_GAMMA] = s[SC_GAMMA_NEW];
-      }
-      break;
     case ST_EPS_M:
       s[SC_EPS_M] = A.b_m * s[SC_MMAX] / 100.0;
       if (A.rep) A.rep[g].eps_m[A.outer] = s[SC_EPS_M];
@@ -355,6 +345,77 @@ __global__ __launch_bounds__(kThreads) void k_count_live(const GatherDev* gd, in
   if (threadIdx.x == 0) sc[g * kNScal + SC_NLIVE] = r * (double)G.nt;
 }
 
+// CG initialisation / update over model-vector items (see CgArgs).
+__global__ __launch_bounds__(kThreads) void k_cg(CgArgs A) {
+  __shared__ float s_ab[2];
+  __shared__ double sh[kThreads / 64];
+  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    const VecItem w = A.items[it];
+    const GatherDev G = A.gd[w.g];
+    double part = 0.0;
+    for (int i = G.xm_lo + (int)threadIdx.x; i < G.xm_hi; i += kThreads) part += A.part_gamma[i];
+    const double gsum = block_sum(part, sh);
+    if (threadIdx.x == 0) {
+      double* sc = A.sc + (long long)w.g * kNScal;
+      const double gnew = gsum;
+      if (A.init) {
+        if (it == G.mit_lo) {
+          sc[SC_GAMMA0] = gnew;
+          sc[SC_DONE] = 0.0;
+          sc[SC_NINNER] = 0.0;
+        }
+        s_ab[0] = 0.f;
+        s_ab[1] = 0.f;
+      } else {
+        const bool done = sc[SC_DONE] != 0.0;
+        const double gold = sc[SC_GAMMA0 + A.par];
+        const double beta = (done || gold == 0.0) ? 0.0 : gnew / gold;
+        s_ab[0] = done ? 0.f : (float)sc[SC_ALPHA];
+        s_ab[1] = (float)beta;
+        if (it == G.mit_lo) {
+          sc[SC_GAMMA0 + (A.par ^ 1)] = gnew;
+          sc[SC_BETA] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const float alpha = s_ab[0], beta = s_ab[1];
+    float* __restrict__ u = A.u + w.start;
+    float* __restrict__ p = A.pdir + w.start;
+    const float* __restrict__ g = A.g + w.start;
+    if (((w.start | w.len) & 3) == 0) {
+      float4* u4 = reinterpret_cast<float4*>(u);
+      float4* p4 = reinterpret_cast<float4*>(p);
+      const float4* g4 = reinterpret_cast<const float4*>(g);
+      for (long long i = threadIdx.x; i < (w.len >> 2); i += kThreads) {
+        const float4 gv = g4[i];
+        if (A.init) {
+          p4[i] = gv;
+        } else {
+          const float4 pv = p4[i];
+          float4 uv = u4[i];
+          uv = make_float4(fmaf(alpha, pv.x, uv.x), fmaf(alpha, pv.y, uv.y), fmaf(alpha, pv.z, uv.z),
+                           fmaf(alpha, pv.w, uv.w));
+          u4[i] = uv;
+          p4[i] = make_float4(fmaf(beta, pv.x, gv.x), fmaf(beta, pv.y, gv.y), fmaf(beta, pv.z, gv.z),
+                              fmaf(beta, pv.w, gv.w));
+        }
+      }
+    } else {
+      for (long long i = threadIdx.x; i < w.len; i += kThreads) {
+        if (A.init) {
+          p[i] = g[i];
+        } else {
+          const float pv = p[i];
+          u[i] = fmaf(alpha, pv, u[i]);
+          p[i] = fmaf(beta, pv, g[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Clear n 32-bit words (a fill kernel rather than a memset, so the call can
 // sit inside a captured graph).
 __global__ void k_zero_words(unsigned* p, long long n) {
@@ -388,6 +449,11 @@ hipError_t launch_zero_words(void* p, long long n, hipStream_t s) {
   long long blocks = (n + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(kThreads), 0, s, (unsigned*)p, n);
+  return hipGetLastError();
+}
+hipError_t launch_cg(const CgArgs& a, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg, dim3(grid_of(a.nitems)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_count_live(const GatherDev* gd, int ngather, const uint8_t* tmask, double* sc,
