@@ -173,7 +173,7 @@ extern "C" int ashrt_abi_version(void) { return ASHRT_ABI_VERSION; }
 // ------------------------------------------------------------ plans
 struct GatherHost {
   Resolved z;
-  int nrows, tileT, ntiles, nchunk;
+  int nrows, tileT, ntiles, tileTd, ntilesd, nchunk;
   std::vector<PanelDev> panels;
   std::vector<float> wav;
   long long d_off, m_off, mask_off, X_off, H_off, Dp_off;
@@ -262,6 +262,11 @@ static int build_gather(const ashrt_desc* d, GatherHost* gh) {
   T = std::max(2, T & ~1);
   gh->tileT = T;
   gh->ntiles = (z.nt + T - 1) / T;
+  // the data transform is one panel: narrower tiles give it ~256 workgroups
+  int Td = 2 * ((z.nt + 511) / 512);
+  Td = std::max(2, std::min(T, Td));
+  gh->tileTd = Td;
+  gh->ntilesd = (z.nt + Td - 1) / Td;
   gh->panels.resize(z.P);
   const double bin = (double)z.ntp * d->dt / ((double)z.nxp * d->dx);
   for (int p = 0; p < z.P; ++p) {
@@ -423,6 +428,8 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
     }
     G.tileT = gh.tileT;
     G.ntiles = gh.ntiles;
+    G.tileTd = gh.tileTd;
+    G.ntilesd = gh.ntilesd;
     G.nchunk = gh.nchunk;
     G.d_off = gh.d_off;
     G.m_off = gh.m_off;
@@ -440,15 +447,22 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
     G.dit_hi = (int)vd.size();
   }
   // LDS bytes of each kernel family for one gather
+  // (padded FFT buffers: fft_padlen slots; x columns at an odd slot stride)
+  auto xstride = [](const GatherHost& gh) { return (size_t)(fft_padlen(gh.z.nxp) | 1); };
   auto lds_x_of = [&](const GatherHost& gh) {
-    return (size_t)gh.z.nxp * 8 + (size_t)(gh.tileT / 2) * (gh.z.nxp + 1) * 8;
+    return (size_t)gh.z.nxp * 8 + (size_t)(gh.tileT / 2) * xstride(gh) * 8;
+  };
+  auto lds_xd_of = [&](const GatherHost& gh) {
+    return (size_t)gh.z.nxp * 8 + (size_t)(gh.tileTd / 2) * xstride(gh) * 8;
   };
   auto nband_of = [](const GatherHost& gh) { return (size_t)(gh.z.jhi - gh.z.jlo + 1); };
-  auto lds_rf_of = [&](const GatherHost& gh) { return (size_t)gh.z.ntp * 16 + nband_of(gh) * 16; };
-  auto lds_fin_of = [&](const GatherHost& gh) { return (size_t)gh.z.ntp * 16; };
+  auto plen_of = [](const GatherHost& gh) { return (size_t)fft_padlen(gh.z.ntp); };
+  auto lds_rf_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + plen_of(gh)) * 8 + nband_of(gh) * 16; };
+  auto lds_fin_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + plen_of(gh)) * 8; };
   auto lds_ra_of = [&](const GatherHost& gh) {
     const size_t nb = nband_of(gh);
-    return (size_t)gh.z.ntp * 24 + (nb + (nb & 1)) * 8 + nb * 20;
+    return ((size_t)gh.z.ntp + 2 * plen_of(gh) + (plen_of(gh) & 1)) * 8 + nb * 16 +
+           (size_t)(gh.z.kmax + 2 * gh.z.R + 1) * 4;
   };
   // work lists grouped by kernel instantiation; a gather's items stay contiguous
   auto build_segments = [&](const std::vector<int>& keys, std::vector<PlanImpl::Seg>& segs,
@@ -473,9 +487,9 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   }, lds_x_of);
   build_segments(key_x, P.s_xd, xd, [&](int gi) {
     gd[gi].xd_lo = (int)xd.size();
-    for (int t = 0; t < P.g[gi].ntiles; ++t) xd.push_back(WorkItem{gi, 0, t, 0});
+    for (int t = 0; t < P.g[gi].ntilesd; ++t) xd.push_back(WorkItem{gi, 0, t, 0});
     gd[gi].xd_hi = (int)xd.size();
-  }, lds_x_of);
+  }, lds_xd_of);
   build_segments(key_t, P.s_rf, rf, [&](int gi) {
     for (int r = 0; r < P.g[gi].nrows; ++r)
       for (int c = 0; c < P.g[gi].nchunk; ++c) rf.push_back(WorkItem{gi, r, c, 0});

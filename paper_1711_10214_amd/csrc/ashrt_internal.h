@@ -11,7 +11,8 @@
 
 namespace ashrt {
 
-constexpr int kThreads = 256;          // threads per workgroup of every kernel
+constexpr int kThreads = 256;          // threads per workgroup (all kernels but the row passes)
+constexpr int kRowThreads = 512;       // threads per workgroup of the forward/adjoint row passes
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
 constexpr int kXfftMaxTotal = 8192;    // complex points of one x-FFT tile in LDS
@@ -34,8 +35,10 @@ struct GatherDev {
   int twp_t_off;    // float2 offset of the ntp pass table (compile-time FFT lengths)
   int twp_x_off;    // float2 offset of the nxp pass table
   int wav_off;      // float offset of the W_j table, -1 = none
-  int tileT;        // time columns per x-FFT tile (even)
+  int tileT;        // time columns per x-FFT tile of a model panel (even)
   int ntiles;       // ceil(nt / tileT)
+  int tileTd;       // time columns per x-FFT tile of the data (even, smaller: more workgroups)
+  int ntilesd;      // ceil(nt / tileTd)
   int nchunk;       // panel chunks of the forward row pass
   int mit_lo, mit_hi;   // model-vector work items of this gather
   int dit_lo, dit_hi;   // data-vector work items of this gather

@@ -5,6 +5,9 @@
 // with radix R and span Ns (product of the earlier radices) maps
 //   v_r = x[j + r N/R] * w^(r (j mod Ns)),  w = exp(-+2 pi i / (Ns R)),
 //   y[(j div Ns) Ns R + (j mod Ns) + r Ns] = DFT_R(v)_r .
+// Elements live at padded LDS positions fft_pad(i) = i + i/16 (one 8-byte
+// gap every 128 bytes), which makes the strided writes of the first passes
+// hit distinct banks; a padded transform occupies fft_padlen(N) slots.
 // Its twiddles w^(r jm), r = 1..R-1, jm = 0..Ns-1, are stored [r-1][jm]
 // (consecutive jm for a fixed r, so a wave reads consecutive LDS words) at
 // FftPlan<N>::twoff(i) in a per-length "pass table" built in FP64 on the
@@ -20,6 +23,17 @@
 namespace ashrt {
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+__host__ __device__ constexpr int fft_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int fft_padlen(int n) { return n + (n >> 4); }
+
+// Index of logical element i of a buffer written by an FFT of compile-time
+// length N (padded) or by the generic runtime FFT (N == 0, unpadded).
+template <int N>
+__device__ __forceinline__ int px(int i) {
+  if constexpr (N > 0) return fft_pad(i);
+  else return i;
+}
 
 template <int N>
 struct FftPlan {
@@ -97,30 +111,31 @@ __device__ __forceinline__ void dft_r(float2 (&v)[R]) {
   else butterfly<R, INV>(v);
 }
 
-// One pass of a batch of nb transforms (nb * N <= NBN) at buf + b*bstride.
-template <int N, int PASS, int NBN, bool INV>
+// One pass of a batch of nb transforms (nb * N <= NBN) at buf + b*bstride,
+// run by a workgroup of NT threads.
+template <int N, int PASS, int NBN, bool INV, int NT = kThreads>
 __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const float2* twp) {
   using P = FftPlan<N>;
   constexpr int R = P::radix(PASS);
   constexpr int Ns = P::ns(PASS);
   constexpr int B = N / R;
   constexpr int TW = P::twoff(PASS);
-  constexpr int MAXB = (NBN / R + kThreads - 1) / kThreads;
+  constexpr int MAXB = (NBN / R + NT - 1) / NT;
   float2 v[MAXB][R];
-  int dst[MAXB];
+  int dst[MAXB], bq[MAXB];
   const int total = B * nb;
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int id = (int)threadIdx.x + i * kThreads;
+    const int id = (int)threadIdx.x + i * NT;
     dst[i] = -1;
     if (id < total) {
       const int b = id / B;
       const int j = id - b * B;
       const int jq = j / Ns;
       const int jm = j - jq * Ns;
-      const float2* src = buf + b * bstride + j;
+      const float2* src = buf + b * bstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[r * B];
+      for (int r = 0; r < R; ++r) v[i][r] = src[fft_pad(j + r * B)];
       if constexpr (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -130,7 +145,8 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
         }
       }
       dft_r<R, INV>(v[i]);
-      dst[i] = b * bstride + jq * Ns * R + jm;
+      dst[i] = b * bstride;
+      bq[i] = jq * Ns * R + jm;
     }
   }
   __syncthreads();
@@ -138,24 +154,24 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
   for (int i = 0; i < MAXB; ++i) {
     if (dst[i] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-template <int N, int PASS, int NBN, bool INV>
+template <int N, int PASS, int NBN, bool INV, int NT>
 __device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, const float2* twp) {
   if constexpr (PASS < FftPlan<N>::npass) {
-    tpl_pass<N, PASS, NBN, INV>(buf, nb, bstride, twp);
-    tpl_passes<N, PASS + 1, NBN, INV>(buf, nb, bstride, twp);
+    tpl_pass<N, PASS, NBN, INV, NT>(buf, nb, bstride, twp);
+    tpl_passes<N, PASS + 1, NBN, INV, NT>(buf, nb, bstride, twp);
   }
 }
 
 // Full transform(s); the caller places a barrier after filling buf.
-template <int N, int NBN, bool INV>
+template <int N, int NBN, bool INV, int NT = kThreads>
 __device__ __forceinline__ void fft_tpl(float2* buf, int nb, int bstride, const float2* twp) {
-  tpl_passes<N, 0, NBN, INV>(buf, nb, bstride, twp);
+  tpl_passes<N, 0, NBN, INV, NT>(buf, nb, bstride, twp);
 }
 
 }  // namespace ashrt

@@ -160,14 +160,14 @@ __device__ __forceinline__ float2 bin_factor(const GatherDev& G, const PanelDev&
 // ------------------------------------------------------------ FFT dispatch
 // Copy the twiddles an FFT of length n needs into LDS (pass table for the
 // compile-time lengths, plain table otherwise).  No barrier.
-template <int N>
+template <int N, int NT = kThreads>
 __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ tw, int plain_off,
                                                int pass_off, int n) {
   if constexpr (N > 0) {
     constexpr int ntw = FftPlan<N>::twsize();
-    for (int i = threadIdx.x; i < ntw; i += kThreads) dst[i] = tw[pass_off + i];
+    for (int i = threadIdx.x; i < ntw; i += NT) dst[i] = tw[pass_off + i];
   } else {
-    for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = tw[plain_off + i];
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = tw[plain_off + i];
   }
 }
 
@@ -222,10 +222,11 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     }
     const int p = w.a;
     const int nx = G.nx, nt = G.nt, nxp = G.nxp, nrows = G.nrows;
-    const int T = G.tileT, half = T >> 1, bs = nxp + 1;
+    const int T = A.is_model ? G.tileT : G.tileTd, half = T >> 1;
+    const int bs = ((NX > 0 ? fft_padlen(nxp) : nxp) | 1);  // odd slot stride between columns
     const int t0 = w.b * T;
     float2* twl = lds;          // x twiddles (at most nxp entries)
-    float2* buf = lds + nxp;    // T/2 packed column pairs, stride nxp + 1
+    float2* buf = lds + nxp;    // T/2 packed column pairs, odd slot stride bs
     stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
     const float* __restrict__ src = A.src + fbase;
@@ -267,12 +268,12 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
         a = 0.f;
         b = 0.f;
       }
-      buf[i * bs + x] = make_float2(a, b);
+      buf[i * bs + px<NX>(x)] = make_float2(a, b);
     }
     for (int idx = threadIdx.x; idx < (nxp - nx) * half; idx += kThreads) {
       const int xx = idx / half;
       const int i = idx - xx * half;
-      buf[i * bs + nx + xx] = make_float2(0.f, 0.f);
+      buf[i * bs + px<NX>(nx + xx)] = make_float2(0.f, 0.f);
     }
     __syncthreads();
     xfft_tile<NX, false>(buf, nxp, half, bs, twl);
@@ -286,11 +287,11 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       const float2* Z = buf + (c >> 1) * bs;
       float2 out;
       if (r == 0) {
-        const float2 z0 = Z[0], zn = Z[nrows];
+        const float2 z0 = Z[0], zn = Z[px<NX>(nrows)];
         out = (c & 1) ? make_float2(z0.y, zn.y) : make_float2(z0.x, zn.x);
       } else {
-        const float2 a = Z[r];
-        const float2 b = cconj(Z[nxp - r]);
+        const float2 a = Z[px<NX>(r)];
+        const float2 b = cconj(Z[px<NX>(nxp - r)]);
         out = (c & 1) ? make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x))
                       : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       }
@@ -310,7 +311,8 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const GatherDev G = A.gd[w.g];
     const int p = w.a;
     const int nx = G.nx, nt = G.nt, nxp = G.nxp, nrows = G.nrows;
-    const int T = G.tileT, half = T >> 1, bs = nxp + 1;
+    const int T = A.is_model ? G.tileT : G.tileTd, half = T >> 1;
+    const int bs = ((NX > 0 ? fft_padlen(nxp) : nxp) | 1);  // odd slot stride between columns
     const int t0 = w.b * T;
     const float2* __restrict__ src = A.src + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
     float2* twl = lds;
@@ -327,10 +329,10 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       float2* Z = buf + i * bs;
       if (l == 0) {
         Z[0] = make_float2(h1.x, h2.x);
-        Z[nrows] = make_float2(h1.y, h2.y);
+        Z[px<NX>(nrows)] = make_float2(h1.y, h2.y);
       } else {
-        Z[l] = make_float2(h1.x - h2.y, h1.y + h2.x);
-        Z[nxp - l] = make_float2(h1.x + h2.y, -h1.y + h2.x);
+        Z[px<NX>(l)] = make_float2(h1.x - h2.y, h1.y + h2.x);
+        Z[px<NX>(nxp - l)] = make_float2(h1.x + h2.y, -h1.y + h2.x);
       }
     }
     __syncthreads();
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       const int c = idx - x * T;
       const int t = t0 + c;
       if (t >= nt) continue;
-      const float2 z = buf[(c >> 1) * bs + x];
+      const float2 z = buf[(c >> 1) * bs + px<NX>(x)];
       float v = ((c & 1) ? z.y : z.x) * inv;
       const long long o = fbase + (long long)x * nt + t;
       if (A.raw_out) A.raw_out[o] = v;
@@ -368,36 +370,36 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
 // forward time FFT, and for row 0 separate the packed kx = 0 / Nyquist
 // spectra: slot k gets the kx = 0 spectrum, slot ntp-k the conjugate of the
 // Nyquist one, so that both rows read "up = buf[k], lo = conj(buf[ntp-k])".
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restrict__ src, int r, int nt,
                                              int ntp, const float2* twl) {
-  for (int t = threadIdx.x; t < ntp; t += kThreads) buf[t] = (t < nt) ? src[t] : make_float2(0.f, 0.f);
+  for (int t = threadIdx.x; t < ntp; t += NT) buf[px<N>(t)] = (t < nt) ? src[t] : make_float2(0.f, 0.f);
   __syncthreads();
-  if constexpr (N > 0) fft_tpl<N, N, false>(buf, 1, N, twl);
-  else fft_lds<kThreads, kRowMaxN, false>(buf, ntp, 1, ntp, twl);
+  if constexpr (N > 0) fft_tpl<N, N, false, NT>(buf, 1, fft_padlen(N), twl);
+  else fft_lds<NT, kRowMaxN, false>(buf, ntp, 1, ntp, twl);
   if (r == 0) {
-    for (int k = 1 + threadIdx.x; k < ntp / 2; k += kThreads) {
-      const float2 a = buf[k];
-      const float2 b = cconj(buf[ntp - k]);
+    for (int k = 1 + threadIdx.x; k < ntp / 2; k += NT) {
+      const float2 a = buf[px<N>(k)];
+      const float2 b = cconj(buf[px<N>(ntp - k)]);
       const float2 m0 = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       const float2 m1 = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
-      buf[k] = m0;
-      buf[ntp - k] = cconj(m1);
+      buf[px<N>(k)] = m0;
+      buf[px<N>(ntp - k)] = cconj(m1);
     }
     __syncthreads();
   }
 }
 
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void row_inverse(float2* buf, int ntp, const float2* twl) {
-  if constexpr (N > 0) fft_tpl<N, N, true>(buf, 1, N, twl);
-  else fft_lds<kThreads, kRowMaxN, true>(buf, ntp, 1, ntp, twl);
+  if constexpr (N > 0) fft_tpl<N, N, true, NT>(buf, 1, fft_padlen(N), twl);
+  else fft_lds<NT, kRowMaxN, true>(buf, ntp, 1, ntp, twl);
 }
 
 // ------------------------------------------------------------ forward rows
 //
 // LDS: twiddles [ntp], row spectrum [ntp], accumulators D(+l), D(-l) [2 nband].
-template <int N, int RC>
+template <int N, int RC, int NT>
 __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
                                               float2* lds, const float* ctab, const float* stab) {
   const int R = RC > 0 ? RC : A.R;
@@ -407,22 +409,23 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
   const int p0 = (int)((long long)chunk * P / G.nchunk);
   const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
   const int hmax = ntp / 2 - 1;
+  const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
   float2* buf = lds + ntp;
-  float2* acc = lds + 2 * ntp;
-  stage_twiddles<N>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
-  for (int i = threadIdx.x; i < 2 * nband; i += kThreads) acc[i] = make_float2(0.f, 0.f);
+  float2* acc = buf + plen;
+  stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
+  for (int i = threadIdx.x; i < 2 * nband; i += NT) acc[i] = make_float2(0.f, 0.f);
   const int lu = (r == 0) ? 0 : r;
   const int ll = (r == 0) ? nrows : r;
   const double lup2 = (double)lu * (double)lu;
   const double llo2 = (double)ll * (double)ll;
 
   for (int p = p0; p < p1; ++p) {
-    row_spectrum<N>(buf, A.X + G.X_off + ((long long)p * nrows + r) * nt, r, nt, ntp, twl);
+    row_spectrum<N, NT>(buf, A.X + G.X_off + ((long long)p * nrows + r) * nt, r, nt, ntp, twl);
     const PanelDev PD = A.panels[G.panel_off + p];
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
 #pragma unroll 1
-    for (int j = jlo + (int)threadIdx.x; j <= jhi; j += kThreads) {
+    for (int j = jlo + (int)threadIdx.x; j <= jhi; j += NT) {
       const Taps tu = taps_of<RC>(j, PD.c2 * lup2, R);
       float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
       if (r != 0) {
@@ -430,11 +433,12 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 #pragma unroll
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tu.k0 + t;
-            if (k >= 1 && k <= hmax) {
-              const float wt = tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]);
-              au = cfma(wt, buf[k], au);
-              al = cfma(wt, cconj(buf[ntp - k]), al);
-            }
+            const bool ok = (k >= 1) && (k <= hmax);
+            const int kc = ok ? k : 1;
+            float wt = tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]);
+            wt = ok ? wt : 0.f;
+            au = cfma(wt, buf[px<N>(kc)], au);
+            al = cfma(wt, cconj(buf[px<N>(ntp - kc)]), al);
           }
         }
       } else {
@@ -443,7 +447,8 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 #pragma unroll
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tu.k0 + t;
-            if (k >= 1 && k <= hmax) au = cfma(tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]), buf[k], au);
+            if (k >= 1 && k <= hmax)
+              au = cfma(tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]), buf[px<N>(k)], au);
           }
         }
         if (tl.k0 != kNoTap) {
@@ -451,7 +456,7 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tl.k0 + t;
             if (k >= 1 && k <= hmax)
-              al = cfma(tap_weight(tl.trig, t, ctab[t + R - 1], stab[t + R - 1]), cconj(buf[ntp - k]), al);
+              al = cfma(tap_weight(tl.trig, t, ctab[t + R - 1], stab[t + R - 1]), cconj(buf[px<N>(ntp - k)]), al);
           }
         }
       }
@@ -469,12 +474,12 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
     __syncthreads();
   }
   float2* __restrict__ dp = A.Dp + G.Dp_off + ((long long)chunk * nrows + r) * 2 * nband;
-  for (int i = threadIdx.x; i < 2 * nband; i += kThreads) dp[i] = acc[i];
+  for (int i = threadIdx.x; i < 2 * nband; i += NT) dp[i] = acc[i];
   __syncthreads();
 }
 
 template <int N, int RC>
-__global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
+__global__ __launch_bounds__(kRowThreads) void k_rows_fwd(RowsArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    rows_fwd_item<N, RC>(A, w, G, lds, ctab, stab);
+    rows_fwd_item<N, RC, kRowThreads>(A, w, G, lds, ctab, stab);
   }
 }
 
@@ -490,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(RowsArgs A) {
 // spectrum (rows >= 1: Q[j] = D(+l,j), Q[ntp-j] = conj D(-l,j); row 0:
 // Q[j] = D(0,j) + i D(N,j), Q[ntp-j] = conj D(0,j) + i conj D(N,j)), inverse
 // time FFT, scale 1/ntp, keep t < nt.
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
                                               float2* lds) {
   const int r = w.a;
@@ -498,8 +503,8 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
   const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
   float2* twl = lds;
   float2* buf = lds + ntp;
-  stage_twiddles<N>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
-  for (int k = threadIdx.x; k < ntp; k += kThreads) {
+  stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
+  for (int k = threadIdx.x; k < ntp; k += NT) {
     float2 v = make_float2(0.f, 0.f);
     const int j = (k >= jlo && k <= jhi) ? k : ((ntp - k >= jlo && ntp - k <= jhi) ? ntp - k : -1);
     if (j >= 0) {
@@ -515,13 +520,13 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
         v = (r == 0) ? make_float2(su.x + sl.y, -su.y + sl.x) : cconj(sl);
       }
     }
-    buf[k] = v;
+    buf[px<N>(k)] = v;
   }
   __syncthreads();
-  row_inverse<N>(buf, ntp, twl);
+  row_inverse<N, NT>(buf, ntp, twl);
   const float inv = 1.0f / (float)ntp;
   float2* __restrict__ dst = A.H + G.H_off + (long long)r * nt;
-  for (int t = threadIdx.x; t < nt; t += kThreads) dst[t] = cscale(buf[t], inv);
+  for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(buf[px<N>(t)], inv);
   __syncthreads();
 }
 
@@ -531,70 +536,84 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd_fin(RowsArgs A) {
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    rows_fin_item<N>(A, w, G, lds);
+    rows_fin_item<N, kThreads>(A, w, G, lds);
   }
 }
 
 // ------------------------------------------------------------ adjoint rows
 //
-// LDS: twiddles [ntp], data row spectrum bufD [ntp], model spectrum bufM
-// [ntp], and per band bin: the data-bin factor c_j (float2, only when a
-// panel has a ramp or a wavelet weight), tap trig (float4) and k0 (int).
-template <int N, int RC>
+// The transpose of the forward gather, itself as a gather: for model bin k
+// and tap t the only data bin that reaches it is the j with floor(u_j) =
+// k - t, because floor(u_j) is strictly increasing in j inside the cone
+// (u_{j+1} - u_j = (2j+1) / (u_{j+1} + u_j) >= 1).  Phase 1 evaluates the
+// taps of every band bin once and records inv[floor(u_j)] = j; phase 2 sums
+// the 2R (j, t) pairs of each k with the same weights the forward uses.
+//
+// LDS: twiddles [ntp], data row spectrum bufD and model spectrum bufM
+// (padded lengths), per band bin the tap trig (float4), and inv over the
+// model bins (offset R so k - t never goes negative).
+template <int N, int RC, int NT>
 __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
                                               float2* lds, const float* ctab, const float* stab) {
+  constexpr int RT = RC > 0 ? RC : kMaxHalfWidth;  // tap-loop bound
   const int R = RC > 0 ? RC : A.R;
   const int r = w.a, chunk = w.b;
   const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows, P = G.npanel;
   const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
   const int kmax = G.kmax;
+  const int ninv = kmax + 2 * R + 1;
   const int p0 = (int)((long long)chunk * P / G.nchunk);
   const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
+  const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
   float2* bufD = lds + ntp;
-  float2* bufM = lds + 2 * ntp;
-  float2* tab_c = lds + 3 * ntp;
-  float4* tab_tr = reinterpret_cast<float4*>(tab_c + nband + (nband & 1));
-  int* tab_k0 = reinterpret_cast<int*>(tab_tr + nband);
-  stage_twiddles<N>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
+  float2* bufM = bufD + plen;
+  float4* tab_tr = reinterpret_cast<float4*>(bufM + plen + (plen & 1));
+  int* inv = reinterpret_cast<int*>(tab_tr + nband);
+  stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
 
-  row_spectrum<N>(bufD, A.H + G.H_off + (long long)r * nt, r, nt, ntp, twl);
+  row_spectrum<N, NT>(bufD, A.H + G.H_off + (long long)r * nt, r, nt, ntp, twl);
 
   const int npass = (r == 0) ? 2 : 1;
   for (int p = p0; p < p1; ++p) {
     const PanelDev PD = A.panels[G.panel_off + p];
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
-    for (int k = threadIdx.x; k < ntp; k += kThreads) bufM[k] = make_float2(0.f, 0.f);
+    for (int k = threadIdx.x; k < plen; k += NT) bufM[k] = make_float2(0.f, 0.f);
     for (int pass = 0; pass < npass; ++pass) {
       const int l = (r == 0) ? (pass == 0 ? 0 : nrows) : r;
       const double a2 = PD.c2 * (double)l * (double)l;
-      // phase 1: taps (and the ramp factor) per band bin
-      for (int j = jlo + threadIdx.x; j <= jhi; j += kThreads) {
+      for (int i = threadIdx.x; i < ninv; i += NT) inv[i] = -1;
+      __syncthreads();
+      // phase 1: taps of every band bin, and the inverse index of floor(u)
+      for (int j = jlo + threadIdx.x; j <= jhi; j += NT) {
         const Taps T = taps_of<RC>(j, a2, R);
-        tab_k0[j - jlo] = T.k0;
         tab_tr[j - jlo] = T.trig;
-        if (!plain) tab_c[j - jlo] = bin_factor(G, PD, A.tw, A.wav, j);
+        if (T.k0 != kNoTap) inv[R + T.k0] = j - jlo;
       }
       __syncthreads();
-      // phase 2: gather over the data bins whose taps reach model bin k
-      const float a2f = (float)a2;
+      // phase 2: model bin k gathers tap t from data bin inv[k - t]
 #pragma unroll 1
-      for (int k = 1 + (int)threadIdx.x; k <= kmax; k += kThreads) {
-        const float lo = (float)max(k - R, 0);
-        const float hi = (float)(k + R);
-        int ja = (int)ceilf(sqrtf(fmaf(lo, lo, a2f))) - 1;
-        int jb = (int)ceilf(sqrtf(fmaf(hi, hi, a2f))) + 1;
-        ja = max(ja, jlo);
-        jb = min(jb, jhi);
+      for (int k = 1 + (int)threadIdx.x; k <= kmax; k += NT) {
         float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
-        for (int j = ja; j <= jb; ++j) {
-          const int t = k - tab_k0[j - jlo];
-          if (t < -R + 1 || t > R) continue;
-          const float wgt = tap_weight(tab_tr[j - jlo], t, ctab[t + R - 1], stab[t + R - 1]);
-          float2 du = bufD[j];
-          float2 dl = cconj(bufD[ntp - j]);
+        // tap t = R - q reads inv[k + q]: one contiguous run per k, loaded
+        // up front; missing sources are clamped to bin 0 with weight 0 so
+        // every tap issues the same loads (no data-dependent branches)
+        int jrs[2 * RT];
+#pragma unroll
+        for (int q = 0; q < 2 * RT; ++q) jrs[q] = (RC > 0 || q < 2 * R) ? inv[k + q] : -1;
+#pragma unroll
+        for (int q = 0; q < 2 * RT; ++q) {
+          if (RC == 0 && q >= 2 * R) break;
+          const int t = R - q;
+          const int jr = jrs[q];
+          const int jc = jr < 0 ? 0 : jr;
+          const int j = jlo + jc;
+          float wgt = tap_weight(tab_tr[jc], t, ctab[t + R - 1], stab[t + R - 1]);
+          wgt = jr < 0 ? 0.f : wgt;
+          float2 du = bufD[px<N>(j)];
+          float2 dl = cconj(bufD[px<N>(ntp - j)]);
           if (!plain) {
-            const float2 c = tab_c[j - jlo];
+            const float2 c = bin_factor(G, PD, A.tw, A.wav, j);
             du = cmulconj(du, c);
             dl = cmulconj(dl, c);
           }
@@ -608,28 +627,28 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
         // model time spectrum: rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l);
         // row 0: Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
         if (r != 0) {
-          bufM[k] = au;
-          bufM[ntp - k] = cconj(al);
+          bufM[px<N>(k)] = au;
+          bufM[px<N>(ntp - k)] = cconj(al);
         } else if (pass == 0) {
-          bufM[k] = au;  // kept until pass 1 (same thread owns k)
+          bufM[px<N>(k)] = au;  // kept until pass 1 (same thread owns k)
         } else {
-          const float2 u = bufM[k];
-          bufM[k] = make_float2(u.x - al.y, u.y + al.x);
-          bufM[ntp - k] = make_float2(u.x + al.y, -u.y + al.x);
+          const float2 u = bufM[px<N>(k)];
+          bufM[px<N>(k)] = make_float2(u.x - al.y, u.y + al.x);
+          bufM[px<N>(ntp - k)] = make_float2(u.x + al.y, -u.y + al.x);
         }
       }
       __syncthreads();
     }
-    row_inverse<N>(bufM, ntp, twl);
-    const float inv = 1.0f / (float)ntp;
+    row_inverse<N, NT>(bufM, ntp, twl);
+    const float inv_n = 1.0f / (float)ntp;
     float2* __restrict__ dst = A.X + G.X_off + ((long long)p * nrows + r) * nt;
-    for (int t = threadIdx.x; t < nt; t += kThreads) dst[t] = cscale(bufM[t], inv);
+    for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(bufM[px<N>(t)], inv_n);
     __syncthreads();
   }
 }
 
 template <int N, int RC>
-__global__ __launch_bounds__(kThreads) void k_rows_adj(RowsArgs A) {
+__global__ __launch_bounds__(kRowThreads) void k_rows_adj(RowsArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
@@ -637,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_adj(RowsArgs A) {
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    rows_adj_item<N, RC>(A, w, G, lds, ctab, stab);
+    rows_adj_item<N, RC, kRowThreads>(A, w, G, lds, ctab, stab);
   }
 }
 
@@ -725,12 +744,12 @@ hipError_t launch_rows_fwd(int key, const RowsArgs& a, size_t lds, hipStream_t s
   switch (key) {
 #define L_(S)                                                                                  \
   case S:                                                                                      \
-    hipLaunchKernelGGL((k_rows_fwd<S, 4>), dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    hipLaunchKernelGGL((k_rows_fwd<S, 4>), dim3(a.nitems), dim3(kRowThreads), lds, s, a); \
     break;
     ASHRT_ROW_SIZES(L_)
 #undef L_
     default:
-      hipLaunchKernelGGL((k_rows_fwd<0, 0>), dim3(a.nitems), dim3(kThreads), lds, s, a);
+      hipLaunchKernelGGL((k_rows_fwd<0, 0>), dim3(a.nitems), dim3(kRowThreads), lds, s, a);
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -757,12 +776,12 @@ hipError_t launch_rows_adj(int key, const RowsArgs& a, size_t lds, hipStream_t s
   switch (key) {
 #define L_(S)                                                                                  \
   case S:                                                                                      \
-    hipLaunchKernelGGL((k_rows_adj<S, 4>), dim3(a.nitems), dim3(kThreads), lds, s, a); \
+    hipLaunchKernelGGL((k_rows_adj<S, 4>), dim3(a.nitems), dim3(kRowThreads), lds, s, a); \
     break;
     ASHRT_ROW_SIZES(L_)
 #undef L_
     default:
-      hipLaunchKernelGGL((k_rows_adj<0, 0>), dim3(a.nitems), dim3(kThreads), lds, s, a);
+      hipLaunchKernelGGL((k_rows_adj<0, 0>), dim3(a.nitems), dim3(kRowThreads), lds, s, a);
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
