@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define ASHRT_ABI_VERSION 1
+#define ASHRT_ABI_VERSION 2
 
 enum ashrt_status {
   ASHRT_OK = 0,
@@ -106,6 +106,10 @@ typedef struct irls_params {
   double tol;                  /* stop when the relative change of sum|r|^p < tol; 0 = fixed counts */
   double eps_floor_rel;        /* eps_r >= eps_floor_rel * max|d_live| (1e-6)                        */
   int32_t freeze_eps;          /* nonzero: eps_r computed once (after outer 1) and kept             */
+  int32_t cg_graph;            /* nonzero (default): CG iterations replayed two at a time from a
+                                  hipGraph captured on first use and cached in the plan per
+                                  (workspace, m, mask, q); 0 = launched one by one.  Results are
+                                  identical either way.  Ignored while kernel timing is enabled. */
 } irls_params;
 
 /* Per-solve report (host memory).  Entry k describes outer iteration k+1,
@@ -131,7 +135,7 @@ typedef struct ashrt_plan_info {
 typedef struct ashrt_plan ashrt_plan;
 
 /* Fill defaults: desc -> all zero except half_width 4; params -> p=1, q=2,
- * 10 x 20, b_r 1.345, b_m 1, tol 0, floor 1e-6. */
+ * 10 x 20, b_r 1.345, b_m 1, tol 0, floor 1e-6, cg_graph 1. */
 void ashrt_desc_default(ashrt_desc *desc);
 void irls_params_default(irls_params *params);
 

@@ -45,6 +45,7 @@ class IrlsParams(C.Structure):
         ("p", C.c_int32), ("q", C.c_int32), ("n_outer", C.c_int32), ("n_inner", C.c_int32),
         ("b_r", C.c_double), ("b_m", C.c_double), ("tol", C.c_double), ("eps_floor_rel", C.c_double),
         ("freeze_eps", C.c_int32),
+        ("cg_graph", C.c_int32),
     ]
 
 
@@ -68,6 +69,9 @@ class PlanInfo(C.Structure):
 
 
 _lib = None
+
+
+ABI_VERSION = 2  # struct layouts below match include/ashrt.h at this version
 
 
 def lib():
@@ -112,6 +116,8 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if L.ashrt_abi_version() != ABI_VERSION:
+        raise ImportError(f"libashrt.so has ABI {L.ashrt_abi_version()}, the binding expects {ABI_VERSION}; rebuild it")
     _lib = L
     return L
 

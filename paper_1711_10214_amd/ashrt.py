@@ -38,10 +38,12 @@ class Params:
     tol: float = 0.0
     eps_floor_rel: float = 1e-6
     freeze_eps: bool = False
+    cg_graph: bool = True
 
     def c(self):
         return L.IrlsParams(self.p, self.q, self.n_outer, self.n_inner, self.b_r, self.b_m,
-                            self.tol, self.eps_floor_rel, int(bool(self.freeze_eps)))
+                            self.tol, self.eps_floor_rel, int(bool(self.freeze_eps)),
+                            int(bool(self.cg_graph)))
 
 
 def report_dict(r: L.IrlsReport):
@@ -225,6 +227,13 @@ class BatchPlan:
         for g, a in enumerate(arrays):
             a = torch.as_tensor(a, dtype=torch.float32).reshape(-1)
             out[self.data_off[g]: self.data_off[g] + a.numel()] = a.to(self.device)
+        return out
+
+    def pack_model(self, arrays):
+        out = torch.zeros(self.model_total, dtype=torch.float32, device=self.device)
+        for g, a in enumerate(arrays):
+            a = torch.as_tensor(a, dtype=torch.float32).reshape(-1)
+            out[self.model_off[g]: self.model_off[g] + a.numel()] = a.to(self.device)
         return out
 
     def pack_mask(self, masks):

@@ -82,6 +82,7 @@ extern "C" void irls_params_default(irls_params* p) {
   p->tol = 0.0;
   p->eps_floor_rel = 1e-6;
   p->freeze_eps = 0;
+  p->cg_graph = 1;
 }
 
 struct Resolved {
@@ -209,6 +210,17 @@ struct PlanImpl {
   std::vector<Seg> s_xm, s_xd, s_rf, s_rfin, s_ra;
   VecItem *d_vm = nullptr, *d_vd = nullptr;
   int n_vm = 0, n_vd = 0;
+  // Executable graphs of a CG iteration pair, keyed by the buffers their
+  // launches read and write (everything else comes from the plan).
+  struct CgGraph {
+    const void* ws;
+    const float* m;
+    const uint8_t* mask;
+    int q;
+    hipGraphExec_t exec;
+  };
+  mutable std::mutex graph_mu;
+  mutable std::vector<CgGraph> graphs;
   long long tot_d = 0, tot_m = 0, tot_mask = 0, tot_X = 0, tot_H = 0, tot_Dp = 0;
 
   WsLayout layout(int op, int q) const {
@@ -258,7 +270,7 @@ static int build_gather(const ashrt_desc* d, GatherHost* gh) {
   if (st) return st;
   const Resolved& z = gh->z;
   gh->nrows = z.nxp / 2;
-  int T = std::min(64, 2 * (kXfftMaxTotal / z.nxp));
+  int T = std::min(64, 2 * (kXfftTilePoints / z.nxp));
   T = std::max(2, T & ~1);
   gh->tileT = T;
   gh->ntiles = (z.nt + T - 1) / T;
@@ -285,14 +297,19 @@ static int build_gather(const ashrt_desc* d, GatherHost* gh) {
 
 static void destroy_impl(PlanImpl& P) {
   if (P.dev) {
+    // hipFree waits for the device, so no cached graph is still running
+    // when it is destroyed
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != P.device) {
       (void)hipSetDevice(P.device);
       (void)hipFree(P.dev);
+      for (auto& gr : P.graphs) (void)hipGraphExecDestroy(gr.exec);
       (void)hipSetDevice(cur);
     } else {
       (void)hipFree(P.dev);
+      for (auto& gr : P.graphs) (void)hipGraphExecDestroy(gr.exec);
     }
+    P.graphs.clear();
     P.dev = nullptr;
   }
 }
@@ -938,7 +955,7 @@ int adjoint_impl(const PlanImpl& P, const float* d, float* m, const uint8_t* mas
 
 // ------------------------------------------------------------ IRLS-CG driver
 struct Solver {
-  const Ctx& c;
+  Ctx c;
   const PlanImpl& P;
   const irls_params& prm;
   float* r;
@@ -1044,6 +1061,66 @@ struct Solver {
     if (e_ != hipSuccess) return fail(ASHRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// One CG iteration on A = W_r S L W_m^-1, all on S.c.s:
+//   q = A pdir (per-tile partials of |q|^2); alpha = gamma / |q|^2;
+//   s -= alpha q; g = A' s (partials of |g|^2); beta; u += alpha pdir;
+//   pdir = g + beta pdir.  par selects the gamma slot pair.
+hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par) {
+  hipError_t e = run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel);
+  if (e != hipSuccess) return e;
+  CgStep st;
+  st.s_inout = S.s;
+  st.qv = S.q;
+  st.part_delta = S.pdel;
+  st.sc = S.sc;
+  st.par = par;
+  e = run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st);
+  if (e != hipSuccess) return e;
+  return S.cg(0, par);
+}
+
+constexpr size_t kMaxCgGraphs = 8;
+
+// The executable graph of two CG iterations (parities 0 and 1) for these
+// buffers: captured on a private stream the first time, then cached.
+int cg_graph_get(const PlanImpl& P, const Solver& S, const uint8_t* mask, int q, hipGraphExec_t* out) {
+  std::lock_guard<std::mutex> lk(P.graph_mu);
+  const float* mkey = S.u;
+  for (const auto& gr : P.graphs)
+    if (gr.ws == (const void*)S.c.ws && gr.m == mkey && gr.mask == mask && gr.q == q) {
+      *out = gr.exec;
+      return ASHRT_OK;
+    }
+  if (P.graphs.size() >= kMaxCgGraphs) {
+    // the oldest graph may still be running on some stream
+    E_TRY(hipDeviceSynchronize());
+    (void)hipGraphExecDestroy(P.graphs.front().exec);
+    P.graphs.erase(P.graphs.begin());
+  }
+  hipStream_t cs = nullptr;
+  E_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  Solver S2 = S;
+  S2.c.s = cs;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    e = cg_iteration(S2, mask, 0);
+    if (e == hipSuccess) e = cg_iteration(S2, mask, 1);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e_end;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) {
+      P.graphs.push_back(PlanImpl::CgGraph{S.c.ws, mkey, mask, q, exec});
+      *out = exec;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail(ASHRT_E_HIP, std::string("CG graph capture: ") + hipGetErrorString(e));
+  return ASHRT_OK;
+}
+
 int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const uint8_t* mask, float* m,
                 const float* w0, float* d_rec, irls_report* reps, void* ws, size_t wsb, void* stream,
                 bool batched) {
@@ -1068,6 +1145,11 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
            (RepDev*)(W + L.rep)};
   const hipStream_t s = c.s;
   const bool q1 = prm->q == 1, p1 = prm->p == 1;
+  hipGraphExec_t cg_exec = nullptr;
+  if (prm->cg_graph && prm->n_inner >= 2 && g_prof.mask == 0) {
+    st = cg_graph_get(P, S, mask, prm->q, &cg_exec);
+    if (st) return st;
+  }
 
   // clear scalars, selection histograms and the report
   E_TRY(launch_zero_words(S.sc, (long long)P.ngather * kNScal * 2, s));
@@ -1126,21 +1208,10 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
     }
     E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam));
     E_TRY(S.cg(1, 0));
-    for (int i = 0; i < prm->n_inner; ++i) {
-      const int par = i & 1;
-      // q = W_r S L W_m^-1 pdir, with per-tile partials of |q|^2
-      E_TRY(run_forward(c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel));
-      // alpha = gamma / |q|^2 ; s -= alpha q ; g = W_m^-1 L' S W_r s (partials of |g|^2)
-      CgStep st;
-      st.s_inout = S.s;
-      st.qv = S.q;
-      st.part_delta = S.pdel;
-      st.sc = S.sc;
-      st.par = par;
-      E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st));
-      // beta ; u += alpha pdir ; pdir = g + beta pdir
-      E_TRY(S.cg(0, par));
-    }
+    int i = 0;
+    if (cg_exec)
+      for (; i + 1 < prm->n_inner; i += 2) E_TRY(hipGraphLaunch(cg_exec, s));
+    for (; i < prm->n_inner; ++i) E_TRY(cg_iteration(S, mask, i & 1));
     E_TRY(S.scalar(ST_REPORT_INNER, k));
     if (q1) {
       EwArgs a = S.ew(EW_MUL, true);

@@ -15,7 +15,7 @@ constexpr int kThreads = 256;          // threads per workgroup (all kernels but
 constexpr int kRowThreads = 512;       // threads per workgroup of the forward/adjoint row passes
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
-constexpr int kXfftMaxTotal = 8192;    // complex points of one x-FFT tile in LDS
+constexpr int kXfftTilePoints = 4096;  // complex points of a model x-FFT tile (T = 2 * this / nxp columns)
 constexpr int kXfftBatch = 2048;       // complex points per compile-time x-FFT call (register bound)
 constexpr int kXfftGenericBatch = 4096;  // complex points per generic x-FFT call (nxp <= 4096)
 constexpr int kMaxSlots = (kRowMaxN / 2 + kThreads - 1) / kThreads;  // per-thread bins

@@ -189,13 +189,24 @@ __device__ __forceinline__ void xfft_tile(float2* buf, int n, int nb, int bstrid
   }
 }
 
+// Work-item order for a one-item-per-workgroup launch of n items on the 8
+// XCDs.  Workgroup b runs on XCD b mod 8; this gives XCD x the consecutive
+// items [x q + min(x, r), ...) (q = n div 8, r = n mod 8), so neighbouring
+// time tiles, which share 128-byte lines of the trace-major arrays, are read
+// through one L2.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
 // ------------------------------------------------------------ x-direction RFFT
 template <int NX>
 __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float s_alpha;
   __shared__ double s_red[kThreads / 64];
-  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+  for (int it0 = blockIdx.x; it0 < A.nitems; it0 += gridDim.x) {
+    const int it = (int)gridDim.x == A.nitems ? xcd_item(it0, A.nitems) : it0;
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
     float alpha = 0.f;
@@ -232,6 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     const float* __restrict__ src = A.src + fbase;
     const float* __restrict__ mul = A.mul ? A.mul + fbase : nullptr;
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
+    const bool even = (nt & 1) == 0;
 
     for (int idx = threadIdx.x; idx < nx * half; idx += kThreads) {
       const int x = idx / half;
@@ -253,6 +265,16 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
         if (mul) {
           a *= (t < nt) ? mul[o] : 0.f;
           b *= (t + 1 < nt) ? mul[o + 1] : 0.f;
+        }
+      } else if (even && t < nt) {
+        // nt even: (t, t+1) is an aligned pair inside the trace
+        const float2 v = *reinterpret_cast<const float2*>(src + o);
+        a = v.x;
+        b = v.y;
+        if (mul) {
+          const float2 wv = *reinterpret_cast<const float2*>(mul + o);
+          a *= wv.x;
+          b *= wv.y;
         }
       } else {
         if (t < nt) {
@@ -306,7 +328,8 @@ template <int NX>
 __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
   extern __shared__ float2 lds[];
   __shared__ double sh[kThreads / 64];
-  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+  for (int it0 = blockIdx.x; it0 < A.nitems; it0 += gridDim.x) {
+    const int it = (int)gridDim.x == A.nitems ? xcd_item(it0, A.nitems) : it0;
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
     const int p = w.a;
@@ -342,20 +365,41 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     double ss = 0.0;
-    for (int idx = threadIdx.x; idx < nx * T; idx += kThreads) {
-      const int x = idx / T;
-      const int c = idx - x * T;
-      const int t = t0 + c;
+    const bool even = (nt & 1) == 0;
+    for (int idx = threadIdx.x; idx < nx * half; idx += kThreads) {
+      const int x = idx / half;
+      const int i = idx - x * half;
+      const int t = t0 + 2 * i;
       if (t >= nt) continue;
-      const float2 z = buf[(c >> 1) * bs + px<NX>(x)];
-      float v = ((c & 1) ? z.y : z.x) * inv;
+      const float2 z = buf[i * bs + px<NX>(x)];
+      const bool live = !(tm && tm[x] == 0);
       const long long o = fbase + (long long)x * nt + t;
-      if (A.raw_out) A.raw_out[o] = v;
-      if (A.sub) v = A.sub[o] - v;
-      if (tm && tm[x] == 0) v = 0.f;
-      if (A.wmul) v *= A.wmul[o];
-      A.out[o] = v;
-      ss += (double)v * (double)v;
+      if (even) {
+        // nt even: columns t, t+1 form an aligned pair inside the trace
+        float2 v = make_float2(z.x * inv, z.y * inv);
+        if (A.raw_out) *reinterpret_cast<float2*>(A.raw_out + o) = v;
+        if (A.sub) {
+          const float2 sv = *reinterpret_cast<const float2*>(A.sub + o);
+          v = make_float2(sv.x - v.x, sv.y - v.y);
+        }
+        if (!live) v = make_float2(0.f, 0.f);
+        if (A.wmul) {
+          const float2 wv = *reinterpret_cast<const float2*>(A.wmul + o);
+          v = make_float2(v.x * wv.x, v.y * wv.y);
+        }
+        *reinterpret_cast<float2*>(A.out + o) = v;
+        ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      } else {
+        for (int c = 0; c < 2 && t + c < nt; ++c) {
+          float v = (c ? z.y : z.x) * inv;
+          if (A.raw_out) A.raw_out[o + c] = v;
+          if (A.sub) v = A.sub[o + c] - v;
+          if (!live) v = 0.f;
+          if (A.wmul) v *= A.wmul[o + c];
+          A.out[o + c] = v;
+          ss += (double)v * (double)v;
+        }
+      }
     }
     if (A.part) {
       const double tot = block_sum(ss, sh);

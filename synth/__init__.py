@@ -17,6 +17,7 @@ from .gathers import (  # noqa: F401
     render_events,
     make_gather,
     make_cfg3_batch,
+    batch_shapes,
     random_model,
     random_data,
 )

@@ -102,7 +102,10 @@ def test_status_strings(A):
         s = lib.ashrt_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.ashrt_status_string(-99).decode() == "unknown status"
-    assert lib.ashrt_abi_version() == 1
+    import re
+    hdr = open(os.path.join(ROOT, "include", "ashrt.h")).read()
+    assert lib.ashrt_abi_version() == int(re.search(r"#define ASHRT_ABI_VERSION (\d+)", hdr).group(1))
+    assert lib.ashrt_abi_version() == A._lib.ABI_VERSION
 
 
 def test_null_plan_and_workspace_errors(A):

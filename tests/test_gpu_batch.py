@@ -1,0 +1,118 @@
+"""GPU parity of the batched entry points: gathers of uneven nt / nx / panel
+count packed back to back, every pipeline stage one launch over all of them.
+
+Bars: per gather, relative L2 <= 1e-5 against the FP64 oracle for the
+operator pair and <= 1e-4 on the separated gather after a solve (the same
+bars as the single-gather entry points); at the batched production shapes,
+where the oracle is too slow, each gather of the batch matches the
+single-gather entry point (itself pinned to the oracle) to 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.irls import IrlsParams
+from synth import batch_shapes, make_gather, workload
+from tests.gpu_common import f32, geom_kwargs, oracle_geometry, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    import paper_1711_10214_amd as A
+    assert torch.cuda.is_available()
+    return A
+
+
+GEOMS = [
+    geom_kwargs(256, 64, 0.004, 12.5, list(np.linspace(1500, 3000, 8)), fmax=100.0),
+    geom_kwargs(203, 37, 0.004, 12.5, [1400.0, 2200.0, 3900.0], fmax=90.0),
+    geom_kwargs(190, 90, 0.004, 12.5, [1600.0, 2500.0], ntp=384, nxp=192, fmax=120.0),
+    geom_kwargs(256, 48, 0.004, 12.5, [1500.0, 1500.0, 2400.0, 2400.0], tau0=[0, 7, 0, 23],
+                scale=[1.0, 0.5, 2.0, 1.5], fmin=5.0, fmax=80.0),
+    geom_kwargs(128, 32, 0.002, 10.0, [0.0, 1800.0, 5000.0], ntp=128, nxp=32),
+]
+
+
+def test_batched_operator_matches_oracle(A):
+    import torch
+    print("[gpu] batched forward/adjoint, 5 uneven gathers vs oracle", flush=True)
+    rng = np.random.default_rng(20)
+    plan = A.BatchPlan(GEOMS)
+    gs = [oracle_geometry(kw) for kw in GEOMS]
+    ms = [f32(rng.standard_normal((g.npanel, g.nx, g.nt))) for g in gs]
+    ds = [f32(rng.standard_normal((g.nx, g.nt))) for g in gs]
+    masks = [None, None, (rng.uniform(size=90) > 0.4).astype(np.uint8), (rng.uniform(size=48) > 0.3).astype(np.uint8),
+             None]
+    mk = plan.pack_mask(masks)
+    d_out = plan.forward(plan.pack_model(ms), mask_packed=mk)
+    m_out = plan.adjoint(plan.pack_data(ds), mask_packed=mk)
+    torch.cuda.synchronize()
+    for i, g in enumerate(gs):
+        e_f = rel_l2(plan.unpack_data(d_out, i).cpu().numpy(), oracle.forward(g, ms[i], masks[i]))
+        e_a = rel_l2(plan.unpack_model(m_out, i).cpu().numpy(), oracle.adjoint(g, ds[i], masks[i]))
+        print(f"  gather {i}: fwd {e_f:.2e} adj {e_a:.2e}", flush=True)
+        assert e_f <= 1e-5 and e_a <= 1e-5
+
+
+def test_batched_solve_matches_oracle(A):
+    print("[gpu] batched robust_invert, 3 uneven gathers vs oracle", flush=True)
+    w = workload("crg-256x64-nv8")
+    shapes = [(256, 64, 1), (192, 50, 11), (160, 72, 12)]
+    gths = [make_gather(w, seed=s, nt=nt, nx=nx) for nt, nx, s in shapes]
+    kws = [geom_kwargs(nt, nx, w.dt, w.dx, list(w.vel), fmax=w.fmax) for nt, nx, _ in shapes]
+    plan = A.BatchPlan(kws)
+    prm = IrlsParams(p=1, q=2, n_outer=3, n_inner=6)
+    P = A.Params(p=1, q=2, n_outer=3, n_inner=6)
+    d = plan.pack_data([f32(g.d_blend) for g in gths])
+    _, drec, reps = plan.robust_invert(d, P)
+    for i, (g, kw) in enumerate(zip(gths, kws)):
+        _, d_ref, rep_ref = oracle.robust_invert(oracle_geometry(kw), f32(g.d_blend), prm)
+        e = rel_l2(plan.unpack_data(drec, i).cpu().numpy(), d_ref)
+        print(f"  gather {i} {shapes[i][:2]}: d_rec rel-L2 {e:.2e}", flush=True)
+        assert e <= 1e-4
+        assert reps[i]["inner"] == rep_ref["inner"]
+        np.testing.assert_allclose(reps[i]["misfit"], rep_ref["misfit"], rtol=1e-4)
+
+
+def test_batched_production_shapes_match_single_gather(A):
+    """Six gathers drawn like the 512-gather workload (nt up to 2048, nx up to
+    320, 24 velocities): batched forward, adjoint and a short solve agree with
+    the single-gather entry point gather by gather."""
+    import torch
+    w = workload("batch512-crg-nv24")
+    shapes = batch_shapes(6, w.seed)
+    print(f"[gpu] batched production shapes {[(nt, nx) for nt, nx, _ in shapes]}", flush=True)
+    kws = [geom_kwargs(nt, nx, w.dt, w.dx, list(w.vel), fmax=w.fmax) for nt, nx, _ in shapes]
+    gths = [make_gather(w, seed=s, nt=nt, nx=nx) for nt, nx, s in shapes]
+    plan = A.BatchPlan(kws)
+    rng = np.random.default_rng(21)
+    ms = [rng.standard_normal((w.npanel, nx, nt)).astype(np.float32) for nt, nx, _ in shapes]
+    d_b = plan.forward(plan.pack_model(ms))
+    dd = plan.pack_data([g.d_blend.astype(np.float32) for g in gths])
+    m_b = plan.adjoint(dd)
+    P = A.Params(p=1, q=2, n_outer=2, n_inner=3)
+    _, drec_b, reps = plan.robust_invert(dd, P)
+    for i, kw in enumerate(kws):
+        single = A.Plan(**kw)
+        d_s = single.forward(torch.tensor(ms[i], device="cuda"))
+        m_s = single.adjoint(plan.unpack_data(dd, i).contiguous())
+        _, drec_s, rep_s = single.robust_invert(plan.unpack_data(dd, i).contiguous(), P)
+        e_f = rel_l2(plan.unpack_data(d_b, i).cpu().numpy(), d_s.cpu().numpy())
+        e_a = rel_l2(plan.unpack_model(m_b, i).cpu().numpy(), m_s.cpu().numpy())
+        e_s = rel_l2(plan.unpack_data(drec_b, i).cpu().numpy(), drec_s.cpu().numpy())
+        print(f"  gather {i}: fwd {e_f:.1e} adj {e_a:.1e} solve {e_s:.1e}", flush=True)
+        assert e_f <= 1e-5 and e_a <= 1e-5 and e_s <= 1e-5
+        np.testing.assert_allclose(reps[i]["misfit"], rep_s["misfit"], rtol=1e-5)
+
+
+def test_batched_rejects_tolerance_and_empty(A):
+    import torch
+    plan = A.BatchPlan(GEOMS[:2])
+    d = torch.zeros(plan.data_total, device="cuda")
+    with pytest.raises(A.AshrtError):
+        plan.robust_invert(d, A.Params(n_outer=3, n_inner=2, tol=0.01))
+    with pytest.raises(Exception):
+        A.BatchPlan([])
