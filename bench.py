@@ -150,7 +150,8 @@ def main():
     prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
     lib = L.lib()
 
-    def solve():
+    def solve(graph=True):
+        prm.cg_graph = graph
         return plan.robust_invert(d, prm, mask=mask, want_report=False)
 
     # warm-up, plus one fully profiled solve to find the dominant kernel
@@ -183,7 +184,7 @@ def main():
     ev0.record()
     out = None
     for _ in range(args.steps):
-        out = solve()
+        out = solve(graph=False)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -205,6 +206,15 @@ def main():
         if ref and ref["n_outer"] == w.n_outer and ref["n_inner"] == w.n_inner:
             snr["oracle_q_r_db"] = ref["q_r_db"]
             snr["reached"] = bool(q_r >= ref["q_r_db"] - 0.05)
+
+    # the same solves with the CG iterations replayed from a hipGraph (no
+    # per-kernel events, which keep the timed region above on plain launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solve(graph=True)
+    torch.cuda.synchronize()
+    graph_wall = time.perf_counter() - t0
 
     # operator pairs per second
     rng = np.random.default_rng(0)
@@ -266,6 +276,7 @@ def main():
                    "nxp": plan.info["nxp"], "npanel": w.npanel, "p": w.p, "q": w.q,
                    "n_outer": w.n_outer, "n_inner": w.n_inner, "fmax_hz": w.fmax,
                    "reductions": "f64", "seed": w.seed},
+        "graph_gathers_per_s": args.steps / graph_wall,
         "pairs_per_s": 1.0 / pair_s,
         "pair_ms": pair_s * 1e3,
         "pair_algorithmic_gbs": pair_bytes / pair_s / 1e9,

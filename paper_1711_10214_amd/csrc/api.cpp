@@ -476,11 +476,7 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   auto plen_of = [](const GatherHost& gh) { return (size_t)fft_padlen(gh.z.ntp); };
   auto lds_rf_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + plen_of(gh)) * 8 + nband_of(gh) * 16; };
   auto lds_fin_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + plen_of(gh)) * 8; };
-  auto lds_ra_of = [&](const GatherHost& gh) {
-    const size_t nb = nband_of(gh);
-    return ((size_t)gh.z.ntp + 2 * plen_of(gh) + (plen_of(gh) & 1)) * 8 + nb * 16 +
-           (size_t)(gh.z.kmax + 2 * gh.z.R + 1) * 4;
-  };
+  auto lds_ra_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + 2 * plen_of(gh)) * 8; };
   // work lists grouped by kernel instantiation; a gather's items stay contiguous
   auto build_segments = [&](const std::vector<int>& keys, std::vector<PlanImpl::Seg>& segs,
                             std::vector<WorkItem>& items, auto&& add_items, auto&& lds_of) {

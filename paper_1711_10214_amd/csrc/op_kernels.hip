@@ -586,102 +586,117 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd_fin(RowsArgs A) {
 
 // ------------------------------------------------------------ adjoint rows
 //
-// The transpose of the forward gather, itself as a gather: for model bin k
-// and tap t the only data bin that reaches it is the j with floor(u_j) =
-// k - t, because floor(u_j) is strictly increasing in j inside the cone
-// (u_{j+1} - u_j = (2j+1) / (u_{j+1} + u_j) >= 1).  Phase 1 evaluates the
-// taps of every band bin once and records inv[floor(u_j)] = j; phase 2 sums
-// the 2R (j, t) pairs of each k with the same weights the forward uses.
+// The transpose of the forward gather, as a scatter: data bin j adds
+// h(u_j - k) times its ramped, scaled value to the 2R model bins
+// k = floor(u_j) - R + 1 .. floor(u_j) + R, with the weights the forward
+// uses.  floor(u_j) is strictly increasing in j inside the cone
+// (u_{j+1} - u_j = (2j+1) / (u_{j+1} + u_j) >= 1), so:
+//
+// * for one tap, different bins j write different k: the lanes of a wave,
+//   taking the taps in order, never collide within a tap, and the LDS
+//   operations of one wave complete in issue order, so the read-modify-write
+//   of tap t+1 sees that of tap t (a wave barrier keeps the compiler from
+//   reordering them);
+// * a wave owns a 64-bin segment of the band; two segments with a full
+//   segment between them (64 >= 2R - 1 bins) touch disjoint model bins, so
+//   even segments run first, then a barrier, then odd ones.
+//
+// No atomics: each model bin sums its contributions in a fixed order.
 //
 // LDS: twiddles [ntp], data row spectrum bufD and model spectrum bufM
-// (padded lengths), per band bin the tap trig (float4), and inv over the
-// model bins (offset R so k - t never goes negative).
+// (padded lengths).
 template <int N, int RC, int NT>
 __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
                                               float2* lds, const float* ctab, const float* stab) {
-  constexpr int RT = RC > 0 ? RC : kMaxHalfWidth;  // tap-loop bound
+  constexpr int NW = NT / 64;
   const int R = RC > 0 ? RC : A.R;
   const int r = w.a, chunk = w.b;
   const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows, P = G.npanel;
   const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
-  const int kmax = G.kmax;
-  const int ninv = kmax + 2 * R + 1;
+  const int hmax = ntp / 2 - 1;
+  const int nseg = (nband + 63) >> 6;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int p0 = (int)((long long)chunk * P / G.nchunk);
   const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
   const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
   float2* bufD = lds + ntp;
   float2* bufM = bufD + plen;
-  float4* tab_tr = reinterpret_cast<float4*>(bufM + plen + (plen & 1));
-  int* inv = reinterpret_cast<int*>(tab_tr + nband);
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
 
   row_spectrum<N, NT>(bufD, A.H + G.H_off + (long long)r * nt, r, nt, ntp, twl);
+
+  // window rotations cos/sin(pi t / R) in registers (the wave barriers below
+  // would otherwise reload them from LDS at every tap)
+  constexpr int RT = RC > 0 ? RC : 1;
+  float cr[2 * RT], sr[2 * RT];
+  if constexpr (RC > 0) {
+#pragma unroll
+    for (int i = 0; i < 2 * RC; ++i) {
+      cr[i] = ctab[i];
+      sr[i] = stab[i];
+    }
+  }
 
   const int npass = (r == 0) ? 2 : 1;
   for (int p = p0; p < p1; ++p) {
     const PanelDev PD = A.panels[G.panel_off + p];
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
     for (int k = threadIdx.x; k < plen; k += NT) bufM[k] = make_float2(0.f, 0.f);
+    __syncthreads();
     for (int pass = 0; pass < npass; ++pass) {
       const int l = (r == 0) ? (pass == 0 ? 0 : nrows) : r;
       const double a2 = PD.c2 * (double)l * (double)l;
-      for (int i = threadIdx.x; i < ninv; i += NT) inv[i] = -1;
-      __syncthreads();
-      // phase 1: taps of every band bin, and the inverse index of floor(u)
-      for (int j = jlo + threadIdx.x; j <= jhi; j += NT) {
-        const Taps T = taps_of<RC>(j, a2, R);
-        tab_tr[j - jlo] = T.trig;
-        if (T.k0 != kNoTap) inv[R + T.k0] = j - jlo;
-      }
-      __syncthreads();
-      // phase 2: model bin k gathers tap t from data bin inv[k - t]
+      for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll 1
-      for (int k = 1 + (int)threadIdx.x; k <= kmax; k += NT) {
-        float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
-        // tap t = R - q reads inv[k + q]: one contiguous run per k, loaded
-        // up front; missing sources are clamped to bin 0 with weight 0 so
-        // every tap issues the same loads (no data-dependent branches)
-        int jrs[2 * RT];
+        for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
+          const int j = jlo + sg * 64 + lane;
+          if (j <= jhi) {
+            const Taps T = taps_of<RC>(j, a2, R);
+            if (T.k0 != kNoTap) {
+              // spectrum values of bin j, ramped and scaled; the tap adds
+              // wgt * e1 at k and wgt * e2 at ntp - k of the model spectrum:
+              //   rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l)
+              //   row 0:     Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
+              float2 du = bufD[px<N>(j)];
+              float2 dl = cconj(bufD[px<N>(ntp - j)]);
+              if (plain) {
+                du = cscale(du, PD.scale);
+                dl = cscale(dl, PD.scale);
+              } else {
+                const float2 c = bin_factor(G, PD, A.tw, A.wav, j);
+                du = cmulconj(du, c);
+                dl = cmulconj(dl, c);
+              }
+              float2 e1, e2;
+              if (r != 0) {
+                e1 = du;
+                e2 = cconj(dl);
+              } else if (pass == 0) {
+                e1 = du;
+                e2 = cconj(du);
+              } else {
+                e1 = make_float2(-dl.y, dl.x);
+                e2 = make_float2(dl.y, dl.x);
+              }
 #pragma unroll
-        for (int q = 0; q < 2 * RT; ++q) jrs[q] = (RC > 0 || q < 2 * R) ? inv[k + q] : -1;
-#pragma unroll
-        for (int q = 0; q < 2 * RT; ++q) {
-          if (RC == 0 && q >= 2 * R) break;
-          const int t = R - q;
-          const int jr = jrs[q];
-          const int jc = jr < 0 ? 0 : jr;
-          const int j = jlo + jc;
-          float wgt = tap_weight(tab_tr[jc], t, ctab[t + R - 1], stab[t + R - 1]);
-          wgt = jr < 0 ? 0.f : wgt;
-          float2 du = bufD[px<N>(j)];
-          float2 dl = cconj(bufD[px<N>(ntp - j)]);
-          if (!plain) {
-            const float2 c = bin_factor(G, PD, A.tw, A.wav, j);
-            du = cmulconj(du, c);
-            dl = cmulconj(dl, c);
+              for (int t = -R + 1; t <= R; ++t) {
+                const int k = T.k0 + t;
+                if (k >= 1 && k <= hmax) {
+                  const float wt = RC > 0 ? tap_weight(T.trig, t, cr[(t + R - 1) % (2 * RT)], sr[(t + R - 1) % (2 * RT)])
+                                          : tap_weight(T.trig, t, ctab[t + R - 1], stab[t + R - 1]);
+                  float2* q1 = bufM + px<N>(k);
+                  float2* q2 = bufM + px<N>(ntp - k);
+                  *q1 = cfma(wt, e1, *q1);
+                  *q2 = cfma(wt, e2, *q2);
+                }
+                __builtin_amdgcn_wave_barrier();
+              }
+            }
           }
-          if (r != 0 || pass == 0) au = cfma(wgt, du, au);
-          if (r != 0 || pass == 1) al = cfma(wgt, dl, al);
         }
-        if (plain) {
-          au = cscale(au, PD.scale);
-          al = cscale(al, PD.scale);
-        }
-        // model time spectrum: rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l);
-        // row 0: Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
-        if (r != 0) {
-          bufM[px<N>(k)] = au;
-          bufM[px<N>(ntp - k)] = cconj(al);
-        } else if (pass == 0) {
-          bufM[px<N>(k)] = au;  // kept until pass 1 (same thread owns k)
-        } else {
-          const float2 u = bufM[px<N>(k)];
-          bufM[px<N>(k)] = make_float2(u.x - al.y, u.y + al.x);
-          bufM[px<N>(ntp - k)] = make_float2(u.x + al.y, -u.y + al.x);
-        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     row_inverse<N, NT>(bufM, ntp, twl);
     const float inv_n = 1.0f / (float)ntp;
