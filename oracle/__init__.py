@@ -11,6 +11,11 @@ Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import it.  It shares no code with the library: the two meet only through the
 seeded input generator in ``synth``.
 
+``unet`` is the FP64 reference of the learned warm start (a U-Net that
+predicts an initial model and initial residual weights for the robust
+inversion): its forward pass is the network's definition, its hand-written
+gradient is pinned against finite differences.
+
 Pinned by ``tests/test_oracle_*.py`` against brute-force DFTs, a brute-force
 time-domain hyperbola summation, the dispersion relation, closed-form special
 cases, the dot-product test, Krylov-subspace least squares, a convex-optimum
@@ -41,4 +46,5 @@ from .irls import (  # noqa: F401
     robust_invert,
 )
 from .quality import q_db  # noqa: F401
+from . import unet  # noqa: F401
 from . import timedomain  # noqa: F401
