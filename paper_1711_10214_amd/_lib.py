@@ -49,6 +49,15 @@ class IrlsParams(C.Structure):
     ]
 
 
+class UnetDesc(C.Structure):
+    _fields_ = [("cin", C.c_int32), ("pout", C.c_int32), ("base", C.c_int32)]
+
+
+class UnetTrainParams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double), ("lam_w", C.c_double)]
+
+
 class IrlsReport(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("outer_done", C.c_int32),
@@ -111,6 +120,17 @@ def lib():
         "ashrt_profile_enable": (C.c_int, [C.c_uint32]),
         "ashrt_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
         "ashrt_kernel_name": (C.c_char_p, [C.c_int]),
+        # learned warm start (include/unet.h)
+        "unet_create": (C.c_int, [C.POINTER(UnetDesc), C.c_int, C.POINTER(vp)]),
+        "unet_destroy": (None, [vp]),
+        "unet_param_count": (C.c_int64, [vp]),
+        "unet_set_params": (C.c_int, [vp, vp, C.c_int64]),
+        "unet_get_params": (C.c_int, [vp, vp, C.c_int64]),
+        "unet_workspace_bytes": (C.c_int, [vp, i32, i32, i32, i32, C.POINTER(sz)]),
+        "unet_forward": (C.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]),
+        "unet_loss_grad": (C.c_int, [vp, vp, vp, vp, i32, i32, i32, C.c_double, vp, vp, vp, sz, vp]),
+        "unet_train_step": (C.c_int, [vp, C.POINTER(UnetTrainParams), vp, vp, vp, i32, i32, i32, vp, vp, sz,
+                                      vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

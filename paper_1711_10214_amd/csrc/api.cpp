@@ -29,6 +29,11 @@ static int fail(int code, const std::string& msg) {
   return code;
 }
 
+// Shared with the other C-ABI sources of the library (unet.cpp).
+namespace ashrt {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace ashrt
+
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \

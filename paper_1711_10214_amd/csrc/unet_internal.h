@@ -1,0 +1,107 @@
+// Internal types shared by the U-Net host code and its HIP kernels.
+//
+// Activations are BF16 (stored as raw uint16_t bit patterns) in NHWC layout
+// [B][H][W][C]; activation gradients are FP32 NHWC.  A 3x3 convolution is an
+// implicit GEMM on the BF16 matrix cores: out[co][pixel] = sum over
+// k = (tap, ci) of Wp[co][k] * in[pixel + tap][ci].  The reduction index is
+// split into channel chunks of CC channels (8, 16 or 32), and one 32-wide
+// MFMA k-step covers TPK = 32 / CC taps of one chunk; taps are padded to KKp
+// (a multiple of TPK) with zero weights.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace unet {
+
+constexpr int kConvTH = 4;    // output rows per conv workgroup (one per wave)
+constexpr int kConvTW = 32;   // output columns per conv workgroup
+constexpr int kConvCoT = 64;  // output channels per conv workgroup
+constexpr int kWgTH = 4;      // pixel tile of the weight-gradient kernel (rows)
+constexpr int kWgTW = 32;     //                                      (columns)
+constexpr int kWgCoT = 64;    // output channels per weight-gradient workgroup
+
+// Input of a convolution as its loader sees it: channels [0, Ca) come from
+// tensor A (mode 0: same resolution; 1: A at half resolution, nearest 2x
+// upsample; 2: A at double resolution, 2x2 mean), channels [Ca, Ca + Cb)
+// from tensor Bs at the same resolution (the concatenated skip), and the
+// rest up to the padded count are zero.
+struct ConvIn {
+  const void* A;            // BF16 NHWC, or FP32 NHWC when the kernel's AF32 is set
+  const uint16_t* Amask;    // FP32 A only: multiply by (Amask > 0) (ReLU derivative), or null
+  const uint16_t* Bs;       // BF16 NHWC skip, or null
+  int Ca, Cb, modeA;
+  int H, W;                 // conv (output) resolution
+};
+
+// Packed-weight geometry of one convolution (forward or transposed).
+struct ConvPack {
+  int Cin, Cout;            // real channel counts
+  int Cip;                  // padded input channels: 8, 16 or a multiple of 32
+  int CC, ncc, TPK, KKp;    // channel chunk, chunk count, taps per k-step, padded taps
+  int Coutp;                // Cout rounded up to 16
+};
+
+struct ConvArgs {
+  ConvIn in;
+  ConvPack pk;
+  const uint16_t* Wp;       // BF16 [Coutp][ncc][KKp][CC]
+  const float* bias;        // [Cout] or null
+  int relu;
+  void* out;                // BF16 or FP32 NHWC [B][H][W][Cout]
+  int B;
+};
+
+struct WgradArgs {
+  ConvIn in;                // the convolution's input (forward view)
+  const float* gY;          // FP32 NHWC [B][H][W][Cout]: gradient of the conv output
+  const uint16_t* Y;        // BF16 conv output (ReLU mask), or null
+  int Cout, Cin;            // real counts
+  int CCw, nccw, Cipw;      // channel chunk of the reduction tile (16 or 32), chunks, padded count
+  float* part;              // [nsplit][Cout][9][Cipw]
+  int nsplit, B;
+};
+
+struct PackArgs {
+  const float* W;           // canonical [Cout][Cin][3][3]
+  uint16_t* Wp;             // forward packing
+  uint16_t* Wtp;            // transposed packing (input = Cout channels, output = Cin)
+  ConvPack f, t;
+};
+
+struct RouteArgs {
+  const float* gX;          // [B][H][W][Ca + Cb] FP32 gradient of the conv input
+  float* gA;                // gradient of A (at A's resolution), accumulated
+  float* gB;                // gradient of the skip, accumulated, or null
+  int Ca, Cb, modeA, H, W, B;
+};
+
+struct BiasArgs {
+  const float* gY;
+  const uint16_t* Y;
+  int C;
+  long long npix;
+  float* part;              // [nblk][C]
+};
+
+struct HeadArgs {
+  const uint16_t* h;        // BF16 NHWC [B][H][W][C1]
+  const float* Wm;          // [P][C1], then bias [P]
+  const float* Ww;          // [1][C1], then bias [1]
+  float* y_m;               // [B][P][H][W]
+  float* y_w;               // [B][H][W]
+  int C1, P, B, H, W;
+};
+
+struct LossArgs {
+  HeadArgs hd;
+  const float* t_m;
+  const float* t_w;
+  float lam_w;
+  float* g_h;               // FP32 NHWC [B][H][W][C1] gradient of the head input
+  float* hpart;             // [nblk][17 * P + 17 ... ] head parameter-gradient partials
+  double* lpart;            // [nblk][2]
+  int ne;                   // entries per head partial: P*C1 + P + C1 + 1
+};
+
+}  // namespace unet

@@ -1,0 +1,682 @@
+// HIP kernels of the warm-start U-Net for gfx950.
+//
+// 3x3 convolutions (forward and input-gradient) and their weight gradients
+// run on the BF16 matrix cores, v_mfma_f32_16x16x32_bf16: a wave multiplies
+// a 16 x 32 BF16 tile A by a 32 x 16 tile B into a 16 x 16 FP32 tile.
+// Lane l supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16]
+// (i = 0..7, eight consecutive BF16 values = 16 bytes) and receives
+// D[4 (l / 16) + i][l % 16] (i = 0..3).
+//
+// Forward convolution: A = packed weights (rows = output channels, k =
+// (tap, input channel)), B = the input tile staged in LDS as [row][col][ci]
+// (so eight consecutive channels of one tap are one 16-byte read), D =
+// output channels x pixels, written as four consecutive channels of one
+// pixel (NHWC).  The input-gradient is the same kernel on the gradient of
+// the output (masked by the ReLU) with the transposed, tap-flipped weights.
+// Weight gradient: A = output gradient staged [co][pixel], B = input staged
+// [dx][ci][row][col] (three column-shifted copies keep every read aligned),
+// k = pixels; workgroups split the pixels and write FP32 partials that a
+// second kernel sums in a fixed order.
+#include "unet_internal.h"
+
+namespace unet {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ uint4 pack8(const float v[8]) {
+  uint4 r;
+  r.x = f2bf(v[0]) | (f2bf(v[1]) << 16);
+  r.y = f2bf(v[2]) | (f2bf(v[3]) << 16);
+  r.z = f2bf(v[4]) | (f2bf(v[5]) << 16);
+  r.w = f2bf(v[6]) | (f2bf(v[7]) << 16);
+  return r;
+}
+
+__device__ __forceinline__ void unpack8(uint4 q, float v[8]) {
+  v[0] = bf2f(q.x & 0xFFFFu);
+  v[1] = bf2f(q.x >> 16);
+  v[2] = bf2f(q.y & 0xFFFFu);
+  v[3] = bf2f(q.y >> 16);
+  v[4] = bf2f(q.z & 0xFFFFu);
+  v[5] = bf2f(q.z >> 16);
+  v[6] = bf2f(q.w & 0xFFFFu);
+  v[7] = bf2f(q.w >> 16);
+}
+
+// ReLU derivative from the stored (post-ReLU) BF16 output: 1 where it is > 0.
+__device__ __forceinline__ bool relu_on(uint32_t h) { return (h & 0x8000u) == 0 && (h & 0x7FFFu) != 0; }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Channels [c, c + 8) of conv-input pixel (b, y, x); zero outside the image
+// and beyond the real channels.  c is a multiple of 8, and so are Ca and Cb
+// unless Ca == 1 (the FP32 network input).
+template <bool AF32>
+__device__ __forceinline__ void load_in8(const ConvIn& I, int b, int y, int x, int c, float v[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = 0.f;
+  if (y < 0 || y >= I.H || x < 0 || x >= I.W) return;
+  if (c < I.Ca) {
+    if constexpr (AF32) {
+      const float* A = static_cast<const float*>(I.A);
+      if (I.Ca == 1) {
+        v[0] = A[((long long)b * I.H + y) * I.W + x];
+      } else {
+        const long long o = (((long long)b * I.H + y) * I.W + x) * I.Ca + c;
+        const float4 p = *reinterpret_cast<const float4*>(A + o);
+        const float4 q = *reinterpret_cast<const float4*>(A + o + 4);
+        v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w;
+        v[4] = q.x; v[5] = q.y; v[6] = q.z; v[7] = q.w;
+        if (I.Amask) {
+          const uint4 m = *reinterpret_cast<const uint4*>(I.Amask + o);
+          const uint32_t mm[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (!relu_on(mm[i] & 0xFFFFu)) v[2 * i] = 0.f;
+            if (!relu_on(mm[i] >> 16)) v[2 * i + 1] = 0.f;
+          }
+        }
+      }
+    } else {
+      const uint16_t* A = static_cast<const uint16_t*>(I.A);
+      if (I.modeA == 0) {
+        unpack8(*reinterpret_cast<const uint4*>(A + (((long long)b * I.H + y) * I.W + x) * I.Ca + c), v);
+      } else if (I.modeA == 1) {
+        const int Ha = I.H >> 1, Wa = I.W >> 1;
+        unpack8(*reinterpret_cast<const uint4*>(A + (((long long)b * Ha + (y >> 1)) * Wa + (x >> 1)) * I.Ca + c),
+                v);
+      } else {
+        const int Ha = I.H * 2, Wa = I.W * 2;
+        float t[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ya = 2 * y + (q >> 1), xa = 2 * x + (q & 1);
+          unpack8(*reinterpret_cast<const uint4*>(A + (((long long)b * Ha + ya) * Wa + xa) * I.Ca + c), t);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) v[i] += t[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] *= 0.25f;
+      }
+    }
+  } else if (c < I.Ca + I.Cb) {
+    unpack8(*reinterpret_cast<const uint4*>(I.Bs + (((long long)b * I.H + y) * I.W + x) * I.Cb + (c - I.Ca)), v);
+  }
+}
+
+// ------------------------------------------------------------ 3x3 convolution
+// Grid: (row tiles x column tiles, output-channel tiles of 64, batch).
+// Wave w computes output row w of the tile: up to 4 x 2 MFMA tiles
+// (64 channels x 32 columns).
+template <bool AF32, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
+  constexpr int TW2 = kConvTW + 2;
+  __shared__ __attribute__((aligned(16))) uint16_t sX[(kConvTH + 2) * TW2 * 40];
+  const int H = a.in.H, W = a.in.W;
+  const int tiles_x = (W + kConvTW - 1) / kConvTW;
+  const int ty0 = ((int)blockIdx.x / tiles_x) * kConvTH;
+  const int tx0 = ((int)blockIdx.x % tiles_x) * kConvTW;
+  const int co0 = (int)blockIdx.y * kConvCoT, b = (int)blockIdx.z;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int sub = lane >> 4, n16 = lane & 15;
+  const ConvPack& P = a.pk;
+  const int MI = min(4, (P.Coutp - co0) >> 4);
+  const int CC = P.CC, PS = CC + 8, ng = CC >> 3;
+  const int kl = sub * 8, tap_l = kl / CC, coff = kl - tap_l * CC;
+  const int nkc = P.KKp / P.TPK;
+
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int cc = 0; cc < P.ncc; ++cc) {
+    for (int task = threadIdx.x; task < (kConvTH + 2) * TW2 * ng; task += 256) {
+      const int g = task % ng, pix = task / ng;
+      const int ty = pix / TW2, tx = pix - ty * TW2;
+      float v[8];
+      load_in8<AF32>(a.in, b, ty0 + ty - 1, tx0 + tx - 1, cc * CC + g * 8, v);
+      *reinterpret_cast<uint4*>(sX + pix * PS + g * 8) = pack8(v);
+    }
+    __syncthreads();
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int kk = kc * P.TPK + tap_l;
+      const bool valid = kk < 9;
+      const int dy = valid ? kk / 3 : 0, dx = valid ? kk - (kk / 3) * 3 : 0;
+      bf16x8 bfrag[2];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const int px = ni * 16 + n16;
+        uint4 q = *reinterpret_cast<const uint4*>(sX + ((wave + dy) * TW2 + px + dx) * PS + coff);
+        if (!valid) q = make_uint4(0u, 0u, 0u, 0u);
+        bfrag[ni] = __builtin_bit_cast(bf16x8, q);
+      }
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) {
+        if (mi < MI) {
+          const int co = co0 + mi * 16 + n16;
+          const uint4 wq =
+              *reinterpret_cast<const uint4*>(a.Wp + (((long long)co * P.ncc + cc) * P.KKp + kk) * CC + coff);
+          const bf16x8 afrag = __builtin_bit_cast(bf16x8, wq);
+          acc[mi][0] = mfma(afrag, bfrag[0], acc[mi][0]);
+          acc[mi][1] = mfma(afrag, bfrag[1], acc[mi][1]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const int y = ty0 + wave;
+  if (y >= H) return;
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi) {
+    if (mi >= MI) continue;
+    const int co = co0 + mi * 16 + sub * 4;
+    if (co >= P.Cout) continue;
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int x = tx0 + ni * 16 + n16;
+      if (x >= W) continue;
+      float o[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        o[i] = acc[mi][ni][i] + (a.bias ? a.bias[co + i] : 0.f);
+        if (a.relu) o[i] = fmaxf(o[i], 0.f);
+      }
+      const long long off = (((long long)b * H + y) * W + x) * P.Cout + co;
+      if constexpr (OUTF32) {
+        *reinterpret_cast<float4*>(static_cast<float*>(a.out) + off) = make_float4(o[0], o[1], o[2], o[3]);
+      } else {
+        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(a.out) + off) =
+            make_uint2(f2bf(o[0]) | (f2bf(o[1]) << 16), f2bf(o[2]) | (f2bf(o[3]) << 16));
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ weight gradient
+// Grid: (input-channel chunks, output-channel tiles of 64, pixel splits).
+// Wave w accumulates the taps kk = w, w + 4, w + 8.
+template <bool AF32>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  constexpr int ZS = kWgTH * kWgTW + 8;  // LDS stride between output channels
+  constexpr int XR = kWgTH + 2;
+  constexpr int XS = XR * kWgTW + 8;     // LDS stride between input channels
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[kWgCoT * ZS];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[3 * 32 * XS];
+  const int H = a.in.H, W = a.in.W;
+  const int cc = (int)blockIdx.x, co0 = (int)blockIdx.y * kWgCoT, split = (int)blockIdx.z;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int sub = lane >> 4, n16 = lane & 15;
+  const int MI = min(4, (a.Cout - co0 + 15) >> 4);
+  const int NI = a.CCw >> 4;
+  const int ngx = a.CCw >> 3;
+  const int tiles_x = (W + kWgTW - 1) / kWgTW, tiles_y = (H + kWgTH - 1) / kWgTH;
+  const int T = a.B * tiles_x * tiles_y;
+
+  f32x4 acc[3][4][2];
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) acc[s][mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = split; t < T; t += a.nsplit) {
+    const int b = t / (tiles_x * tiles_y);
+    const int rem = t - b * tiles_x * tiles_y;
+    const int ty0 = (rem / tiles_x) * kWgTH, tx0 = (rem % tiles_x) * kWgTW;
+    // output gradient, ReLU-masked, transposed to [co][row][col]
+    for (int task = threadIdx.x; task < kWgTH * kWgTW * (kWgCoT / 8); task += 256) {
+      const int g = task & 7, pix = task >> 3;
+      const int row = pix / kWgTW, px = pix - row * kWgTW;
+      const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (y < H && x < W && co < a.Cout) {
+        const long long o = (((long long)b * H + y) * W + x) * a.Cout + co;
+        const float4 p = *reinterpret_cast<const float4*>(a.gY + o);
+        const float4 q = *reinterpret_cast<const float4*>(a.gY + o + 4);
+        v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w;
+        v[4] = q.x; v[5] = q.y; v[6] = q.z; v[7] = q.w;
+        if (a.Y) {
+          const uint4 m = *reinterpret_cast<const uint4*>(a.Y + o);
+          const uint32_t mm[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (!relu_on(mm[i] & 0xFFFFu)) v[2 * i] = 0.f;
+            if (!relu_on(mm[i] >> 16)) v[2 * i + 1] = 0.f;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sZ[(g * 8 + i) * ZS + row * kWgTW + px] = (uint16_t)f2bf(v[i]);
+    }
+    // input tile with a one-pixel halo, as three column-shifted copies
+    for (int task = threadIdx.x; task < XR * (kWgTW + 2) * ngx; task += 256) {
+      const int g = task % ngx, pix = task / ngx;
+      const int row = pix / (kWgTW + 2), px = pix - row * (kWgTW + 2);
+      float v[8];
+      load_in8<AF32>(a.in, b, ty0 + row - 1, tx0 + px - 1, cc * a.CCw + g * 8, v);
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int txp = px - dx;
+        if (txp >= 0 && txp < kWgTW) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) sX[(dx * 32 + g * 8 + i) * XS + row * kWgTW + txp] = (uint16_t)f2bf(v[i]);
+        }
+      }
+    }
+    __syncthreads();
+    for (int row = 0; row < kWgTH; ++row) {
+      bf16x8 af[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+        af[mi] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(sZ + (mi * 16 + n16) * ZS + row * kWgTW + sub * 8));
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const int kk = wave + 4 * s;
+        if (kk >= 9) continue;
+        const int dy = kk / 3, dx = kk - dy * 3;
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+          if (ni >= NI) continue;
+          const bf16x8 bf = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(sX + (dx * 32 + ni * 16 + n16) * XS + (row + dy) * kWgTW + sub * 8));
+#pragma unroll
+          for (int mi = 0; mi < 4; ++mi)
+            if (mi < MI) acc[s][mi][ni] = mfma(af[mi], bf, acc[s][mi][ni]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int kk = wave + 4 * s;
+    if (kk >= 9) continue;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+      if (mi >= MI) continue;
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        if (ni >= NI) continue;
+        const int ci = cc * a.CCw + ni * 16 + n16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int co = co0 + mi * 16 + sub * 4 + i;
+          if (co < a.Cout && ci < a.Cipw)
+            a.part[(((long long)split * a.Cout + co) * 9 + kk) * a.Cipw + ci] = acc[s][mi][ni][i];
+        }
+      }
+    }
+  }
+}
+
+// Sum the pixel-split partials into the canonical weight gradient
+// [Cout][Cin][3][3] (fixed order over the splits).
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nsplit, int Cout, int Cin,
+                                                     int Cipw, float* __restrict__ grad) {
+  const int n = Cout * Cin * 9;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int co = i / (Cin * 9), r = i - co * Cin * 9;
+    const int ci = r / 9, kk = r - ci * 9;
+    float s = 0.f;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[(((long long)sp * Cout + co) * 9 + kk) * Cipw + ci];
+    grad[i] = s;
+  }
+}
+
+// ------------------------------------------------------------ bias gradient
+// Per-block partial sums of the ReLU-masked output gradient per channel
+// (C divides 256), then a fixed-order sum over the blocks.
+__global__ __launch_bounds__(256) void k_bias_part(BiasArgs a) {
+  __shared__ float s[256];
+  const int C = a.C, tid = (int)threadIdx.x, c = tid % C, q = tid / C, Q = 256 / C;
+  float sum = 0.f;
+  for (long long p = (long long)blockIdx.x * Q + q; p < a.npix; p += (long long)gridDim.x * Q) {
+    const long long o = p * C + c;
+    float g = a.gY[o];
+    if (a.Y && !relu_on(a.Y[o])) g = 0.f;
+    sum += g;
+  }
+  s[tid] = sum;
+  __syncthreads();
+  if (tid < C) {
+    float t = 0.f;
+    for (int k = 0; k < Q; ++k) t += s[k * C + tid];
+    a.part[(long long)blockIdx.x * C + tid] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nblk, int ne,
+                                                  float* __restrict__ out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < nblk; ++k) s += part[(long long)k * ne + e];
+    out[e] = s;
+  }
+}
+
+// ------------------------------------------------------------ gradient routing
+// Adds the gradient of a convolution's input to the tensors it was built
+// from: A (same resolution; or upsampled: sum of the 2x2 block; or pooled:
+// a quarter to each of the four pixels) and the concatenated skip.
+__global__ __launch_bounds__(256) void k_route(RouteArgs a) {
+  const int Ct = a.Ca + a.Cb;
+  const int Ha = a.modeA == 1 ? a.H / 2 : (a.modeA == 2 ? a.H * 2 : a.H);
+  const int Wa = a.modeA == 1 ? a.W / 2 : (a.modeA == 2 ? a.W * 2 : a.W);
+  const long long nA = (long long)a.B * Ha * Wa * a.Ca;
+  const long long nB = a.gB ? (long long)a.B * a.H * a.W * a.Cb : 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nA + nB;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < nA) {
+      const int c = (int)(i % a.Ca);
+      const long long pa = i / a.Ca;
+      const int xa = (int)(pa % Wa);
+      const long long t = pa / Wa;
+      const int ya = (int)(t % Ha);
+      const int b = (int)(t / Ha);
+      float g;
+      if (a.modeA == 0) {
+        g = a.gX[(((long long)b * a.H + ya) * a.W + xa) * Ct + c];
+      } else if (a.modeA == 1) {
+        g = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          g += a.gX[(((long long)b * a.H + 2 * ya + (q >> 1)) * a.W + 2 * xa + (q & 1)) * Ct + c];
+      } else {
+        g = 0.25f * a.gX[(((long long)b * a.H + (ya >> 1)) * a.W + (xa >> 1)) * Ct + c];
+      }
+      a.gA[i] += g;
+    } else {
+      const long long j = i - nA;
+      const int c = (int)(j % a.Cb);
+      const long long p = j / a.Cb;
+      a.gB[j] += a.gX[p * Ct + a.Ca + c];
+    }
+  }
+}
+
+// ------------------------------------------------------------ heads
+// One pixel per thread: y_m = Wm h + bm (P channels, planar output), y_w =
+// sigmoid(Ww h + bw).  FP32 weights in LDS.
+__global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
+  extern __shared__ float shw[];
+  const int C1 = a.C1, P = a.P;
+  float* sWm = shw;             // [P][C1], then bm [P]
+  float* sWw = shw + P * C1 + P;  // [C1], then bw
+  for (int i = threadIdx.x; i < P * C1 + P; i += blockDim.x) sWm[i] = a.Wm[i];
+  for (int i = threadIdx.x; i < C1 + 1; i += blockDim.x) sWw[i] = a.Ww[i];
+  __syncthreads();
+  const long long HW = (long long)a.H * a.W, npix = a.B * HW;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  float h[32];
+  const uint16_t* hp = a.h + p * C1;
+  for (int c = 0; c < C1; c += 8) {
+    float v[8];
+    unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[c + i] = v[i];
+  }
+  const long long b = p / HW, yx = p - b * HW;
+  for (int co = 0; co < P; ++co) {
+    float s = sWm[P * C1 + co];
+    for (int c = 0; c < C1; ++c) s = fmaf(sWm[co * C1 + c], h[c], s);
+    a.y_m[(b * P + co) * HW + yx] = s;
+  }
+  float z = sWw[C1];
+  for (int c = 0; c < C1; ++c) z = fmaf(sWw[c], h[c], z);
+  a.y_w[p] = 1.0f / (1.0f + __expf(-z));
+}
+
+// Loss terms, gradient of the head input (FP32 NHWC) and per-block partial
+// sums of the head-parameter gradient and of the two squared errors.
+// Dynamic LDS: gy [256][P+1], h [256][C1+1], gz [256], Wm [P][C1], Ww [C1].
+__global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
+  extern __shared__ float sh[];
+  __shared__ double sred[2][4];
+  const HeadArgs& d = a.hd;
+  const int C1 = d.C1, P = d.P, tid = (int)threadIdx.x;
+  float* sgy = sh;
+  float* shh = sgy + 256 * (P + 1);
+  float* sgz = shh + 256 * (C1 + 1);
+  float* sWm = sgz + 256;
+  float* sWw = sWm + P * C1;
+  for (int i = tid; i < P * C1; i += 256) sWm[i] = d.Wm[i];
+  for (int i = tid; i < C1; i += 256) sWw[i] = d.Ww[i];
+  const long long HW = (long long)d.H * d.W, npix = d.B * HW;
+  const long long p = (long long)blockIdx.x * 256 + tid;
+  const float inv_m = 1.0f / (float)((double)npix * P), inv_w = 1.0f / (float)npix;
+  double lm = 0.0, lw = 0.0;
+  if (p < npix) {
+    const uint16_t* hp = d.h + p * C1;
+    for (int c = 0; c < C1; c += 8) {
+      float v[8];
+      unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) shh[tid * (C1 + 1) + c + i] = v[i];
+    }
+    const long long b = p / HW, yx = p - b * HW;
+    for (int co = 0; co < P; ++co) {
+      const long long o = (b * P + co) * HW + yx;
+      const float df = d.y_m[o] - a.t_m[o];
+      lm += (double)df * (double)df;
+      sgy[tid * (P + 1) + co] = 2.0f * df * inv_m;
+    }
+    const float yw = d.y_w[p], dw = yw - a.t_w[p];
+    lw = (double)dw * (double)dw;
+    sgz[tid] = 2.0f * a.lam_w * dw * inv_w * yw * (1.0f - yw);
+  } else {
+    for (int co = 0; co < P; ++co) sgy[tid * (P + 1) + co] = 0.f;
+    for (int c = 0; c < C1; ++c) shh[tid * (C1 + 1) + c] = 0.f;
+    sgz[tid] = 0.f;
+  }
+  __syncthreads();
+  if (p < npix) {
+    for (int c = 0; c < C1; ++c) {
+      float s = sWw[c] * sgz[tid];
+      for (int co = 0; co < P; ++co) s = fmaf(sWm[co * C1 + c], sgy[tid * (P + 1) + co], s);
+      a.g_h[p * C1 + c] = s;
+    }
+  }
+  for (int e = tid; e < a.ne; e += 256) {
+    float s = 0.f;
+    if (e < P * C1) {
+      const int co = e / C1, c = e - co * C1;
+      for (int t = 0; t < 256; ++t) s = fmaf(sgy[t * (P + 1) + co], shh[t * (C1 + 1) + c], s);
+    } else if (e < P * C1 + P) {
+      const int co = e - P * C1;
+      for (int t = 0; t < 256; ++t) s += sgy[t * (P + 1) + co];
+    } else if (e < P * C1 + P + C1) {
+      const int c = e - P * C1 - P;
+      for (int t = 0; t < 256; ++t) s = fmaf(sgz[t], shh[t * (C1 + 1) + c], s);
+    } else {
+      for (int t = 0; t < 256; ++t) s += sgz[t];
+    }
+    a.hpart[(long long)blockIdx.x * a.ne + e] = s;
+  }
+  // block sums of the squared errors (fixed order)
+  for (int off = 32; off > 0; off >>= 1) {
+    lm += __shfl_down(lm, off);
+    lw += __shfl_down(lw, off);
+  }
+  if ((tid & 63) == 0) {
+    sred[0][tid >> 6] = lm;
+    sred[1][tid >> 6] = lw;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.lpart[2 * blockIdx.x] = sred[0][0] + sred[0][1] + sred[0][2] + sred[0][3];
+    a.lpart[2 * blockIdx.x + 1] = sred[1][0] + sred[1][1] + sred[1][2] + sred[1][3];
+  }
+}
+
+// loss = sum_m / Nm + lam_w sum_w / Nw over the block partials (one block).
+__global__ __launch_bounds__(256) void k_loss_reduce(const double* __restrict__ lpart, int nblk, double Nm,
+                                                    double Nw, double lam_w, double* loss) {
+  __shared__ double s[2][256];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 256) {
+    a += lpart[2 * k];
+    b += lpart[2 * k + 1];
+  }
+  s[0][threadIdx.x] = a;
+  s[1][threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int k = 0; k < 256; ++k) {
+      ta += s[0][k];
+      tb += s[1][k];
+    }
+    *loss = ta / Nm + lam_w * tb / Nw;
+  }
+}
+
+// ------------------------------------------------------------ parameters
+__global__ __launch_bounds__(256) void k_pack(PackArgs a) {
+  const long long nf = (long long)a.f.Coutp * a.f.ncc * a.f.KKp * a.f.CC;
+  const long long nt = a.Wtp ? (long long)a.t.Coutp * a.t.ncc * a.t.KKp * a.t.CC : 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nf + nt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const bool fw = i < nf;
+    const ConvPack& P = fw ? a.f : a.t;
+    long long r = fw ? i : i - nf;
+    const int c = (int)(r % P.CC);
+    r /= P.CC;
+    const int kk = (int)(r % P.KKp);
+    r /= P.KKp;
+    const int cc = (int)(r % P.ncc);
+    const int co = (int)(r / P.ncc);
+    const int ci = cc * P.CC + c;
+    float v = 0.f;
+    if (co < P.Cout && ci < P.Cin && kk < 9) {
+      // forward: W[co][ci][kk]; transposed: output = forward input channel
+      // co, input = forward output channel ci, taps flipped
+      v = fw ? a.W[((long long)co * P.Cin + ci) * 9 + kk] : a.W[((long long)ci * P.Cout + co) * 9 + (8 - kk)];
+    }
+    (fw ? a.Wp : a.Wtp)[fw ? i : i - nf] = (uint16_t)f2bf(v);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adamw(float* __restrict__ th, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, long long n, float lr,
+                                              float b1, float b2, float eps, float wd, float bc1, float bc2) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1, vh = vi / bc2;
+    th[i] = th[i] * (1.f - lr * wd) - lr * mh / (sqrtf(vh) + eps);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_f32(float* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// ------------------------------------------------------------ launchers
+static inline unsigned grid_for(long long n, int per = 256, int cap = 8192) {
+  long long g = (n + per - 1) / per;
+  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
+  const int tiles = ((a.in.H + kConvTH - 1) / kConvTH) * ((a.in.W + kConvTW - 1) / kConvTW);
+  const dim3 grid(tiles, (a.pk.Coutp + kConvCoT - 1) / kConvCoT, a.B);
+  if (af32 && outf32) hipLaunchKernelGGL((k_conv3<true, true>), grid, dim3(256), 0, s, a);
+  else if (af32) hipLaunchKernelGGL((k_conv3<true, false>), grid, dim3(256), 0, s, a);
+  else if (outf32) hipLaunchKernelGGL((k_conv3<false, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_conv3<false, false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
+  const dim3 grid(a.nccw, (a.Cout + kWgCoT - 1) / kWgCoT, a.nsplit);
+  if (af32) hipLaunchKernelGGL((k_wgrad<true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_wgrad<false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const float* part, int nsplit, int Cout, int Cin, int Cipw, float* grad,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_for((long long)Cout * Cin * 9)), dim3(256), 0, s, part, nsplit, Cout,
+                     Cin, Cipw, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias(const BiasArgs& a, int nblk, float* gb, hipStream_t s) {
+  hipLaunchKernelGGL(k_bias_part, dim3(nblk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const float*)a.part, nblk, a.C, gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
+  const int Ha = a.modeA == 1 ? a.H / 2 : (a.modeA == 2 ? a.H * 2 : a.H);
+  const int Wa = a.modeA == 1 ? a.W / 2 : (a.modeA == 2 ? a.W * 2 : a.W);
+  const long long n = (long long)a.B * Ha * Wa * a.Ca + (a.gB ? (long long)a.B * a.H * a.W * a.Cb : 0);
+  hipLaunchKernelGGL(k_route, dim3(grid_for(n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+size_t head_fwd_lds(int P, int C1) { return (size_t)(P * C1 + P + C1 + 1) * 4; }
+size_t head_bwd_lds(int P, int C1) { return (size_t)(256 * (P + 1) + 256 * (C1 + 1) + 256 + P * C1 + C1) * 4; }
+
+hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
+  const long long npix = (long long)a.B * a.H * a.W;
+  hipLaunchKernelGGL(k_head_fwd, dim3((unsigned)((npix + 255) / 256)), dim3(256), head_fwd_lds(a.P, a.C1), s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s) {
+  const long long npix = (long long)a.hd.B * a.hd.H * a.hd.W;
+  hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), head_bwd_lds(a.hd.P, a.hd.C1), s, a);
+  hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(a.ne)), dim3(256), 0, s, (const float*)a.hpart, nblk, a.ne, ghead);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, (const double*)a.lpart, nblk,
+                     (double)npix * a.hd.P, (double)npix, lam_w, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
+  const long long n = (long long)a.f.Coutp * a.f.ncc * a.f.KKp * a.f.CC +
+                      (a.Wtp ? (long long)a.t.Coutp * a.t.ncc * a.t.KKp * a.t.CC : 0);
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adamw(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                        float eps, float wd, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adamw, dim3(grid_for(n)), dim3(256), 0, s, th, g, m, v, n, lr, b1, b2, eps, wd, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float* p, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t unet_kernels_init() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_head_bwd),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  return e;
+}
+
+}  // namespace unet

@@ -1,5 +1,5 @@
 """Host-only checks of the C ABI boundary (no GPU needed): the library loads,
-exports every function include/ashrt.h declares, validates descriptors and
+exports every function include/*.h declares, validates descriptors and
 solver settings, names its status codes, and the Python binding turns error
 codes into exceptions.  No compute call is made here."""
 import ctypes as C
@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ashrt.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +22,7 @@ def A():
 
 
 def _declared_functions():
-    src = open(HEADER).read()
+    src = "\n".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while", "for")))
@@ -30,6 +31,7 @@ def _declared_functions():
 def test_header_functions_are_exported(A):
     names = _declared_functions()
     assert "ashrt_forward" in names and "robust_invert" in names and "robust_invert_batched" in names
+    assert "unet_forward" in names and "unet_train_step" in names
     lib = A.lib()
     for n in names:
         assert hasattr(lib, n), n
@@ -126,3 +128,17 @@ def test_plan_create_fails_cleanly_without_gpu(A):
     with pytest.raises(A.AshrtError) as ei:
         A.Plan(256, 64, 0.004, 12.5, [1500.0] * 8, fmax=100.0)
     assert ei.value.status == A._lib.ASHRT_E_HIP
+
+
+def test_unet_entry_points_reject_bad_arguments_without_gpu(A):
+    lib = A.lib()
+    L = A._lib
+    out = C.c_void_p()
+    assert lib.unet_create(None, 0, C.byref(out)) == L.ASHRT_E_INVALID_ARG
+    bad = L.UnetDesc(2, 8, 16)
+    assert lib.unet_create(C.byref(bad), 0, C.byref(out)) == L.ASHRT_E_UNSUPPORTED_SIZE
+    bad = L.UnetDesc(1, 8, 12)
+    assert lib.unet_create(C.byref(bad), 0, C.byref(out)) == L.ASHRT_E_UNSUPPORTED_SIZE
+    assert lib.unet_param_count(None) == -1
+    n = C.c_size_t()
+    assert lib.unet_workspace_bytes(None, 1, 16, 16, 0, C.byref(n)) == L.ASHRT_E_INVALID_ARG
