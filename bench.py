@@ -112,6 +112,91 @@ def cpu_baseline(w, gth, budget_s=25.0):
     }
 
 
+def _gen_gather(args):
+    from synth import make_gather, workload
+    name, seed = args
+    g = make_gather(workload(name), seed=seed)
+    return g.d_blend.astype("float32"), g.d_clean
+
+
+def run_warmstart(args):
+    """Learned warm start against the plain zero start on the same GPU: CG
+    iterations and wall time to reach the plain method's final separated-
+    signal SNR (minus 0.05 dB) on held-out gathers drawn like the
+    production gather."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    base = "crg-1024x256-nv32"
+    n_train, n_held = args.train_gathers, args.heldout_gathers
+    t0 = time.perf_counter()
+    # draw the gathers on host worker processes before the GPU is touched
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        train = [g for g, _ in ex.map(_gen_gather, [(base, 1_000_000 + i) for i in range(n_train)])]
+        held = list(ex.map(_gen_gather, [(base, 2_000_000 + i) for i in range(n_held)]))
+    t_gen = time.perf_counter() - t0
+    import torch
+    import paper_1711_10214_amd as A
+    from paper_1711_10214_amd import warmstart as WS
+    from synth import workload
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    w = workload(base)
+    plan = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
+    prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
+    print(f"[bench] warm start: labelling {n_train} gathers", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lab = WS.make_labels(plan, train, prm)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    net = A.UNet(w.npanel, base=16)
+    net.init_params(seed=0)
+    print(f"[bench] warm start: training {args.epochs} epochs", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    losses = WS.train(net, lab, epochs=args.epochs, batch=args.batch, tp=A.TrainParams(lr=1e-3), seed=0,
+                      log_every=max(1, n_train // args.batch))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del lab
+    # one warm-up of each path
+    d0 = torch.tensor(held[0][0], device="cuda")
+    WS.outer_to_target(plan, d0, held[0][1], 1e9, prm, max_outer=1)
+    WS.outer_to_target(plan, d0, held[0][1], 1e9, prm, net=net, max_outer=1)
+    rows = []
+    for i, (g, clean) in enumerate(held):
+        d = torch.tensor(g, device="cuda")
+        _, d_rec, _ = plan.robust_invert(d, prm, want_report=False)
+        target = WS.q_db(clean, d_rec.cpu().numpy())
+        kp, qp, tp_, _ = WS.outer_to_target(plan, d, clean, target, prm)
+        kw, qw, tw, start = WS.outer_to_target(plan, d, clean, target, prm, net=net)
+        rows.append((target, kp, tp_, kw, tw, start, qw))
+        if i % 16 == 0:
+            print(f"[bench] held-out {i}: target {target:.2f} dB plain k={kp} warm k={kw} ({start})",
+                  file=sys.stderr, flush=True)
+    kp = np.array([r[1] or 99 for r in rows], float)
+    kw = np.array([r[3] or 99 for r in rows], float)
+    tp_ = np.array([r[2] for r in rows])
+    tw = np.array([r[4] for r in rows])
+    reached = sum(r[3] is not None for r in rows)
+    rec = {
+        "metric": "learned warm start: wall time to the plain IRLS-CG separated-signal SNR, plain / warm",
+        "value": float(np.mean(tp_) / np.mean(tw)),
+        "unit": "x (speed-up of time-to-SNR)",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16 network, f32 solver",
+        "data": "synthetic",
+        "config": {"workload": "warmstart-crg-1024x256-nv32", "train_gathers": n_train,
+                   "heldout_gathers": n_held, "epochs": args.epochs, "batch": args.batch,
+                   "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner},
+        "plain": {"cg_iterations_mean": float(np.mean(kp) * w.n_inner), "outer_median": float(np.median(kp)),
+                  "ms_mean": float(np.mean(tp_) * 1e3)},
+        "warm": {"cg_iterations_mean": float(np.mean(kw) * w.n_inner), "outer_median": float(np.median(kw)),
+                 "ms_mean": float(np.mean(tw) * 1e3), "reached_target": reached,
+                 "model_start_rate": float(np.mean([r[5] == "model+weights" for r in rows]))},
+        "seconds": {"generate": t_gen, "label": t_lab, "train": t_train},
+        "train_loss": [losses[0], losses[-1]] if losses else None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +207,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB device copy (for HBM counter calibration)")
+    ap.add_argument("--train-gathers", type=int, default=1024, help="warm-start workload: training gathers")
+    ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
+    ap.add_argument("--epochs", type=int, default=12, help="warm-start workload: training epochs")
+    ap.add_argument("--batch", type=int, default=4, help="warm-start workload: batch size")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -129,6 +218,9 @@ def main():
               "multi-GPU path (gathers are independent; see the sharding notes). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload.startswith("warmstart"):
+        return run_warmstart(args)
 
     import numpy as np
     import torch

@@ -103,9 +103,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and L is not None and L._lib is not None:
             L.lib().ashrt_plan_destroy(h)
-            self._h = None
+        self._h = None
 
     # ---------------------------------------------------------------- workspace
     def workspace_bytes(self, op, params: Optional[Params] = None):
@@ -207,9 +207,9 @@ class BatchPlan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and L is not None and L._lib is not None:
             L.lib().ashrt_batch_plan_destroy(h)
-            self._h = None
+        self._h = None
 
     def workspace(self, op, params: Optional[Params] = None):
         n = C.c_size_t()

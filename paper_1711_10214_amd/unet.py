@@ -49,13 +49,29 @@ class UNet:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and L is not None and L._lib is not None:
             L.lib().unet_destroy(h)
-            self._h = None
+        self._h = None
 
     def set_params(self, theta):
         a = np.ascontiguousarray(np.asarray(theta, np.float32).ravel())
         L.check(L.lib().unet_set_params(self._h, a.ctypes.data_as(C.c_void_p), a.size), "unet_set_params")
+
+    def init_params(self, seed=0):
+        """He-normal weights (fan-in), zero biases, drawn on the host."""
+        rng = np.random.default_rng(seed)
+        c1, c2, c3, c4 = (self.base * f for f in (1, 2, 4, 8))
+        convs = [(self.cin, c1, 3), (c1, c1, 3), (c1, c2, 3), (c2, c2, 3), (c2, c3, 3), (c3, c3, 3),
+                 (c3, c4, 3), (c4, c4, 3), (c4 + c3, c3, 3), (c3, c3, 3), (c3 + c2, c2, 3), (c2, c2, 3),
+                 (c2 + c1, c1, 3), (c1, c1, 3), (c1, self.pout, 1), (c1, 1, 1)]
+        parts = []
+        for ci, co, k in convs:
+            parts.append(rng.standard_normal(co * ci * k * k) * np.sqrt(2.0 / (ci * k * k)))
+            parts.append(np.zeros(co))
+        theta = np.concatenate(parts)
+        assert theta.size == self.n_params
+        self.set_params(theta)
+        return theta
 
     def get_params(self):
         a = np.empty(self.n_params, np.float32)
