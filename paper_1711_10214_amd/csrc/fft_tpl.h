@@ -111,9 +111,29 @@ __device__ __forceinline__ void dft_r(float2 (&v)[R]) {
   else butterfly<R, INV>(v);
 }
 
+// Pair layout of a length-N spectrum whose bins 0 and N/2 are not needed:
+// pair k (1 <= k < N/2) holds bin k at float2 slot 2k and bin N-k at slot
+// 2k+1, so a map that touches both mirror bins of k reads 16 bytes at once.
+// The pairs occupy the first N float2 slots of the transform's buffer.
+template <int N>
+__device__ __forceinline__ float2 pair_get(const float2* buf, int i) {
+  if (i == 0 || i == N / 2) return make_float2(0.f, 0.f);
+  return i < N / 2 ? buf[2 * i] : buf[2 * (N - i) + 1];
+}
+
+template <int N>
+__device__ __forceinline__ void pair_put(float2* buf, int o, float2 v) {
+  if (o == 0 || o == N / 2) return;
+  if (o < N / 2) buf[2 * o] = v;
+  else buf[2 * (N - o) + 1] = v;
+}
+
 // One pass of a batch of nb transforms (nb * N <= NBN) at buf + b*bstride,
-// run by a workgroup of NT threads.
-template <int N, int PASS, int NBN, bool INV, int NT = kThreads>
+// run by a workgroup of NT threads.  IO = 1: this pass reads its input from
+// the pair layout; IO = 2: it writes its output in the pair layout (bins 0
+// and N/2 dropped); IO = 0: padded layout both ways.  Reads complete before
+// the barrier and writes follow it, so the layouts may share memory.
+template <int N, int PASS, int NBN, bool INV, int NT = kThreads, int IO = 0>
 __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const float2* twp) {
   using P = FftPlan<N>;
   constexpr int R = P::radix(PASS);
@@ -135,7 +155,10 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
       const int jm = j - jq * Ns;
       const float2* src = buf + b * bstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[fft_pad(j + r * B)];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (IO == 1) v[i][r] = pair_get<N>(src, j + r * B);
+        else v[i][r] = src[fft_pad(j + r * B)];
+      }
       if constexpr (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -154,17 +177,24 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
   for (int i = 0; i < MAXB; ++i) {
     if (dst[i] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (IO == 2) pair_put<N>(buf + dst[i], bq[i] + r * Ns, v[i][r]);
+        else buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+      }
     }
   }
   __syncthreads();
 }
 
-template <int N, int PASS, int NBN, bool INV, int NT>
+// PAIRS_IN: the first pass reads the pair layout; PAIRS_OUT: the last pass
+// writes it.
+template <int N, int PASS, int NBN, bool INV, int NT, bool PAIRS_IN = false, bool PAIRS_OUT = false>
 __device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, const float2* twp) {
   if constexpr (PASS < FftPlan<N>::npass) {
-    tpl_pass<N, PASS, NBN, INV, NT>(buf, nb, bstride, twp);
-    tpl_passes<N, PASS + 1, NBN, INV, NT>(buf, nb, bstride, twp);
+    constexpr int IO = (PAIRS_IN && PASS == 0) ? 1 : ((PAIRS_OUT && PASS == FftPlan<N>::npass - 1) ? 2 : 0);
+    static_assert(!(PAIRS_IN && PAIRS_OUT && FftPlan<N>::npass == 1), "pair input and output need two passes");
+    tpl_pass<N, PASS, NBN, INV, NT, IO>(buf, nb, bstride, twp);
+    tpl_passes<N, PASS + 1, NBN, INV, NT, PAIRS_IN, PAIRS_OUT>(buf, nb, bstride, twp);
   }
 }
 
@@ -172,6 +202,19 @@ __device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, con
 template <int N, int NBN, bool INV, int NT = kThreads>
 __device__ __forceinline__ void fft_tpl(float2* buf, int nb, int bstride, const float2* twp) {
   tpl_passes<N, 0, NBN, INV, NT>(buf, nb, bstride, twp);
+}
+
+// One transform of length N whose output is left in the pair layout.
+template <int N, bool INV, int NT>
+__device__ __forceinline__ void fft_tpl_to_pairs(float2* buf, const float2* twp) {
+  tpl_passes<N, 0, N, INV, NT, false, true>(buf, 1, fft_padlen(N), twp);
+}
+
+// One transform of length N whose input is read from the pair layout (bins
+// 0 and N/2 taken as zero); the output is in the padded layout.
+template <int N, bool INV, int NT>
+__device__ __forceinline__ void fft_tpl_from_pairs(float2* buf, const float2* twp) {
+  tpl_passes<N, 0, N, INV, NT, true, false>(buf, 1, fft_padlen(N), twp);
 }
 
 }  // namespace ashrt

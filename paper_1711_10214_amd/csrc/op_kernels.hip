@@ -410,25 +410,85 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
 }
 
 // ------------------------------------------------------------ rows: shared steps
+// Natural (unpadded, generic-length) layout <-> pair layout (fft_tpl.h),
+// in place: every thread first reads its bins, then all write.
+template <int NT>
+__device__ __forceinline__ void natural_to_pairs(float2* buf, int n) {
+  constexpr int MAXK = (kRowMaxN / 2 + NT - 1) / NT;
+  float2 a[MAXK], b[MAXK];
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    const int k = 1 + (int)threadIdx.x + i * NT;
+    if (k < n / 2) {
+      a[i] = buf[k];
+      b[i] = buf[n - k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    const int k = 1 + (int)threadIdx.x + i * NT;
+    if (k < n / 2) {
+      buf[2 * k] = a[i];
+      buf[2 * k + 1] = b[i];
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ void pairs_to_natural(float2* buf, int n) {
+  constexpr int MAXK = (kRowMaxN / 2 + NT - 1) / NT;
+  float2 a[MAXK], b[MAXK];
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    const int k = 1 + (int)threadIdx.x + i * NT;
+    if (k < n / 2) {
+      a[i] = buf[2 * k];
+      b[i] = buf[2 * k + 1];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    const int k = 1 + (int)threadIdx.x + i * NT;
+    if (k < n / 2) {
+      buf[k] = a[i];
+      buf[n - k] = b[i];
+    }
+  }
+  if (threadIdx.x == 0) {
+    buf[0] = make_float2(0.f, 0.f);
+    buf[n / 2] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+}
+
 // Load row r of a [nrows][nt] complex field into buf[0..nt), zero to ntp,
-// forward time FFT, and for row 0 separate the packed kx = 0 / Nyquist
-// spectra: slot k gets the kx = 0 spectrum, slot ntp-k the conjugate of the
-// Nyquist one, so that both rows read "up = buf[k], lo = conj(buf[ntp-k])".
+// forward time FFT, leaving the spectrum in the pair layout: pair k holds
+// (Q[k], Q[ntp-k]).  Rows >= 1 then read "up = Q[k], lo = conj Q[ntp-k]"
+// (the +l and -l spectra); row 0 separates the packed kx = 0 / Nyquist
+// spectra so that the same reading gives them.
 template <int N, int NT>
 __device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restrict__ src, int r, int nt,
                                              int ntp, const float2* twl) {
   for (int t = threadIdx.x; t < ntp; t += NT) buf[px<N>(t)] = (t < nt) ? src[t] : make_float2(0.f, 0.f);
   __syncthreads();
-  if constexpr (N > 0) fft_tpl<N, N, false, NT>(buf, 1, fft_padlen(N), twl);
-  else fft_lds<NT, kRowMaxN, false>(buf, ntp, 1, ntp, twl);
+  if constexpr (N > 0) {
+    fft_tpl_to_pairs<N, false, NT>(buf, twl);
+  } else {
+    fft_lds<NT, kRowMaxN, false>(buf, ntp, 1, ntp, twl);
+    natural_to_pairs<NT>(buf, ntp);
+  }
   if (r == 0) {
+    float4* P = reinterpret_cast<float4*>(buf);
     for (int k = 1 + threadIdx.x; k < ntp / 2; k += NT) {
-      const float2 a = buf[px<N>(k)];
-      const float2 b = cconj(buf[px<N>(ntp - k)]);
+      const float4 q = P[k];
+      const float2 a = make_float2(q.x, q.y);
+      const float2 b = make_float2(q.z, -q.w);
       const float2 m0 = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       const float2 m1 = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
-      buf[px<N>(k)] = m0;
-      buf[px<N>(ntp - k)] = cconj(m1);
+      P[k] = make_float4(m0.x, m0.y, m1.x, -m1.y);
     }
     __syncthreads();
   }
@@ -438,6 +498,18 @@ template <int N, int NT>
 __device__ __forceinline__ void row_inverse(float2* buf, int ntp, const float2* twl) {
   if constexpr (N > 0) fft_tpl<N, N, true, NT>(buf, 1, fft_padlen(N), twl);
   else fft_lds<NT, kRowMaxN, true>(buf, ntp, 1, ntp, twl);
+}
+
+// Inverse time FFT of a spectrum held in the pair layout (bins 0 and ntp/2
+// zero); the output is in the transform's usual layout.
+template <int N, int NT>
+__device__ __forceinline__ void row_inverse_from_pairs(float2* buf, int ntp, const float2* twl) {
+  if constexpr (N > 0) {
+    fft_tpl_from_pairs<N, true, NT>(buf, twl);
+  } else {
+    pairs_to_natural<NT>(buf, ntp);
+    fft_lds<NT, kRowMaxN, true>(buf, ntp, 1, ntp, twl);
+  }
 }
 
 // ------------------------------------------------------------ forward rows
@@ -457,6 +529,7 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
   float2* twl = lds;
   float2* buf = lds + ntp;
   float2* acc = buf + plen;
+  const float4* P4 = reinterpret_cast<const float4*>(buf);  // row spectrum, pair layout
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
   for (int i = threadIdx.x; i < 2 * nband; i += NT) acc[i] = make_float2(0.f, 0.f);
   const int lu = (r == 0) ? 0 : r;
@@ -481,8 +554,9 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
             const int kc = ok ? k : 1;
             float wt = tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]);
             wt = ok ? wt : 0.f;
-            au = cfma(wt, buf[px<N>(kc)], au);
-            al = cfma(wt, cconj(buf[px<N>(ntp - kc)]), al);
+            const float4 q = P4[kc];
+            au = cfma(wt, make_float2(q.x, q.y), au);
+            al = cfma(wt, make_float2(q.z, -q.w), al);
           }
         }
       } else {
@@ -491,16 +565,20 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 #pragma unroll
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tu.k0 + t;
-            if (k >= 1 && k <= hmax)
-              au = cfma(tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]), buf[px<N>(k)], au);
+            if (k >= 1 && k <= hmax) {
+              const float4 q = P4[k];
+              au = cfma(tap_weight(tu.trig, t, ctab[t + R - 1], stab[t + R - 1]), make_float2(q.x, q.y), au);
+            }
           }
         }
         if (tl.k0 != kNoTap) {
 #pragma unroll
           for (int t = -R + 1; t <= R; ++t) {
             const int k = tl.k0 + t;
-            if (k >= 1 && k <= hmax)
-              al = cfma(tap_weight(tl.trig, t, ctab[t + R - 1], stab[t + R - 1]), cconj(buf[px<N>(ntp - k)]), al);
+            if (k >= 1 && k <= hmax) {
+              const float4 q = P4[k];
+              al = cfma(tap_weight(tl.trig, t, ctab[t + R - 1], stab[t + R - 1]), make_float2(q.z, -q.w), al);
+            }
           }
         }
       }
@@ -596,7 +674,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd_fin(RowsArgs A) {
 //   taking the taps in order, never collide within a tap, and the LDS
 //   operations of one wave complete in issue order, so the read-modify-write
 //   of tap t+1 sees that of tap t (a wave barrier keeps the compiler from
-//   reordering them);
+//   reordering them); the model spectrum is kept in the pair layout, so
+//   one 16-byte read-modify-write updates bins k and ntp - k together;
 // * a wave owns a 64-bin segment of the band; two segments with a full
 //   segment between them (64 >= 2R - 1 bins) touch disjoint model bins, so
 //   even segments run first, then a barrier, then odd ones.
@@ -642,7 +721,7 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
   for (int p = p0; p < p1; ++p) {
     const PanelDev PD = A.panels[G.panel_off + p];
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
-    for (int k = threadIdx.x; k < plen; k += NT) bufM[k] = make_float2(0.f, 0.f);
+    for (int k = threadIdx.x; k < ntp / 2; k += NT) reinterpret_cast<float4*>(bufM)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     for (int pass = 0; pass < npass; ++pass) {
       const int l = (r == 0) ? (pass == 0 ? 0 : nrows) : r;
@@ -658,8 +737,9 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
               // wgt * e1 at k and wgt * e2 at ntp - k of the model spectrum:
               //   rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l)
               //   row 0:     Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
-              float2 du = bufD[px<N>(j)];
-              float2 dl = cconj(bufD[px<N>(ntp - j)]);
+              const float4 dq = reinterpret_cast<const float4*>(bufD)[j];
+              float2 du = make_float2(dq.x, dq.y);
+              float2 dl = make_float2(dq.z, -dq.w);
               if (plain) {
                 du = cscale(du, PD.scale);
                 dl = cscale(dl, PD.scale);
@@ -685,10 +765,13 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
                 if (k >= 1 && k <= hmax) {
                   const float wt = RC > 0 ? tap_weight(T.trig, t, cr[(t + R - 1) % (2 * RT)], sr[(t + R - 1) % (2 * RT)])
                                           : tap_weight(T.trig, t, ctab[t + R - 1], stab[t + R - 1]);
-                  float2* q1 = bufM + px<N>(k);
-                  float2* q2 = bufM + px<N>(ntp - k);
-                  *q1 = cfma(wt, e1, *q1);
-                  *q2 = cfma(wt, e2, *q2);
+                  float4* q = reinterpret_cast<float4*>(bufM) + k;
+                  float4 v = *q;
+                  v.x = fmaf(wt, e1.x, v.x);
+                  v.y = fmaf(wt, e1.y, v.y);
+                  v.z = fmaf(wt, e2.x, v.z);
+                  v.w = fmaf(wt, e2.y, v.w);
+                  *q = v;
                 }
                 __builtin_amdgcn_wave_barrier();
               }
@@ -698,7 +781,7 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
         __syncthreads();
       }
     }
-    row_inverse<N, NT>(bufM, ntp, twl);
+    row_inverse_from_pairs<N, NT>(bufM, ntp, twl);
     const float inv_n = 1.0f / (float)ntp;
     float2* __restrict__ dst = A.X + G.X_off + ((long long)p * nrows + r) * nt;
     for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(bufM[px<N>(t)], inv_n);
