@@ -382,7 +382,8 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
       tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
     }
     // pass table of the compile-time FFT: per pass (radix R, span Ns) the
-    // twiddles exp(-2 pi i r jm / (Ns R)) laid out [r-1][jm]
+    // base twiddles exp(-2 pi i jm / (Ns R)), jm = 0..Ns-1 (the kernels take
+    // the powers r = 2..R-1 by recurrence)
     twp_off[i] = (int)tw.size();
     const int want = fft_tpl_twsize(N);
     if (want > 0) {
@@ -400,11 +401,10 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
       int Ns = 1;
       const size_t start = tw.size();
       for (int R : radices) {
-        for (int r = 1; r < R; ++r)
-          for (int jm = 0; jm < Ns; ++jm) {
-            const double a = -2.0 * M_PI * (double)r * (double)jm / ((double)Ns * (double)R);
-            tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
-          }
+        for (int jm = 0; jm < Ns; ++jm) {
+          const double a = -2.0 * M_PI * (double)jm / ((double)Ns * (double)R);
+          tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+        }
         Ns *= R;
       }
       if ((int)(tw.size() - start) != want || Ns != N)
@@ -471,17 +471,23 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   // LDS bytes of each kernel family for one gather
   // (padded FFT buffers: fft_padlen slots; x columns at an odd slot stride)
   auto xstride = [](const GatherHost& gh) { return (size_t)(fft_padlen(gh.z.nxp) | 1); };
+  auto twx_of = [](const GatherHost& gh) {
+    return (size_t)fft_tw_slots(x_size_is_tpl(gh.z.nxp) ? gh.z.nxp : 0, gh.z.nxp);
+  };
+  auto twt_of = [](const GatherHost& gh) {
+    return (size_t)fft_tw_slots(rows_size_is_tpl(gh.z.ntp, gh.z.R) ? gh.z.ntp : 0, gh.z.ntp);
+  };
   auto lds_x_of = [&](const GatherHost& gh) {
-    return (size_t)gh.z.nxp * 8 + (size_t)(gh.tileT / 2) * xstride(gh) * 8;
+    return twx_of(gh) * 8 + (size_t)(gh.tileT / 2) * xstride(gh) * 8;
   };
   auto lds_xd_of = [&](const GatherHost& gh) {
-    return (size_t)gh.z.nxp * 8 + (size_t)(gh.tileTd / 2) * xstride(gh) * 8;
+    return twx_of(gh) * 8 + (size_t)(gh.tileTd / 2) * xstride(gh) * 8;
   };
   auto nband_of = [](const GatherHost& gh) { return (size_t)(gh.z.jhi - gh.z.jlo + 1); };
   auto plen_of = [](const GatherHost& gh) { return (size_t)fft_padlen(gh.z.ntp); };
-  auto lds_rf_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + plen_of(gh)) * 8 + nband_of(gh) * 16; };
-  auto lds_fin_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + plen_of(gh)) * 8; };
-  auto lds_ra_of = [&](const GatherHost& gh) { return ((size_t)gh.z.ntp + 2 * plen_of(gh)) * 8; };
+  auto lds_rf_of = [&](const GatherHost& gh) { return (twt_of(gh) + plen_of(gh)) * 8 + nband_of(gh) * 16; };
+  auto lds_fin_of = [&](const GatherHost& gh) { return (twt_of(gh) + plen_of(gh)) * 8; };
+  auto lds_ra_of = [&](const GatherHost& gh) { return (twt_of(gh) + 2 * plen_of(gh)) * 8; };
   // work lists grouped by kernel instantiation; a gather's items stay contiguous
   auto build_segments = [&](const std::vector<int>& keys, std::vector<PlanImpl::Seg>& segs,
                             std::vector<WorkItem>& items, auto&& add_items, auto&& lds_of) {

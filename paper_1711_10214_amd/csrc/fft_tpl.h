@@ -8,11 +8,11 @@
 // Elements live at padded LDS positions fft_pad(i) = i + i/16 (one 8-byte
 // gap every 128 bytes), which makes the strided writes of the first passes
 // hit distinct banks; a padded transform occupies fft_padlen(N) slots.
-// Its twiddles w^(r jm), r = 1..R-1, jm = 0..Ns-1, are stored [r-1][jm]
-// (consecutive jm for a fixed r, so a wave reads consecutive LDS words) at
-// FftPlan<N>::twoff(i) in a per-length "pass table" built in FP64 on the
-// host.  Each pass reads its butterflies into registers, waits at a barrier,
-// and writes the outputs in place.
+// Its twiddles w^(r jm), r = 1..R-1, jm = 0..Ns-1, come from one tabulated
+// w^jm per butterfly (FftPlan<N>::twoff(i) + jm in a per-length "pass
+// table" built in FP64 on the host) by complex multiplication.  Each pass
+// reads its butterflies into registers, waits at a barrier, and writes the
+// outputs in place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -53,11 +53,16 @@ struct FftPlan {
   }
   static constexpr int twoff(int i) {
     int o = 0;
-    for (int k = 0; k < i; ++k) o += ns(k) * (radix(k) - 1);
+    for (int k = 0; k < i; ++k) o += ns(k);
     return o;
   }
   static constexpr int twsize() { return twoff(npass); }
 };
+
+// LDS slots of the staged twiddles in front of an FFT buffer: the pass
+// table rounded up to an even count (what follows stays 16-byte aligned), or
+// the plain n-entry table of the generic runtime FFT (key 0).
+inline __host__ __device__ int fft_tw_slots(int key, int n);
 
 // Host and device: pass-table length for a runtime N of a supported size
 // (0 for lengths handled by the generic runtime FFT).
@@ -71,6 +76,8 @@ inline __host__ __device__ int fft_tpl_twsize(int n) {
 #undef ASHRT_TW_CASE
   return 0;
 }
+
+inline __host__ __device__ int fft_tw_slots(int key, int n) { return key > 0 ? (fft_tpl_twsize(key) + 1) & ~1 : n; }
 
 
 template <bool INV>
@@ -160,11 +167,14 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
         else v[i][r] = src[fft_pad(j + r * B)];
       }
       if constexpr (Ns > 1) {
+        // w^r by recurrence from the tabulated w = exp(-+2 pi i jm / (Ns R))
+        float2 w1 = twp[TW + jm];
+        if (INV) w1.y = -w1.y;
+        float2 w = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = twp[TW + (r - 1) * Ns + jm];
-          if (INV) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
         }
       }
       dft_r<R, INV>(v[i]);

@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     const int T = A.is_model ? G.tileT : G.tileTd, half = T >> 1;
     const int bs = ((NX > 0 ? fft_padlen(nxp) : nxp) | 1);  // odd slot stride between columns
     const int t0 = w.b * T;
-    float2* twl = lds;          // x twiddles (at most nxp entries)
-    float2* buf = lds + nxp;    // T/2 packed column pairs, odd slot stride bs
+    float2* twl = lds;                          // x twiddles
+    float2* buf = lds + fft_tw_slots(NX, nxp);  // T/2 packed column pairs, odd slot stride bs
     stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
     const float* __restrict__ src = A.src + fbase;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const int t0 = w.b * T;
     const float2* __restrict__ src = A.src + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
     float2* twl = lds;
-    float2* buf = lds + nxp;
+    float2* buf = lds + fft_tw_slots(NX, nxp);
     stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
 
     for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
@@ -527,7 +527,7 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
   const int hmax = ntp / 2 - 1;
   const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
-  float2* buf = lds + ntp;
+  float2* buf = lds + fft_tw_slots(N, ntp);
   float2* acc = buf + plen;
   const float4* P4 = reinterpret_cast<const float4*>(buf);  // row spectrum, pair layout
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
@@ -624,7 +624,7 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
   const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows;
   const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
   float2* twl = lds;
-  float2* buf = lds + ntp;
+  float2* buf = lds + fft_tw_slots(N, ntp);
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
   for (int k = threadIdx.x; k < ntp; k += NT) {
     float2 v = make_float2(0.f, 0.f);
@@ -699,7 +699,7 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
   const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
   const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
-  float2* bufD = lds + ntp;
+  float2* bufD = lds + fft_tw_slots(N, ntp);
   float2* bufM = bufD + plen;
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
 
