@@ -119,3 +119,40 @@ def test_linearity_and_zero(A):
     lhs = plan.forward(a + 2 * b).cpu().numpy()
     rhs = (plan.forward(a) + 2 * plan.forward(b)).cpu().numpy()
     assert rel_l2(lhs, rhs) < 1e-6
+
+
+def test_aashrt_full_size_matches_stored_oracle_samples(A):
+    """The asymptote-shifted workload at full size (1024 x 256, 24 velocities
+    x 16 asymptote shifts = 384 panels, half the traces decimated): forward
+    and adjoint of seeded Gaussian inputs against the FP64 oracle's outputs
+    stored by tests/golden/make_oracle_values.py --operator (norms and 512
+    sampled values each; the oracle needs ~20 s for the pair, too slow to run
+    inside the test)."""
+    import json
+    import os
+    import torch
+    from synth import make_gather, random_data, random_model, workload
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_operator_samples.json")))
+    for name in ("aashrt-1024x256-nv24x16", "crg-1024x256-nv32"):
+        ref = gold[name]
+        w = workload(name)
+        gth = make_gather(w)
+        print(f"[gpu] full-size operator vs stored oracle samples case={name}", flush=True)
+        plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
+                      half_width=w.half_width)
+        mask = torch.tensor(gth.mask, device="cuda") if w.decimate_frac > 0 else None
+        rng = np.random.default_rng(ref["input_seed"])
+        m = random_model(rng, w.npanel, gth.nx, gth.nt, np.float32)
+        d = random_data(rng, gth.nx, gth.nt, np.float32)
+        # FP64 copies: a norm over 1e8 values needs an FP64 accumulator
+        fwd = plan.forward(torch.tensor(m, device="cuda"), mask=mask).cpu().numpy().ravel().astype(np.float64)
+        adj = plan.adjoint(torch.tensor(d, device="cuda"), mask=mask).cpu().numpy().ravel().astype(np.float64)
+        for out, key in ((fwd, "forward"), (adj, "adjoint")):
+            e_norm = abs(np.linalg.norm(out) / ref[f"{key}_norm"] - 1.0)
+            idx = np.asarray(ref[f"{key}_index"])
+            sv = np.asarray(ref[f"{key}_value"])
+            e_s = rel_l2(out[idx], sv)
+            print(f"  {key}: norm rel err {e_norm:.2e}, sampled rel-L2 {e_s:.2e}", flush=True)
+            assert e_norm <= TOL
+            # 512 samples estimate the whole-output relative L2 error
+            assert e_s <= 3 * TOL
