@@ -156,6 +156,68 @@ def _gen_gather(args):
     return g.d_blend.astype("float32"), g.d_clean
 
 
+def _gen_batch_gather(args):
+    from synth import make_gather, workload
+    name, nt, nx, seed = args
+    g = make_gather(workload(name), seed=seed, nt=nt, nx=nx)
+    return g.d_blend.astype("float32"), g.d_clean.astype("float32")
+
+
+def run_batch(args):
+    """The batched workload: 512 receiver gathers of uneven size (nx in
+    96..320, nt in {1024, 1536, 2048}, 24 velocities) solved together by
+    robust_invert_batched (every stage one launch per FFT size class)."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    from synth import batch_shapes, workload
+    w = workload(args.workload)
+    n = args.batch_gathers
+    shapes = batch_shapes(n, w.seed)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        gathers = list(ex.map(_gen_batch_gather, [(w.name, nt, nx, s) for nt, nx, s in shapes]))
+    t_gen = time.perf_counter() - t0
+    import torch
+    import paper_1711_10214_amd as A
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    descs = [dict(nt=nt, nx=nx, dt=w.dt, dx=w.dx, vel=list(w.vel), fmax=w.fmax, half_width=w.half_width)
+             for nt, nx, _ in shapes]
+    plan = A.BatchPlan(descs)
+    d = plan.pack_data([g for g, _ in gathers])
+    prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
+    print(f"[bench] batch of {n} gathers: model {plan.model_total * 4 / 2**30:.1f} GiB, "
+          f"data {plan.data_total * 4 / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    for _ in range(max(args.warmup, 0)):
+        plan.robust_invert(d, prm, want_report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(args.steps):
+        out = plan.robust_invert(d, prm, want_report=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, drec, _ = out
+    q = []
+    for gi, (g, clean) in enumerate(gathers):
+        rec = plan.unpack_data(drec, gi).cpu().numpy()
+        q.append((_q_db(clean, rec), _q_db(clean, g)))
+    q = np.array(q)
+    rec = {
+        "metric": "robust ASHRT gathers solved/s (batched, IRLS-CG 10x20, l1 misfit)",
+        "value": n * args.steps / wall, "unit": "gathers/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "gathers": n, "npanel": w.npanel, "n_outer": w.n_outer,
+                   "n_inner": w.n_inner, "nt_set": sorted(set(s[0] for s in shapes)),
+                   "nx_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)],
+                   "model_gib": plan.model_total * 4 / 2**30, "reductions": "f64"},
+        "snr": {"q_r_db_mean": float(q[:, 0].mean()), "q_pd_db_mean": float(q[:, 1].mean()),
+                "improved": int((q[:, 0] > q[:, 1]).sum())},
+        "seconds_generate": t_gen,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def run_warmstart(args):
     """Learned warm start against the plain zero start on the same GPU: CG
     iterations and wall time to reach the plain method's final separated-
@@ -248,6 +310,7 @@ def main():
     ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
     ap.add_argument("--epochs", type=int, default=12, help="warm-start workload: training epochs")
     ap.add_argument("--batch", type=int, default=4, help="warm-start workload: batch size")
+    ap.add_argument("--batch-gathers", type=int, default=512, help="batched workload: number of gathers")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -258,6 +321,8 @@ def main():
 
     if args.workload.startswith("warmstart"):
         return run_warmstart(args)
+    if args.workload.startswith("batch"):
+        return run_batch(args)
 
     import numpy as np
     import torch
