@@ -311,6 +311,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=12, help="warm-start workload: training epochs")
     ap.add_argument("--batch", type=int, default=4, help="warm-start workload: batch size")
     ap.add_argument("--batch-gathers", type=int, default=512, help="batched workload: number of gathers")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling rule")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -337,8 +338,10 @@ def main():
     gth = make_gather(w)
     print(f"[bench] workload {w.name}: nt={gth.nt} nx={gth.nx} P={w.npanel} "
           f"{w.n_outer}x{w.n_inner} p={w.p} q={w.q}", file=sys.stderr, flush=True)
+    # tiling chosen by the library's autotuner (timed forward + adjoint pairs)
     plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
-                  half_width=w.half_width, device=0)
+                  half_width=w.half_width, device=0, tuning=None if args.no_autotune else "auto")
+    print(f"[bench] tiling {plan.tuning}", file=sys.stderr, flush=True)
     d = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
     mask = None if w.decimate_frac == 0 else torch.tensor(gth.mask, device=dev)
     prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
@@ -467,6 +470,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "nt": gth.nt, "nx": gth.nx, "ntp": plan.info["ntp"],
+                   "tiling": {"tile_model": plan.info["tile_model"], "tile_data": plan.info["tile_data"],
+                              "nchunk": plan.info["nchunk"]},
                    "nxp": plan.info["nxp"], "npanel": w.npanel, "p": w.p, "q": w.q,
                    "n_outer": w.n_outer, "n_inner": w.n_inner, "fmax_hz": w.fmax,
                    "reductions": "f64", "seed": w.seed},

@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define ASHRT_ABI_VERSION 2
+#define ASHRT_ABI_VERSION 3
 
 enum ashrt_status {
   ASHRT_OK = 0,
@@ -128,9 +128,21 @@ typedef struct ashrt_plan_info {
   int32_t nt, nx, ntp, nxp, npanel, half_width;
   int32_t jlo, jhi;            /* mapped data band (inclusive)                                       */
   int32_t kmax;                /* highest model frequency bin the map touches                        */
-  int32_t nchunk;              /* panel chunks of the forward row pass                               */
+  int32_t nchunk;              /* panel chunks of the row passes                                     */
+  int32_t tile_model, tile_data;  /* x-FFT time columns per workgroup (model panels, data)           */
   size_t ws_forward, ws_adjoint, ws_invert_q2, ws_invert_q1;   /* workspace bytes per operation    */
 } ashrt_plan_info;
+
+/* Tile shapes of the pipeline; 0 selects the built-in rule.
+ *   tile_model: time columns per model-panel x-FFT workgroup (even, >= 2)
+ *   tile_data:  time columns per data x-FFT workgroup (even, >= 2)
+ *   nchunk:     panel chunks of the row passes (1..npanel)
+ * Any setting gives the same results up to FP32 rounding order; it only
+ * changes the work decomposition.  Tiles whose LDS exceeds the
+ * per-workgroup limit make plan creation fail with ASHRT_E_UNSUPPORTED_SIZE. */
+typedef struct ashrt_tuning {
+  int32_t tile_model, tile_data, nchunk;
+} ashrt_tuning;
 
 typedef struct ashrt_plan ashrt_plan;
 
@@ -146,6 +158,18 @@ int irls_params_validate(const irls_params *params);
 /* Create a plan on HIP device `device`; uploads twiddle tables, panel
  * constants and work lists (a few hundred KB).  *out is NULL on failure. */
 int ashrt_plan_create(const ashrt_desc *desc, int device, ashrt_plan **out);
+/* As ashrt_plan_create with explicit tile shapes (tuning may be NULL). */
+int ashrt_plan_create_tuned(const ashrt_desc *desc, const ashrt_tuning *tuning, int device, ashrt_plan **plan);
+
+/* Autotuner: times one forward + adjoint pair (median of `repeats`, >= 1)
+ * for every candidate tiling -- model tiles {8, 16, 32}, data tiles
+ * {2, 4, 8}, chunks {1, 2, 4, 8} within 1..npanel -- on zero-filled scratch
+ * inputs of the descriptor's geometry, and returns the fastest in *best
+ * (and its time in *best_ms, may be NULL).  Allocates and frees its own
+ * scratch device memory and synchronises `device`; results are cached per
+ * geometry for the life of the process. */
+int ashrt_autotune(const ashrt_desc *desc, int device, int32_t repeats, ashrt_tuning *best, double *best_ms);
+
 void ashrt_plan_destroy(ashrt_plan *plan);
 int ashrt_plan_get_info(const ashrt_plan *plan, ashrt_plan_info *info);
 
@@ -192,6 +216,9 @@ typedef struct ashrt_batch_plan ashrt_batch_plan;
 
 int ashrt_batch_plan_create(const ashrt_desc *descs, int32_t ngather, int device,
                             ashrt_batch_plan **out);
+/* As ashrt_batch_plan_create with one tiling for every gather (NULL = rule). */
+int ashrt_batch_plan_create_tuned(const ashrt_desc *descs, int32_t ngather, const ashrt_tuning *tuning, int device,
+                                  ashrt_batch_plan **plan);
 void ashrt_batch_plan_destroy(ashrt_batch_plan *plan);
 /* Offsets (host arrays of ngather entries, may be NULL) and totals. */
 int ashrt_batch_layout(const ashrt_batch_plan *plan, int64_t *data_off, int64_t *model_off,

@@ -58,6 +58,10 @@ class UnetTrainParams(C.Structure):
                 ("weight_decay", C.c_double), ("lam_w", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("tile_model", C.c_int32), ("tile_data", C.c_int32), ("nchunk", C.c_int32)]
+
+
 class IrlsReport(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("outer_done", C.c_int32),
@@ -72,6 +76,7 @@ class PlanInfo(C.Structure):
         ("nt", C.c_int32), ("nx", C.c_int32), ("ntp", C.c_int32), ("nxp", C.c_int32),
         ("npanel", C.c_int32), ("half_width", C.c_int32),
         ("jlo", C.c_int32), ("jhi", C.c_int32), ("kmax", C.c_int32), ("nchunk", C.c_int32),
+        ("tile_model", C.c_int32), ("tile_data", C.c_int32),
         ("ws_forward", C.c_size_t), ("ws_adjoint", C.c_size_t),
         ("ws_invert_q2", C.c_size_t), ("ws_invert_q1", C.c_size_t),
     ]
@@ -80,7 +85,7 @@ class PlanInfo(C.Structure):
 _lib = None
 
 
-ABI_VERSION = 2  # struct layouts below match include/ashrt.h at this version
+ABI_VERSION = 3  # struct layouts below match include/ashrt.h at this version
 
 
 def lib():
@@ -101,6 +106,9 @@ def lib():
         "ashrt_desc_validate": (C.c_int, [P_desc]),
         "irls_params_validate": (C.c_int, [P_prm]),
         "ashrt_plan_create": (C.c_int, [P_desc, C.c_int, C.POINTER(vp)]),
+        "ashrt_plan_create_tuned": (C.c_int, [P_desc, C.POINTER(Tuning), C.c_int, C.POINTER(vp)]),
+        "ashrt_batch_plan_create_tuned": (C.c_int, [P_desc, i32, C.POINTER(Tuning), C.c_int, C.POINTER(vp)]),
+        "ashrt_autotune": (C.c_int, [P_desc, C.c_int, i32, C.POINTER(Tuning), C.POINTER(C.c_double)]),
         "ashrt_plan_destroy": (None, [vp]),
         "ashrt_plan_get_info": (C.c_int, [vp, C.POINTER(PlanInfo)]),
         "ashrt_workspace_bytes": (C.c_int, [vp, C.c_int, P_prm, C.POINTER(sz)]),

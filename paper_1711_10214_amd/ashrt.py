@@ -82,16 +82,45 @@ def validate_desc(**kw) -> int:
     return L.lib().ashrt_desc_validate(C.byref(_Desc(**kw).c))
 
 
+def _desc_kwargs(nt, nx, dt, dx, vel, tau0, scale, ntp, nxp, fmin, fmax, half_width, wavelet):
+    return dict(nt=nt, nx=nx, dt=dt, dx=dx, vel=vel, tau0=tau0, scale=scale, ntp=ntp, nxp=nxp, fmin=fmin,
+                fmax=fmax, half_width=half_width, wavelet=wavelet)
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    return L.Tuning(int(t.get("tile_model", 0)), int(t.get("tile_data", 0)), int(t.get("nchunk", 0)))
+
+
+def autotune(device=0, repeats=3, **geom):
+    """Fastest tiling of one forward + adjoint pair for this geometry (the
+    library's autotuner; cached per geometry for the process)."""
+    d = _Desc(**geom)
+    best = L.Tuning()
+    ms = C.c_double()
+    L.check(L.lib().ashrt_autotune(C.byref(d.c), int(device), int(repeats), C.byref(best), C.byref(ms)),
+            "ashrt_autotune")
+    return {"tile_model": best.tile_model, "tile_data": best.tile_data, "nchunk": best.nchunk, "pair_ms": ms.value}
+
+
 class Plan:
     """One gather geometry and its panel list (velocity, asymptote shift, scale)."""
 
     def __init__(self, nt, nx, dt, dx, vel, tau0=None, scale=None, ntp=0, nxp=0, fmin=0.0,
-                 fmax=0.0, half_width=4, wavelet=None, device=0):
+                 fmax=0.0, half_width=4, wavelet=None, device=0, tuning=None):
+        """tuning: None (built-in tiling), "auto" (run the autotuner, cached
+        per geometry) or a dict with tile_model / tile_data / nchunk."""
         self._desc = _Desc(nt, nx, dt, dx, vel, tau0, scale, ntp, nxp, fmin, fmax, half_width, wavelet)
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if isinstance(tuning, str) and tuning == "auto":
+            tuning = autotune(device=self.device.index or 0, **_desc_kwargs(nt, nx, dt, dx, vel, tau0, scale, ntp,
+                                                                          nxp, fmin, fmax, half_width, wavelet))
+        self.tuning = tuning
+        tn = _tuning(tuning)
         h = C.c_void_p()
-        L.check(L.lib().ashrt_plan_create(C.byref(self._desc.c), self.device.index or 0, C.byref(h)),
-                "ashrt_plan_create")
+        L.check(L.lib().ashrt_plan_create_tuned(C.byref(self._desc.c), C.byref(tn) if tn is not None else None,
+                                                self.device.index or 0, C.byref(h)), "ashrt_plan_create")
         self._h = h
         info = L.PlanInfo()
         L.check(L.lib().ashrt_plan_get_info(self._h, C.byref(info)), "ashrt_plan_get_info")
@@ -185,13 +214,16 @@ class Plan:
 class BatchPlan:
     """Many gathers of uneven size in one plan; arrays are packed."""
 
-    def __init__(self, descs: Sequence[dict], device=0):
+    def __init__(self, descs: Sequence[dict], device=0, tuning=None):
+        """tuning: None or a dict (tile_model / tile_data / nchunk) applied to every gather."""
         self._descs = [_Desc(**kw) for kw in descs]
         arr = (L.AshrtDesc * len(self._descs))(*[d.c for d in self._descs])
         self._arr = arr
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        tn = _tuning(tuning)
         h = C.c_void_p()
-        L.check(L.lib().ashrt_batch_plan_create(arr, len(self._descs), self.device.index or 0, C.byref(h)),
+        L.check(L.lib().ashrt_batch_plan_create_tuned(arr, len(self._descs), C.byref(tn) if tn is not None else None,
+                                                      self.device.index or 0, C.byref(h)),
                 "ashrt_batch_plan_create")
         self._h = h
         n = len(self._descs)

@@ -270,18 +270,23 @@ struct ashrt_batch_plan {
   PlanImpl impl;
 };
 
-static int build_gather(const ashrt_desc* d, GatherHost* gh) {
+static int build_gather(const ashrt_desc* d, const ashrt_tuning* tn, GatherHost* gh) {
   int st = resolve_desc(d, &gh->z);
   if (st) return st;
   const Resolved& z = gh->z;
   gh->nrows = z.nxp / 2;
+  if (tn && ((tn->tile_model < 0 || (tn->tile_model & 1)) || (tn->tile_data < 0 || (tn->tile_data & 1)) ||
+             tn->nchunk < 0))
+    return fail(ASHRT_E_INVALID_ARG, "tile sizes must be even (or 0) and nchunk >= 0");
   int T = std::min(64, 2 * (kXfftTilePoints / z.nxp));
   T = std::max(2, T & ~1);
+  if (tn && tn->tile_model > 0) T = tn->tile_model;
   gh->tileT = T;
   gh->ntiles = (z.nt + T - 1) / T;
   // the data transform is one panel: narrower tiles give it ~256 workgroups
   int Td = 2 * ((z.nt + 511) / 512);
   Td = std::max(2, std::min(T, Td));
+  if (tn && tn->tile_data > 0) Td = tn->tile_data;
   gh->tileTd = Td;
   gh->ntilesd = (z.nt + Td - 1) / Td;
   gh->panels.resize(z.P);
@@ -320,13 +325,14 @@ static void destroy_impl(PlanImpl& P) {
 }
 
 // Build work lists and device tables for a set of gathers.
-static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImpl& P) {
+static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImpl& P,
+                       const ashrt_tuning* tn = nullptr) {
   if (!descs || ngather < 1) return fail(ASHRT_E_INVALID_ARG, "no gathers");
   P.device = device;
   P.ngather = ngather;
   P.g.resize(ngather);
   for (int i = 0; i < ngather; ++i) {
-    int st = build_gather(&descs[i], &P.g[i]);
+    int st = build_gather(&descs[i], tn, &P.g[i]);
     if (st) return st;
   }
   P.R = P.g[0].z.R;
@@ -338,6 +344,7 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   for (auto& gh : P.g) total_rows += gh.nrows;
   for (auto& gh : P.g) {
     long long want = (1024 + total_rows - 1) / total_rows;
+    if (tn && tn->nchunk > 0) want = tn->nchunk;
     gh.nchunk = (int)std::max(1LL, std::min<long long>(want, gh.z.P));
   }
 
@@ -592,11 +599,16 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
 }
 
 extern "C" int ashrt_plan_create(const ashrt_desc* desc, int device, ashrt_plan** out) {
+  return ashrt_plan_create_tuned(desc, nullptr, device, out);
+}
+
+extern "C" int ashrt_plan_create_tuned(const ashrt_desc* desc, const ashrt_tuning* tuning, int device,
+                                       ashrt_plan** out) {
   if (!out) return fail(ASHRT_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   ashrt_plan* p = new (std::nothrow) ashrt_plan();
   if (!p) return fail(ASHRT_E_OOM, "host allocation failed");
-  int st = create_impl(desc, 1, device, p->impl);
+  int st = create_impl(desc, 1, device, p->impl, tuning);
   if (st) {
     destroy_impl(p->impl);
     delete p;
@@ -614,11 +626,16 @@ extern "C" void ashrt_plan_destroy(ashrt_plan* p) {
 
 extern "C" int ashrt_batch_plan_create(const ashrt_desc* descs, int32_t ngather, int device,
                                        ashrt_batch_plan** out) {
+  return ashrt_batch_plan_create_tuned(descs, ngather, nullptr, device, out);
+}
+
+extern "C" int ashrt_batch_plan_create_tuned(const ashrt_desc* descs, int32_t ngather, const ashrt_tuning* tuning,
+                                             int device, ashrt_batch_plan** out) {
   if (!out) return fail(ASHRT_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   ashrt_batch_plan* p = new (std::nothrow) ashrt_batch_plan();
   if (!p) return fail(ASHRT_E_OOM, "host allocation failed");
-  int st = create_impl(descs, ngather, device, p->impl);
+  int st = create_impl(descs, ngather, device, p->impl, tuning);
   if (st) {
     destroy_impl(p->impl);
     delete p;
@@ -649,6 +666,8 @@ extern "C" int ashrt_plan_get_info(const ashrt_plan* plan, ashrt_plan_info* info
   info->jhi = g.z.jhi;
   info->kmax = g.z.kmax;
   info->nchunk = g.nchunk;
+  info->tile_model = g.tileT;
+  info->tile_data = g.tileTd;
   info->ws_forward = P.layout(ASHRT_OP_FORWARD, 2).total;
   info->ws_adjoint = P.layout(ASHRT_OP_ADJOINT, 2).total;
   info->ws_invert_q2 = P.layout(ASHRT_OP_INVERT, 2).total;
@@ -1312,4 +1331,115 @@ extern "C" int robust_invert_batched(const ashrt_batch_plan* plan, const irls_pa
                                      irls_report* reps, void* ws, size_t wsb, void* stream) {
   if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
   return invert_impl(plan->impl, prm, d, mask, m, w0, d_rec, reps, ws, wsb, stream, true);
+}
+
+// ------------------------------------------------------------ autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<ashrt_tuning, double>> g_tune_cache;
+}  // namespace
+
+extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeats, ashrt_tuning* best,
+                              double* best_ms) {
+  if (!desc || !best) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  if (repeats < 1) return fail(ASHRT_E_INVALID_ARG, "repeats must be >= 1");
+  Resolved z;
+  int st = resolve_desc(desc, &z);
+  if (st) return st;
+  // cost depends on the geometry, the band, R and whether the panels carry
+  // phase ramps or bin weights -- not on the velocity values beyond that
+  char key[192];
+  std::snprintf(key, sizeof key, "%d:%d,%d,%d,%d,%d,%d,%d,%d,%d", device, z.nt, z.nx, z.ntp, z.nxp, z.P, z.R, z.jlo,
+                z.jhi, (desc->tau0_samples || desc->wavelet_amp) ? 1 : 0);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *best = it->second.first;
+      if (best_ms) *best_ms = it->second.second;
+      return ASHRT_OK;
+    }
+  }
+  DeviceGuard dg(device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the device");
+  const size_t nm = (size_t)z.P * z.nx * z.nt, nd = (size_t)z.nx * z.nt;
+  float *m = nullptr, *d = nullptr, *m2 = nullptr;
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&] {
+    if (s) (void)hipStreamSynchronize(s);
+    if (m) (void)hipFree(m);
+    if (d) (void)hipFree(d);
+    if (m2) (void)hipFree(m2);
+    if (ws) (void)hipFree(ws);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+  };
+  if (hipMalloc(&m, nm * 4) != hipSuccess || hipMalloc(&d, nd * 4) != hipSuccess ||
+      hipMalloc(&m2, nm * 4) != hipSuccess) {
+    cleanup();
+    return fail(ASHRT_E_OOM, "autotune scratch allocation failed");
+  }
+  if (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemsetAsync(m, 0, nm * 4, s) != hipSuccess || hipMemsetAsync(d, 0, nd * 4, s) != hipSuccess) {
+    cleanup();
+    return fail(ASHRT_E_HIP, "autotune set-up failed");
+  }
+  double best_t = 1e300;
+  ashrt_tuning bt{0, 0, 0};
+  for (int tm : {8, 16, 32})
+    for (int td : {2, 4, 8})
+      for (int ch : {1, 2, 4, 8}) {
+        if (ch > z.P) continue;
+        const ashrt_tuning tn{tm, td, ch};
+        PlanImpl P;
+        if (create_impl(desc, 1, device, P, &tn) != ASHRT_OK) {  // e.g. the tile does not fit in LDS
+          destroy_impl(P);
+          continue;
+        }
+        const size_t need = std::max(P.layout(ASHRT_OP_FORWARD, 2).total, P.layout(ASHRT_OP_ADJOINT, 2).total);
+        if (need > ws_cap) {
+          if (ws) (void)hipFree(ws);
+          ws = nullptr;
+          ws_cap = 0;
+          if (hipMalloc(&ws, need) != hipSuccess) {
+            destroy_impl(P);
+            cleanup();
+            return fail(ASHRT_E_OOM, "autotune workspace allocation failed");
+          }
+          ws_cap = need;
+        }
+        bool ok = forward_impl(P, m, d, nullptr, ws, ws_cap, s) == ASHRT_OK &&
+                  adjoint_impl(P, d, m2, nullptr, ws, ws_cap, s) == ASHRT_OK;
+        std::vector<float> ts;
+        for (int r = 0; ok && r < repeats; ++r) {
+          ok = hipEventRecord(e0, s) == hipSuccess && forward_impl(P, m, d, nullptr, ws, ws_cap, s) == ASHRT_OK &&
+               adjoint_impl(P, d, m2, nullptr, ws, ws_cap, s) == ASHRT_OK && hipEventRecord(e1, s) == hipSuccess &&
+               hipEventSynchronize(e1) == hipSuccess;
+          float ms = 0.f;
+          if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+          ts.push_back(ms);
+        }
+        (void)hipStreamSynchronize(s);
+        destroy_impl(P);
+        if (!ok) continue;
+        std::sort(ts.begin(), ts.end());
+        const double med = ts[ts.size() / 2];
+        if (med < best_t) {
+          best_t = med;
+          bt = tn;
+        }
+      }
+  cleanup();
+  if (best_t >= 1e300) return fail(ASHRT_E_UNSUPPORTED_SIZE, "no candidate tiling could run");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {bt, best_t};
+  }
+  *best = bt;
+  if (best_ms) *best_ms = best_t;
+  return ASHRT_OK;
 }

@@ -32,6 +32,7 @@ def test_header_functions_are_exported(A):
     names = _declared_functions()
     assert "ashrt_forward" in names and "robust_invert" in names and "robust_invert_batched" in names
     assert "unet_forward" in names and "unet_train_step" in names
+    assert "ashrt_autotune" in names and "ashrt_plan_create_tuned" in names
     lib = A.lib()
     for n in names:
         assert hasattr(lib, n), n

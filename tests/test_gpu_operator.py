@@ -156,3 +156,36 @@ def test_aashrt_full_size_matches_stored_oracle_samples(A):
             assert e_norm <= TOL
             # 512 samples estimate the whole-output relative L2 error
             assert e_s <= 3 * TOL
+
+
+def test_tuned_tilings_give_the_same_operator(A):
+    """Every tiling the autotuner may choose computes the same operator (only
+    the panel-chunk partial sums change the FP32 summation order)."""
+    import torch
+    kw = geom_kwargs(203, 37, 0.004, 12.5, [1400.0, 2200.0, 3900.0, 2600.0, 1800.0], fmax=90.0)
+    rng = np.random.default_rng(41)
+    m = torch.tensor(rng.standard_normal((5, 37, 203)), dtype=torch.float32, device="cuda")
+    d = torch.tensor(rng.standard_normal((37, 203)), dtype=torch.float32, device="cuda")
+    base = A.Plan(**kw)
+    f0, a0 = base.forward(m).cpu().numpy(), base.adjoint(d).cpu().numpy()
+    for tm, td, ch in [(8, 2, 1), (32, 8, 5), (16, 4, 2), (64, 2, 8)]:
+        plan = A.Plan(**kw, tuning={"tile_model": tm, "tile_data": td, "nchunk": ch})
+        assert (plan.info["tile_model"], plan.info["tile_data"]) == (tm, td)
+        assert plan.info["nchunk"] == min(ch, 5)
+        ef = rel_l2(plan.forward(m).cpu().numpy(), f0)
+        ea = rel_l2(plan.adjoint(d).cpu().numpy(), a0)
+        print(f"[gpu] tiling {tm}/{td}/{ch}: forward {ef:.1e} adjoint {ea:.1e}", flush=True)
+        assert ef <= 1e-6 and ea <= 1e-6
+    with pytest.raises(A.AshrtError):
+        A.Plan(**kw, tuning={"tile_model": 7})
+
+
+def test_autotune_is_cached_and_usable(A):
+    kw = geom_kwargs(256, 64, 0.004, 12.5, list(np.linspace(1500, 3000, 8)), fmax=100.0)
+    t1 = A.autotune(**kw)
+    t2 = A.autotune(**kw)
+    print(f"[gpu] autotune crg-256x64-nv8: {t1}", flush=True)
+    assert t1 == t2
+    assert t1["tile_model"] in (8, 16, 32) and t1["tile_data"] in (2, 4, 8) and 1 <= t1["nchunk"] <= 8
+    plan = A.Plan(**kw, tuning="auto")
+    assert plan.info["tile_model"] == t1["tile_model"] and plan.info["nchunk"] == t1["nchunk"]
