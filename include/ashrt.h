@@ -226,6 +226,19 @@ int ashrt_batch_layout(const ashrt_batch_plan *plan, int64_t *data_off, int64_t 
                        int64_t *mask_total);
 int ashrt_batch_workspace_bytes(const ashrt_batch_plan *plan, int op, const irls_params *params,
                                 size_t *bytes);
+/* Time-domain (classical) ASHRT / AASHRT pair on the plan's single gather
+ * (thesis Chapter 3, the hyperbolic Radon-operator table; Chapter 6,
+ * equations ch6_AASHRT_forward and ch6_AASHRT_adjoint): a model sample at
+ * apex time tau, apex trace xa and panel p lies on
+ * t = tau0_p + sqrt(tau^2 + (x - xa)^2 dx^2 / v_p^2), read (adjoint) or
+ * spread (forward, the exact transpose) with linear interpolation in time;
+ * the apex grid is the receiver grid; samples outside the record dropped.
+ * Cost O(P nx^2 nt): the operator the Stolt pair is compared against.  No
+ * padding, band or wavelet; panel_scale is not applied.  Same layouts and
+ * mask semantics as ashrt_forward / ashrt_adjoint; no workspace. */
+int ashrt_td_forward(const ashrt_plan *plan, const float *m, float *d, const uint8_t *trace_mask, void *stream);
+int ashrt_td_adjoint(const ashrt_plan *plan, const float *d, float *m, const uint8_t *trace_mask, void *stream);
+
 int ashrt_forward_batched(const ashrt_batch_plan *plan, const float *m_packed, float *d_packed,
                           const uint8_t *mask_packed, void *ws, size_t ws_bytes, void *stream);
 int ashrt_adjoint_batched(const ashrt_batch_plan *plan, const float *d_packed, float *m_packed,

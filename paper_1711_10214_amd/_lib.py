@@ -109,6 +109,8 @@ def lib():
         "ashrt_plan_create_tuned": (C.c_int, [P_desc, C.POINTER(Tuning), C.c_int, C.POINTER(vp)]),
         "ashrt_batch_plan_create_tuned": (C.c_int, [P_desc, i32, C.POINTER(Tuning), C.c_int, C.POINTER(vp)]),
         "ashrt_autotune": (C.c_int, [P_desc, C.c_int, i32, C.POINTER(Tuning), C.POINTER(C.c_double)]),
+        "ashrt_td_forward": (C.c_int, [vp, vp, vp, vp, vp]),
+        "ashrt_td_adjoint": (C.c_int, [vp, vp, vp, vp, vp]),
         "ashrt_plan_destroy": (None, [vp]),
         "ashrt_plan_get_info": (C.c_int, [vp, C.POINTER(PlanInfo)]),
         "ashrt_workspace_bytes": (C.c_int, [vp, C.c_int, P_prm, C.POINTER(sz)]),

@@ -191,6 +191,23 @@ class Plan:
                                       _stream(self.device)), "ashrt_adjoint")
         return m
 
+    def td_forward(self, m, mask=None, out=None):
+        """Time-domain (classical) forward operator (no padding, band or wavelet)."""
+        self._check_model(m)
+        d = out if out is not None else torch.empty((self.nx, self.nt), dtype=torch.float32, device=self.device)
+        L.check(L.lib().ashrt_td_forward(self._h, _ptr(m), _ptr(d), _ptr(self._mask(mask)), _stream(self.device)),
+                "ashrt_td_forward")
+        return d
+
+    def td_adjoint(self, d, mask=None, out=None):
+        """Time-domain (classical) adjoint operator."""
+        self._check_data(d)
+        m = out if out is not None else torch.empty((self.npanel, self.nx, self.nt), dtype=torch.float32,
+                                                    device=self.device)
+        L.check(L.lib().ashrt_td_adjoint(self._h, _ptr(d), _ptr(m), _ptr(self._mask(mask)), _stream(self.device)),
+                "ashrt_td_adjoint")
+        return m
+
     def robust_invert(self, d, params: Params, mask=None, m0=None, w0=None, want_drec=True,
                       want_report=True):
         """IRLS-CG solve.  Returns (m, d_rec or None, report dict or None)."""

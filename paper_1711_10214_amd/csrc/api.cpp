@@ -1307,6 +1307,26 @@ extern "C" int ashrt_adjoint(const ashrt_plan* plan, const float* d, float* m, c
   return adjoint_impl(plan->impl, d, m, mask, ws, wsb, stream);
 }
 
+extern "C" int ashrt_td_forward(const ashrt_plan* plan, const float* m, float* d, const uint8_t* mask, void* stream) {
+  if (!plan || !m || !d) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  const PlanImpl& P = plan->impl;
+  DeviceGuard dg(P.device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
+  TdArgs a{P.d_gd, P.d_pan, const_cast<float*>(m), d, mask, (long long)P.g[0].nd()};
+  HIP_TRY(launch_td(a, true, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_td_adjoint(const ashrt_plan* plan, const float* d, float* m, const uint8_t* mask, void* stream) {
+  if (!plan || !m || !d) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  const PlanImpl& P = plan->impl;
+  DeviceGuard dg(P.device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
+  TdArgs a{P.d_gd, P.d_pan, m, const_cast<float*>(d), mask, (long long)P.g[0].nm()};
+  HIP_TRY(launch_td(a, false, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
 extern "C" int ashrt_forward_batched(const ashrt_batch_plan* plan, const float* m, float* d,
                                      const uint8_t* mask, void* ws, size_t wsb, void* stream) {
   if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");

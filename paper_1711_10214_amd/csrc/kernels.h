@@ -162,6 +162,17 @@ struct CgArgs {
 // operator kernels; `key` is the FFT length class (see rows_size_is_tpl /
 // x_size_is_tpl; 0 = generic)
 bool rows_size_is_tpl(int n, int R);
+
+// Time-domain ASHRT pair (one gather, gd[0]): forward m -> d, adjoint d -> m.
+struct TdArgs {
+  const GatherDev* gd;
+  const PanelDev* panels;
+  float* m;                // [P][nx][nt]
+  float* d;                // [nx][nt]
+  const uint8_t* tmask;    // [nx] or null
+  long long n_out;         // output samples of the launch
+};
+hipError_t launch_td(const TdArgs& a, bool forward, hipStream_t s);
 bool x_size_is_tpl(int n);
 hipError_t launch_xfft_fwd(int key, const XfwdArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_xfft_inv(int key, const XinvArgs& a, size_t lds, hipStream_t s);
