@@ -218,6 +218,53 @@ def run_batch(args):
     print(json.dumps(rec), flush=True)
 
 
+def run_speedratio(args):
+    """Classical time-domain ASHRT against the Stolt-based operator on the
+    same GPU (the thesis' Chapter 5 speed comparison, with and without zero
+    padding): median wall time of a forward + adjoint pair for growing
+    gathers with 32 velocities."""
+    import numpy as np
+    import torch
+    import paper_1711_10214_amd as A
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    vel = list(np.linspace(1400.0, 4000.0, 32))
+    rows = []
+
+    def pair_ms(fwd, adj, m, d, reps):
+        for _ in range(2):
+            fwd(m), adj(d)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fwd(m)
+            adj(d)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for nx, nt in [(64, 256), (128, 512), (256, 1024), (512, 2048)]:
+        rng = np.random.default_rng(nx)
+        m = torch.tensor(rng.standard_normal((32, nx, nt)), dtype=torch.float32, device="cuda")
+        d = torch.tensor(rng.standard_normal((nx, nt)), dtype=torch.float32, device="cuda")
+        padded = A.Plan(nt, nx, 0.004, 12.5, vel, fmax=100.0)
+        unpadded = A.Plan(nt, nx, 0.004, 12.5, vel, fmax=100.0, ntp=nt, nxp=nx)
+        t_td = pair_ms(padded.td_forward, padded.td_adjoint, m, d, 5)
+        t_sp = pair_ms(padded.forward, padded.adjoint, m, d, 20)
+        t_su = pair_ms(unpadded.forward, unpadded.adjoint, m, d, 20)
+        rows.append({"nx": nx, "nt": nt, "npanel": 32, "time_domain_ms": t_td, "stolt_padded_ms": t_sp,
+                     "stolt_unpadded_ms": t_su, "ratio_padded": t_td / t_sp, "ratio_unpadded": t_td / t_su})
+        print(f"[bench] {nx}x{nt}: time-domain {t_td:.3f} ms, Stolt padded {t_sp:.3f} ms "
+              f"(x{t_td / t_sp:.1f}), unpadded {t_su:.3f} ms (x{t_td / t_su:.1f})", file=sys.stderr, flush=True)
+    rec = {"metric": "forward+adjoint pair time, classical time-domain ASHRT / Stolt-based ASHRT",
+           "value": rows[-1]["ratio_padded"], "unit": "x (speed-up of the Stolt pair, padded, largest size)",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "speedratio", "npanel": 32, "dt": 0.004, "dx": 12.5}, "sizes": rows}
+    print(json.dumps(rec), flush=True)
+
+
 def run_warmstart(args):
     """Learned warm start against the plain zero start on the same GPU: CG
     iterations and wall time to reach the plain method's final separated-
@@ -324,6 +371,8 @@ def main():
         return run_warmstart(args)
     if args.workload.startswith("batch"):
         return run_batch(args)
+    if args.workload == "speedratio":
+        return run_speedratio(args)
 
     import numpy as np
     import torch
