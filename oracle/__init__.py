@@ -11,6 +11,10 @@ Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import it.  It shares no code with the library: the two meet only through the
 seeded input generator in ``synth``.
 
+``fista`` is the l2-l1 sparse inversion of Chapter 6 (FISTA with a
+power-method step size), pinned against LAPACK eigenvalues and an
+independent coordinate-descent Lasso solver.
+
 ``unet`` is the FP64 reference of the learned warm start (a U-Net that
 predicts an initial model and initial residual weights for the robust
 inversion): its forward pass is the network's definition, its hand-written
@@ -47,4 +51,5 @@ from .irls import (  # noqa: F401
 )
 from .quality import q_db  # noqa: F401
 from . import unet  # noqa: F401
+from . import fista  # noqa: F401
 from . import timedomain  # noqa: F401
