@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define ASHRT_ABI_VERSION 3
+#define ASHRT_ABI_VERSION 4
 
 enum ashrt_status {
   ASHRT_OK = 0,
@@ -80,7 +80,7 @@ enum ashrt_status {
   ASHRT_E_WORKSPACE = -7         /* ws is NULL, misaligned or smaller than required              */
 };
 
-enum ashrt_op { ASHRT_OP_FORWARD = 0, ASHRT_OP_ADJOINT = 1, ASHRT_OP_INVERT = 2 };
+enum ashrt_op { ASHRT_OP_FORWARD = 0, ASHRT_OP_ADJOINT = 1, ASHRT_OP_INVERT = 2, ASHRT_OP_FISTA = 3 };
 
 /* Operator description (host memory; copied at plan creation). */
 typedef struct ashrt_desc {
@@ -174,7 +174,8 @@ void ashrt_plan_destroy(ashrt_plan *plan);
 int ashrt_plan_get_info(const ashrt_plan *plan, ashrt_plan_info *info);
 
 /* Workspace needed by `op` (ASHRT_OP_*); for ASHRT_OP_INVERT pass the params
- * (q = 1 needs two more model-sized vectors), else params may be NULL. */
+ * (q = 1 needs two more model-sized vectors), else params may be NULL
+ * (ASHRT_OP_FISTA: the workspace of fista_invert). */
 int ashrt_workspace_bytes(const ashrt_plan *plan, int op, const irls_params *params, size_t *bytes);
 
 /* d = S L m  (Chapter 5 equation ch5_forward_operator; with tau0 and the mask,
@@ -226,6 +227,36 @@ int ashrt_batch_layout(const ashrt_batch_plan *plan, int64_t *data_off, int64_t 
                        int64_t *mask_total);
 int ashrt_batch_workspace_bytes(const ashrt_batch_plan *plan, int op, const irls_params *params,
                                 size_t *bytes);
+/* l2-l1 sparse inversion by FISTA (thesis Chapter 6, section "Sparse
+ * inversion", equation cost_fn with p = 2, q = 1): minimise
+ * J(m) = ||d - S L m||_2^2 + mu ||m||_1.  The step uses Lf = 2 lambda
+ * lip_safety, lambda the largest eigenvalue of L' S L estimated by n_power
+ * power-method iterations from the all-ones model; mu = the given value if
+ * mu > 0, else mu_rel * max|2 L' S d| (the smallest mu with m = 0 optimal,
+ * scaled).  Iteration (Beck and Teboulle):
+ *   m_k = soft(y_k + (2 / Lf) L' S (d - L y_k), mu / Lf),
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+ *   y_{k+1} = m_k + (t_k - 1) / t_{k+1} (m_k - m_{k-1}),   y_1 = m_0, t_1 = 1.
+ * m: in, the start m_0; out, the model.  d_rec (optional) = L m (unmasked).
+ * Stream-ordered; synchronises once at the end only when rep is non-NULL.
+ * Workspace: ashrt_workspace_bytes(plan, ASHRT_OP_FISTA, NULL, ...). */
+typedef struct fista_params {
+  int32_t n_iter, n_power;   /* FISTA and power-method iterations (>= 1, >= 1)        */
+  double mu;                 /* > 0: the trade-off parameter itself                    */
+  double mu_rel;             /* else mu = mu_rel * max|2 L' S d| (0 < mu_rel)          */
+  double lip_safety;         /* >= 1 (1.05): Lf = 2 * lambda * lip_safety              */
+} fista_params;
+
+typedef struct fista_report {
+  int32_t status, iters;
+  double lipschitz, mu;      /* Lf and mu used                                         */
+  double misfit, l1, objective;  /* ||S(d - L m)||^2, ||m||_1, misfit + mu l1          */
+} fista_report;
+
+void fista_params_default(fista_params *params);
+int fista_invert(const ashrt_plan *plan, const fista_params *params, const float *d, const uint8_t *trace_mask,
+                 float *m, float *d_rec, fista_report *rep, void *ws, size_t ws_bytes, void *stream);
+
 /* Time-domain (classical) ASHRT / AASHRT pair on the plan's single gather
  * (thesis Chapter 3, the hyperbolic Radon-operator table; Chapter 6,
  * equations ch6_AASHRT_forward and ch6_AASHRT_adjoint): a model sample at

@@ -6,7 +6,7 @@ The compute path is ``libashrt.so`` (HIP kernels for gfx950 behind a C ABI,
 as device memory.  Importing it loads the library and fails if it is missing.
 """
 from . import _lib  # noqa: F401
-from ._lib import AshrtError, OP_FORWARD, OP_ADJOINT, OP_INVERT, lib  # noqa: F401
+from ._lib import AshrtError, OP_FORWARD, OP_ADJOINT, OP_INVERT, OP_FISTA, lib  # noqa: F401
 from .ashrt import Plan, BatchPlan, Params, autotune, validate_desc, report_dict  # noqa: F401
 from .unet import UNet, TrainParams  # noqa: F401
 

@@ -18,7 +18,7 @@ ASHRT_E_OOM = -5
 ASHRT_E_NOT_IMPLEMENTED = -6
 ASHRT_E_WORKSPACE = -7
 
-OP_FORWARD, OP_ADJOINT, OP_INVERT = 0, 1, 2
+OP_FORWARD, OP_ADJOINT, OP_INVERT, OP_FISTA = 0, 1, 2, 3
 
 # kernel families for ashrt_profile_enable / ashrt_profile_read
 K_XFFT_MODEL, K_XFFT_DATA, K_ROWS_FWD, K_ROWS_FIN, K_XINV_DATA, K_ROWS_ADJ, K_XINV_MODEL, \
@@ -62,6 +62,16 @@ class Tuning(C.Structure):
     _fields_ = [("tile_model", C.c_int32), ("tile_data", C.c_int32), ("nchunk", C.c_int32)]
 
 
+class FistaParams(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("n_power", C.c_int32), ("mu", C.c_double), ("mu_rel", C.c_double),
+                ("lip_safety", C.c_double)]
+
+
+class FistaReport(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("lipschitz", C.c_double), ("mu", C.c_double),
+                ("misfit", C.c_double), ("l1", C.c_double), ("objective", C.c_double)]
+
+
 class IrlsReport(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("outer_done", C.c_int32),
@@ -85,7 +95,7 @@ class PlanInfo(C.Structure):
 _lib = None
 
 
-ABI_VERSION = 3  # struct layouts below match include/ashrt.h at this version
+ABI_VERSION = 4  # struct layouts below match include/ashrt.h at this version
 
 
 def lib():
@@ -109,6 +119,8 @@ def lib():
         "ashrt_plan_create_tuned": (C.c_int, [P_desc, C.POINTER(Tuning), C.c_int, C.POINTER(vp)]),
         "ashrt_batch_plan_create_tuned": (C.c_int, [P_desc, i32, C.POINTER(Tuning), C.c_int, C.POINTER(vp)]),
         "ashrt_autotune": (C.c_int, [P_desc, C.c_int, i32, C.POINTER(Tuning), C.POINTER(C.c_double)]),
+        "fista_params_default": (None, [C.POINTER(FistaParams)]),
+        "fista_invert": (C.c_int, [vp, C.POINTER(FistaParams), vp, vp, vp, vp, C.POINTER(FistaReport), vp, sz, vp]),
         "ashrt_td_forward": (C.c_int, [vp, vp, vp, vp, vp]),
         "ashrt_td_adjoint": (C.c_int, [vp, vp, vp, vp, vp]),
         "ashrt_plan_destroy": (None, [vp]),

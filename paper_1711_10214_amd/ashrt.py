@@ -191,6 +191,24 @@ class Plan:
                                       _stream(self.device)), "ashrt_adjoint")
         return m
 
+    def fista(self, d, n_iter=50, n_power=20, mu=0.0, mu_rel=0.05, lip_safety=1.05, mask=None, m0=None,
+              want_report=True):
+        """l2-l1 inversion by FISTA (thesis Chapter 6).  Returns (m, L m, report)."""
+        self._check_data(d)
+        mask = self._mask(mask)
+        m = (torch.zeros((self.npanel, self.nx, self.nt), dtype=torch.float32, device=self.device)
+             if m0 is None else m0.clone())
+        self._check_model(m)
+        drec = torch.empty_like(d)
+        prm = L.FistaParams(int(n_iter), int(n_power), float(mu), float(mu_rel), float(lip_safety))
+        ws = self.workspace(L.OP_FISTA)
+        rep = L.FistaReport() if want_report else None
+        L.check(L.lib().fista_invert(self._h, C.byref(prm), _ptr(d), _ptr(mask), _ptr(m), _ptr(drec),
+                                     C.byref(rep) if rep is not None else None, _ptr(ws), ws.numel(),
+                                     _stream(self.device)), "fista_invert")
+        out = None if rep is None else {k: getattr(rep, k) for k, _ in L.FistaReport._fields_}
+        return m, drec, out
+
     def td_forward(self, m, mask=None, out=None):
         """Time-domain (classical) forward operator (no padding, band or wavelet)."""
         self._check_model(m)

@@ -677,7 +677,11 @@ extern "C" int ashrt_plan_get_info(const ashrt_plan* plan, ashrt_plan_info* info
 
 static int ws_bytes_impl(const PlanImpl& P, int op, const irls_params* prm, size_t* bytes) {
   if (!bytes) return fail(ASHRT_E_INVALID_ARG, "bytes is NULL");
-  if (op < ASHRT_OP_FORWARD || op > ASHRT_OP_INVERT) return fail(ASHRT_E_INVALID_ARG, "unknown op");
+  if (op < ASHRT_OP_FORWARD || op > ASHRT_OP_FISTA) return fail(ASHRT_E_INVALID_ARG, "unknown op");
+  if (op == ASHRT_OP_FISTA) {  // the solver layout with four model-sized vectors
+    *bytes = P.layout(ASHRT_OP_INVERT, 1).total;
+    return ASHRT_OK;
+  }
   int q = 2;
   if (op == ASHRT_OP_INVERT) {
     if (!prm) return fail(ASHRT_E_INVALID_ARG, "params needed for ASHRT_OP_INVERT");
@@ -1293,7 +1297,123 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
   return ASHRT_OK;
 }
 
+// ------------------------------------------------------------ FISTA driver
+// Workspace: the solver layout with q = 1 (vectors r: residual; pdir: y;
+// g: gradient; u: power-method vector).
+int fista_impl(const PlanImpl& P, const fista_params* prm, const float* d, const uint8_t* mask, float* m,
+               float* d_rec, fista_report* rep, void* ws, size_t wsb, void* stream) {
+  if (!prm || !d || !m) return fail(ASHRT_E_INVALID_ARG, "params, d and m must be non-NULL");
+  if (prm->n_iter < 1 || prm->n_power < 1) return fail(ASHRT_E_INVALID_ARG, "n_iter and n_power must be >= 1");
+  if (!(prm->mu > 0.0) && !(prm->mu_rel > 0.0))
+    return fail(ASHRT_E_INVALID_ARG, "mu > 0 or mu_rel > 0 required");
+  if (!(prm->lip_safety >= 1.0)) return fail(ASHRT_E_INVALID_ARG, "lip_safety must be >= 1");
+  Ctx c;
+  int st = check_ws(P, ASHRT_OP_INVERT, 1, ws, wsb, &c, stream);
+  if (st) return st;
+  DeviceGuard dg(P.device);
+  if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
+  const WsLayout& L = c.L;
+  unsigned char* W = c.ws;
+  irls_params dummy{};
+  Solver S{c, P, dummy,
+           (float*)(W + L.r), (float*)(W + L.s), (float*)(W + L.q), (float*)(W + L.Wr),
+           (float*)(W + L.pdir), (float*)(W + L.g), (float*)(W + L.u), (float*)(W + L.Wminv),
+           (double*)(W + L.part), (double*)(W + L.pdel), (double*)(W + L.pgam), (double*)(W + L.sc),
+           (SelState*)(W + L.sel), (unsigned*)(W + L.hist), (RepDev*)(W + L.rep)};
+  const hipStream_t s = c.s;
+  float* y = S.pdir;
+  float* g = S.g;
+  float* x = S.u;
+  E_TRY(launch_zero_words(S.sc, (long long)P.ngather * kNScal * 2, s));
+  // power method on L' S L from the all-ones model, normalised
+  {
+    EwArgs f = S.ew(EW_FILL, true);
+    f.y = x;
+    f.value = (float)(1.0 / std::sqrt((double)P.tot_m / P.ngather));
+    E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(f, s); }));
+  }
+  for (int it = 0; it < prm->n_power; ++it) {
+    E_TRY(run_forward(c, x, nullptr, S.r, nullptr, nullptr, nullptr, mask));
+    E_TRY(run_adjoint(c, S.r, nullptr, mask, g, nullptr));
+    E_TRY(S.reduce(RED_SUMSQ, true, g, nullptr, SC_POW_SS, -1, false, nullptr, 0));
+    EwArgs a = S.ew(EW_SCALE_RSQRT, true);
+    a.y = x;
+    a.x = g;
+    a.coef = SC_POW_SS;
+    E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
+  }
+  // mu from max|L' S d|, then Lf, step and threshold
+  E_TRY(run_adjoint(c, d, nullptr, mask, g, nullptr));
+  E_TRY(S.reduce(RED_ABSMAX, true, g, nullptr, SC_MMAX, -1, true, nullptr, 0));
+  {
+    ScalArgs a{};
+    a.ngather = P.ngather;
+    a.step = ST_FISTA;
+    a.sc = S.sc;
+    a.safety = prm->lip_safety;
+    a.mu_abs = prm->mu;
+    a.mu_rel = prm->mu_rel;
+    E_TRY(launch_scalar(a, s));
+  }
+  {
+    EwArgs cp = S.ew(EW_COPY, true);
+    cp.y = y;
+    cp.x = m;
+    E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(cp, s); }));
+  }
+  double t = 1.0;
+  for (int k = 0; k < prm->n_iter; ++k) {
+    // r = S (d - L y); g = L' S r; then the shrinkage and momentum step
+    E_TRY(run_forward(c, y, nullptr, S.r, d, nullptr, nullptr, mask));
+    E_TRY(run_adjoint(c, S.r, nullptr, mask, g, nullptr));
+    const double t_new = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    EwArgs a = S.ew(EW_FISTA, true);
+    a.y = y;
+    a.x = g;
+    a.z_out = m;
+    a.coef = SC_FSTEP;
+    a.value = (float)((t - 1.0) / t_new);
+    E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
+    t = t_new;
+  }
+  // residual, separated / reconstructed gather, objective terms
+  E_TRY(run_forward(c, m, nullptr, S.r, d, nullptr, d_rec, mask));
+  E_TRY(S.reduce(RED_SUMSQ, false, S.r, mask, SC_MISFIT, -1, false, nullptr, 0));
+  E_TRY(S.reduce(RED_ABSSUM, true, m, nullptr, SC_HUBER, -1, false, nullptr, 0));
+  if (rep) {
+    std::vector<double> hsc((size_t)P.ngather * kNScal);
+    E_TRY(hipMemcpyAsync(hsc.data(), S.sc, hsc.size() * 8, hipMemcpyDeviceToHost, s));
+    E_TRY(hipStreamSynchronize(s));
+    std::memset(rep, 0, sizeof(*rep));
+    rep->iters = prm->n_iter;
+    rep->lipschitz = hsc[SC_LIP];
+    rep->mu = hsc[SC_MU];
+    rep->misfit = hsc[SC_MISFIT];
+    rep->l1 = hsc[SC_HUBER];
+    rep->objective = rep->misfit + rep->mu * rep->l1;
+    rep->status = std::isfinite(rep->objective) ? ASHRT_OK : ASHRT_E_NONFINITE;
+    if (rep->status) return fail(ASHRT_E_NONFINITE, "FISTA produced a non-finite objective");
+  }
+  return ASHRT_OK;
+}
+
 }  // namespace
+
+extern "C" void fista_params_default(fista_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n_iter = 50;
+  p->n_power = 20;
+  p->mu = 0.0;
+  p->mu_rel = 0.05;
+  p->lip_safety = 1.05;
+}
+
+extern "C" int fista_invert(const ashrt_plan* plan, const fista_params* prm, const float* d, const uint8_t* mask,
+                            float* m, float* d_rec, fista_report* rep, void* ws, size_t wsb, void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  return fista_impl(plan->impl, prm, d, mask, m, d_rec, rep, ws, wsb, stream);
+}
 
 extern "C" int ashrt_forward(const ashrt_plan* plan, const float* m, float* d, const uint8_t* mask, void* ws,
                              size_t wsb, void* stream) {

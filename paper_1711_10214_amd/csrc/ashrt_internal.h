@@ -78,6 +78,9 @@ enum ScalIdx {
   SC_GAMMA0 = 0, SC_GAMMA1, SC_DELTA, SC_ALPHA, SC_BETA, SC_DONE, SC_NINNER,
   SC_DMAX, SC_MMAX, SC_EPS_R, SC_EPS_M, SC_EPS_FROZEN, SC_FROZEN_SET, SC_MED, SC_MAD,
   SC_NLIVE, SC_MISFIT, SC_HUBER, SC_NONFINITE,
+  // FISTA: power-method sum of squares, Lipschitz constant, mu, step 2 / Lf,
+  // threshold mu / Lf (misfit and ||m||_1 reuse SC_MISFIT and SC_HUBER)
+  SC_POW_SS, SC_LIP, SC_MU, SC_FSTEP, SC_FTHR,
   kNScal = 24
 };
 

@@ -56,7 +56,7 @@ struct RowsArgs {
   int R;                  // interpolation half-width (generic kernels)
 };
 
-enum RedOp { RED_SUMSQ = 0, RED_ABSMAX_LIVE = 1, RED_ABSMAX = 2, RED_MISFIT = 3 };
+enum RedOp { RED_SUMSQ = 0, RED_ABSMAX_LIVE = 1, RED_ABSMAX = 2, RED_MISFIT = 3, RED_ABSSUM = 4 };
 
 struct RedArgs {
   const GatherDev* gd;
@@ -92,7 +92,10 @@ enum EwOp {
   EW_WR_INIT = 5,     // y = live ? (x ? x : 1) : 0           (x = w0 or null)
   EW_WR_UPDATE = 6,   // y = live ? (eps > 0 ? max(|x|, eps)^-1/2 : 1) : 0   (p = 1)
   EW_WM_UPDATE = 7,   // y = max(|x|, eps_m)^1/2 (or 1), z_out = x / y        (q = 1)
-  EW_WR_MASK = 8      // y = live ? 1 : 0                     (p = 2)
+  EW_WR_MASK = 8,     // y = live ? 1 : 0                     (p = 2)
+  EW_SCALE_RSQRT = 9, // y = x / sqrt(sc[g][coef])            (power-method normalisation)
+  EW_FISTA = 10       // v = y + sc[coef] x; m' = soft(v, sc[coef + 1]); y = m' + value (m' - m); m = m'
+                      //   (m is z_out, in and out)
 };
 
 struct EwArgs {
@@ -114,7 +117,8 @@ struct EwArgs {
 enum ScalStep {
   ST_EPS_M = 3,        // eps_m = b_m * mmax / 100
   ST_EPS_R = 4,        // eps_r = max(b_r * MAD / 0.6745, floor * dmax) (or frozen)
-  ST_REPORT_INNER = 5  // report.inner[outer] = ninner
+  ST_REPORT_INNER = 5, // report.inner[outer] = ninner
+  ST_FISTA = 6         // Lf = 2 safety sqrt(pow_ss); mu; step = 2 / Lf; thr = mu / Lf
 };
 
 struct ScalArgs {
@@ -125,6 +129,7 @@ struct ScalArgs {
   int outer;
   double b_r, b_m, floor_rel;
   int freeze;
+  double safety, mu_abs, mu_rel;  // ST_FISTA
 };
 
 struct SelArgs {

@@ -42,6 +42,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce_part(RedArgs A) {
         a += v * v;
       } else if (A.op == RED_ABSMAX) {
         a = fmax(a, fabs(v));
+      } else if (A.op == RED_ABSSUM) {
+        a += fabs(v);
       } else {
         bool live = true;
         if (tm) {
@@ -122,8 +124,17 @@ __global__ __launch_bounds__(kThreads) void k_elementwise(EwArgs A) {
     const VecItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
     float c = 0.f;
+    float c2 = 0.f;
     if (A.op == EW_AXPY || A.op == EW_XPBY || A.op == EW_WR_UPDATE || A.op == EW_WM_UPDATE)
       c = (float)A.sc[w.g * kNScal + A.coef];
+    if (A.op == EW_SCALE_RSQRT) {
+      const double ss = A.sc[w.g * kNScal + A.coef];
+      c = ss > 0.0 ? (float)(1.0 / sqrt(ss)) : 0.f;
+    }
+    if (A.op == EW_FISTA) {
+      c = (float)A.sc[w.g * kNScal + A.coef];
+      c2 = (float)A.sc[w.g * kNScal + A.coef + 1];
+    }
     const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     long long i0 = threadIdx.x;
     if ((A.op <= EW_FILL) && ((w.start | w.len) & 3) == 0) {
@@ -178,6 +189,16 @@ __global__ __launch_bounds__(kThreads) void k_elementwise(EwArgs A) {
           A.z_out[o] = A.x[o] / wi;
           break;
         }
+        case EW_SCALE_RSQRT: A.y[o] = A.x[o] * c; break;
+        case EW_FISTA: {
+          const float v = fmaf(c, A.x[o], A.y[o]);
+          const float a = fabsf(v) - c2;
+          const float mn = a > 0.f ? copysignf(a, v) : 0.f;
+          const float mo = A.z_out[o];
+          A.y[o] = fmaf(A.value, mn - mo, mn);
+          A.z_out[o] = mn;
+          break;
+        }
         default: break;
       }
     }
@@ -214,6 +235,15 @@ __global__ void k_scalar(ScalArgs A) {
     case ST_REPORT_INNER:
       if (A.rep) A.rep[g].inner[A.outer] = s[SC_NINNER];
       break;
+    case ST_FISTA: {
+      const double lf = 2.0 * A.safety * sqrt(fmax(s[SC_POW_SS], 0.0));
+      const double mu = A.mu_abs > 0.0 ? A.mu_abs : A.mu_rel * 2.0 * s[SC_MMAX];
+      s[SC_LIP] = lf;
+      s[SC_MU] = mu;
+      s[SC_FSTEP] = lf > 0.0 ? 2.0 / lf : 0.0;
+      s[SC_FTHR] = lf > 0.0 ? mu / lf : 0.0;
+      break;
+    }
     default:
       break;
   }
