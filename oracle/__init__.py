@@ -52,4 +52,5 @@ from .irls import (  # noqa: F401
 from .quality import q_db  # noqa: F401
 from . import unet  # noqa: F401
 from . import fista  # noqa: F401
+from . import blending  # noqa: F401
 from . import timedomain  # noqa: F401

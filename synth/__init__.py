@@ -21,3 +21,4 @@ from .gathers import (  # noqa: F401
     random_model,
     random_data,
 )
+from .survey import Survey, make_survey  # noqa: F401,E402
