@@ -257,6 +257,22 @@ void fista_params_default(fista_params *params);
 int fista_invert(const ashrt_plan *plan, const fista_params *params, const float *d, const uint8_t *trace_mask,
                  float *m, float *d_rec, fista_report *rep, void *ws, size_t ws_bytes, void *stream);
 
+/* Survey cubes (thesis Chapter 2, equations ch2_blending and
+ * pseudodeblending_equ).  All arrays are device memory; fire holds the
+ * firing time of each source in samples (>= 0).
+ *   ashrt_blend:   b[r][tau] = sum_s D[s][r][tau - fire[s]] over 0 <= tau -
+ *                  fire[s] < nt; D: [ns][nr][nt], b: [nr][nrec].
+ *   ashrt_deblend: the adjoint, D~[s][r][t] = b[r][fire[s] + t] (0 outside
+ *                  the record), written [ns][nr][nt], or [nr][ns][nt] (the
+ *                  batch of common receiver gathers) when receiver_major.
+ *   ashrt_resort:  out[b][a][t] = in[a][b][t] (in [na][nb][nt]); in and out
+ *                  must not alias. */
+int ashrt_blend(const float *D, int32_t ns, int32_t nr, int32_t nt, const int32_t *fire, float *b, int32_t nrec,
+                void *stream);
+int ashrt_deblend(const float *b, int32_t ns, int32_t nr, int32_t nt, const int32_t *fire, int32_t nrec, float *out,
+                  int32_t receiver_major, void *stream);
+int ashrt_resort(const float *in, int32_t na, int32_t nb, int32_t nt, float *out, void *stream);
+
 /* Time-domain (classical) ASHRT / AASHRT pair on the plan's single gather
  * (thesis Chapter 3, the hyperbolic Radon-operator table; Chapter 6,
  * equations ch6_AASHRT_forward and ch6_AASHRT_adjoint): a model sample at

@@ -121,6 +121,9 @@ def lib():
         "ashrt_autotune": (C.c_int, [P_desc, C.c_int, i32, C.POINTER(Tuning), C.POINTER(C.c_double)]),
         "fista_params_default": (None, [C.POINTER(FistaParams)]),
         "fista_invert": (C.c_int, [vp, C.POINTER(FistaParams), vp, vp, vp, vp, C.POINTER(FistaReport), vp, sz, vp]),
+        "ashrt_blend": (C.c_int, [vp, i32, i32, i32, vp, vp, i32, vp]),
+        "ashrt_deblend": (C.c_int, [vp, i32, i32, i32, vp, i32, vp, i32, vp]),
+        "ashrt_resort": (C.c_int, [vp, i32, i32, i32, vp, vp]),
         "ashrt_td_forward": (C.c_int, [vp, vp, vp, vp, vp]),
         "ashrt_td_adjoint": (C.c_int, [vp, vp, vp, vp, vp]),
         "ashrt_plan_destroy": (None, [vp]),

@@ -1583,3 +1583,28 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
   if (best_ms) *best_ms = best_t;
   return ASHRT_OK;
 }
+
+// ------------------------------------------------------------ survey cubes
+extern "C" int ashrt_blend(const float* D, int32_t ns, int32_t nr, int32_t nt, const int32_t* fire, float* b,
+                           int32_t nrec, void* stream) {
+  if (!D || !fire || !b) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  if (ns < 1 || nr < 1 || nt < 1 || nrec < 1) return fail(ASHRT_E_INVALID_ARG, "sizes must be >= 1");
+  HIP_TRY(launch_blend(D, ns, nr, nt, fire, b, nrec, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_deblend(const float* b, int32_t ns, int32_t nr, int32_t nt, const int32_t* fire, int32_t nrec,
+                             float* out, int32_t receiver_major, void* stream) {
+  if (!b || !fire || !out) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  if (ns < 1 || nr < 1 || nt < 1 || nrec < 1) return fail(ASHRT_E_INVALID_ARG, "sizes must be >= 1");
+  HIP_TRY(launch_deblend(b, ns, nr, nt, fire, nrec, out, receiver_major ? 1 : 0, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_resort(const float* in, int32_t na, int32_t nb, int32_t nt, float* out, void* stream) {
+  if (!in || !out) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  if (in == out) return fail(ASHRT_E_INVALID_ARG, "in and out must not alias");
+  if (na < 1 || nb < 1 || nt < 1) return fail(ASHRT_E_INVALID_ARG, "sizes must be >= 1");
+  HIP_TRY(launch_resort(in, na, nb, nt, out, (hipStream_t)stream));
+  return ASHRT_OK;
+}

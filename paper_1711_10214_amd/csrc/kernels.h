@@ -178,6 +178,12 @@ struct TdArgs {
   long long n_out;         // output samples of the launch
 };
 hipError_t launch_td(const TdArgs& a, bool forward, hipStream_t s);
+
+// Blending / pseudo-deblending / re-sort of survey cubes (survey_kernels.hip).
+hipError_t launch_blend(const float* D, int ns, int nr, int nt, const int* fire, float* b, int nrec, hipStream_t s);
+hipError_t launch_deblend(const float* b, int ns, int nr, int nt, const int* fire, int nrec, float* out, int rmaj,
+                          hipStream_t s);
+hipError_t launch_resort(const float* in, int na, int nb, int nt, float* out, hipStream_t s);
 bool x_size_is_tpl(int n);
 hipError_t launch_xfft_fwd(int key, const XfwdArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_xfft_inv(int key, const XinvArgs& a, size_t lds, hipStream_t s);
