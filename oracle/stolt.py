@@ -35,6 +35,13 @@ ch6_adj_operator):
 * S (Chapter 6) is the trace-sampling mask; the sum over panels and its
   spraying adjoint are the ch5 "summation operator".
 
+* Irregular data traces (positions x_i given): the data-side x transform is
+  a non-uniform DFT, D[l] = sum_i exp(-2 pi i l' x_i / (nxp dx)) d_i and
+  d_i = (1/nxp) sum_l exp(+2 pi i l' x_i / (nxp dx)) D[l], without the
+  Nyquist wavenumber (its phase is not real off the grid); the model (apex)
+  grid stays regular.  The thesis names non-uniform transforms as the way
+  to irregular sampling (Chapters 5 and 7) without detail: a reading.
+
 The map is stored as an explicit sparse matrix per panel so the adjoint is
 literally its transpose.
 """
@@ -73,6 +80,7 @@ class Geometry:
     fmax: float
     R: int
     wavelet: Optional[np.ndarray]  # [ntp//2+1] real or None
+    xpos: Optional[np.ndarray] = None  # [nx] data trace positions (m) or None = regular i*dx
     _cache: dict = field(default_factory=dict, repr=False, compare=False)
 
     @property
@@ -85,7 +93,7 @@ class Geometry:
 
 
 def geometry(nt, nx, dt, dx, vel, tau0=None, scale=None, ntp=0, nxp=0, fmin=0.0,
-             fmax=0.0, R=4, wavelet=None) -> Geometry:
+             fmax=0.0, R=4, wavelet=None, xpos=None) -> Geometry:
     vel = np.asarray(vel, dtype=np.float64).ravel()
     P = len(vel)
     tau0 = np.zeros(P, np.int64) if tau0 is None else np.asarray(tau0, np.int64).ravel()
@@ -95,8 +103,11 @@ def geometry(nt, nx, dt, dx, vel, tau0=None, scale=None, ntp=0, nxp=0, fmin=0.0,
     if wavelet is not None:
         wavelet = np.asarray(wavelet, np.float64).ravel()
         assert wavelet.shape == (ntp // 2 + 1,)
+    if xpos is not None:
+        xpos = np.asarray(xpos, np.float64).ravel()
+        assert xpos.shape == (nx,)
     return Geometry(nt, nx, float(dt), float(dx), ntp, nxp, vel, tau0, scale,
-                    float(fmin), float(fmax), int(R), wavelet)
+                    float(fmin), float(fmax), int(R), wavelet, xpos)
 
 
 def band(g: Geometry):
@@ -184,6 +195,34 @@ def _Finv(g: Geometry, X):
     return np.fft.irfft(np.fft.ifft(X, axis=0), n=g.ntp, axis=1)[: g.nx, : g.nt]
 
 
+def nudft_matrix(g: Geometry):
+    """E[i, l] = exp(+2 pi i l' x_i / (nxp dx)) for the data traces at
+    g.xpos, with the Nyquist wavenumber column zero (irregular positions:
+    the thesis' suggested extension of F_x to non-uniform sampling, Chapter
+    5 and Chapter 7).  At x_i = i dx it is the inverse-DFT kernel without
+    the Nyquist term."""
+    lp = signed_kx_index(g.nxp).astype(np.float64)
+    E = np.exp(2j * np.pi * np.outer(g.xpos, lp) / (g.nxp * g.dx))
+    E[:, g.nxp // 2] = 0.0
+    return E
+
+
+def _F_data(g: Geometry, d):
+    """Data-side F: as _F, with the x transform a non-uniform DFT when the
+    traces sit at g.xpos: D[l] = sum_i exp(-2 pi i l' x_i / (nxp dx)) d_i."""
+    if g.xpos is None:
+        return _F(g, d)
+    return nudft_matrix(g).conj().T @ np.fft.rfft(d, n=g.ntp, axis=1)
+
+
+def _Finv_data(g: Geometry, D):
+    """Data-side F^-1: as _Finv, with d_i = (1/nxp) sum_l exp(+2 pi i l' x_i /
+    (nxp dx)) D[l] (x first), then the inverse real FFT along t."""
+    if g.xpos is None:
+        return _Finv(g, D)
+    return np.fft.irfft((nudft_matrix(g) @ D) / g.nxp, n=g.ntp, axis=1)[:, : g.nt]
+
+
 def forward(g: Geometry, m, mask=None):
     """d = S sum_p F^-1 T_p M_p F m_p  (model [P][nx][nt] -> data [nx][nt])."""
     m = np.asarray(m, dtype=np.float64)
@@ -193,7 +232,7 @@ def forward(g: Geometry, m, mask=None):
         Mp = _F(g, m[p])
         Dp = (stolt_matrix(g, p) @ Mp.ravel()).reshape(g.nxp, g.H)
         D += data_bin_factor(g, p)[None, :] * Dp
-    d = _Finv(g, D)
+    d = _Finv_data(g, D)
     if mask is not None:
         d = d * np.asarray(mask, np.float64)[:, None]
     return d
@@ -205,7 +244,7 @@ def adjoint(g: Geometry, d, mask=None):
     assert d.shape == (g.nx, g.nt), d.shape
     if mask is not None:
         d = d * np.asarray(mask, np.float64)[:, None]
-    D = _F(g, d)
+    D = _F_data(g, d)
     m = np.empty((g.npanel, g.nx, g.nt))
     for p in range(g.npanel):
         E = np.conj(data_bin_factor(g, p))[None, :] * D

@@ -317,3 +317,79 @@ def test_wavelet_weight_is_zero_phase_filter_and_scale_is_linear():
     filt = np.fft.irfft(W[None, :] * np.fft.rfft(d0, axis=1), n=nt, axis=1)
     np.testing.assert_allclose(oracle.forward(gw, m), filt, atol=1e-12)
     np.testing.assert_allclose(oracle.forward(gs, m), 2.0 * d0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- irregular traces
+def _irr_geom(xpos=None, nxp=0):
+    return oracle.geometry(48, 16, 0.004, 12.5, [1600.0, 2500.0], fmax=100.0, xpos=xpos, nxp=nxp)
+
+
+def test_nudft_at_regular_positions_is_the_dft_without_nyquist():
+    g = _irr_geom(xpos=np.arange(16) * 12.5)
+    E = oracle.stolt.nudft_matrix(g)
+    rng = np.random.default_rng(0)
+    D = rng.standard_normal((g.nxp, 5)) + 1j * rng.standard_normal((g.nxp, 5))
+    D[g.nxp // 2] = 0.0
+    ref = np.fft.ifft(D, axis=0)[:16] * g.nxp
+    assert np.allclose(E @ D, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_irregular_operator_reduces_to_regular_when_nyquist_is_empty():
+    """At regular positions the irregular pair differs from the regular one
+    only by the Nyquist wavenumber; a model band-limited below it gives the
+    same data."""
+    rng = np.random.default_rng(1)
+    greg = _irr_geom()
+    girr = _irr_geom(xpos=np.arange(16) * 12.5)
+    m = rng.standard_normal((2, 16, 48))
+    # remove the Nyquist wavenumber of the padded x grid from the model
+    Mx = np.fft.fft(m, n=greg.nxp, axis=1)
+    Mx[:, greg.nxp // 2] = 0.0
+    m = np.real(np.fft.ifft(Mx, axis=1))[:, :16]
+    # the model-side transforms zero-pad the truncated model, so compare the
+    # part that does not see the Nyquist term: both operators on the same m
+    d_reg = oracle.forward(greg, m)
+    d_irr = oracle.forward(girr, m)
+    # the difference is exactly the Nyquist-row contribution of the regular operator
+    diff = d_reg - d_irr
+    D = np.zeros((greg.nxp, greg.H), complex)
+    for p in range(2):
+        Mp = oracle.stolt._F(greg, m[p])
+        Dp = (oracle.stolt_matrix(greg, p) @ Mp.ravel()).reshape(greg.nxp, greg.H)
+        D += oracle.data_bin_factor(greg, p)[None, :] * Dp
+    Dn = np.zeros_like(D)
+    Dn[greg.nxp // 2] = D[greg.nxp // 2]
+    assert np.allclose(diff, oracle.stolt._Finv(greg, Dn), rtol=1e-10, atol=1e-12)
+
+
+def test_irregular_dot_product():
+    rng = np.random.default_rng(2)
+    xpos = np.sort(rng.uniform(0, 15 * 12.5, 16))
+    g = _irr_geom(xpos=xpos)
+    m = rng.standard_normal((2, 16, 48))
+    d = rng.standard_normal((16, 48))
+    lhs = np.sum(oracle.forward(g, m) * d)
+    rhs = np.sum(m * oracle.adjoint(g, d))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(oracle.forward(g, m)) * np.linalg.norm(d)
+
+
+def test_irregular_forward_is_the_trigonometric_interpolant():
+    """Data at shifted positions equal the band-limited (Fourier-series)
+    interpolation, on the padded periodic x grid, of the data at regular
+    positions."""
+    rng = np.random.default_rng(3)
+    m = rng.standard_normal((2, 16, 48))
+    shift = 0.37 * 12.5
+    g0 = _irr_geom(xpos=np.arange(16) * 12.5)
+    g1 = _irr_geom(xpos=np.arange(16) * 12.5 + shift)
+    # full padded-grid data of g0's spectrum, then shift by the Fourier phase
+    D = np.zeros((g0.nxp, g0.H), complex)
+    for p in range(2):
+        Mp = oracle.stolt._F(g0, m[p])
+        Dp = (oracle.stolt_matrix(g0, p) @ Mp.ravel()).reshape(g0.nxp, g0.H)
+        D += oracle.data_bin_factor(g0, p)[None, :] * Dp
+    D[g0.nxp // 2] = 0.0
+    lp = oracle.stolt.signed_kx_index(g0.nxp)
+    Ds = D * np.exp(2j * np.pi * lp * shift / (g0.nxp * 12.5))[:, None]
+    ref = oracle.stolt._Finv(g0, Ds)
+    assert np.allclose(oracle.forward(g1, m), ref, rtol=1e-10, atol=1e-12)
