@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define ASHRT_ABI_VERSION 4
+#define ASHRT_ABI_VERSION 5
 
 enum ashrt_status {
   ASHRT_OK = 0,
@@ -95,6 +95,10 @@ typedef struct ashrt_desc {
   double fmin_hz, fmax_hz;     /* mapped band; fmax_hz <= 0 means up to ntp/2-1                      */
   int32_t half_width;          /* R, interpolation half-width in bins, 1..8 (0 = default 4)          */
   const double *wavelet_amp;   /* [ntp/2+1] real per-bin weight W_j (zero-phase wavelet), or NULL    */
+  const double *x_pos;         /* [nx] data trace positions (m, finite), or NULL = regular i*dx.  With
+                                  positions, the data-side x transforms are non-uniform DFTs at them
+                                  (no Nyquist wavenumber); the model (apex) grid stays i*dx.  Thesis
+                                  Chapters 5 and 7 name non-uniform transforms for irregular traces. */
 } ashrt_desc;
 
 /* Inversion settings (thesis Chapter 4). */

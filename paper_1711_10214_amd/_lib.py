@@ -37,6 +37,7 @@ class AshrtDesc(C.Structure):
         ("fmin_hz", C.c_double), ("fmax_hz", C.c_double),
         ("half_width", C.c_int32),
         ("wavelet_amp", C.POINTER(C.c_double)),
+        ("x_pos", C.POINTER(C.c_double)),
     ]
 
 
@@ -95,7 +96,7 @@ class PlanInfo(C.Structure):
 _lib = None
 
 
-ABI_VERSION = 4  # struct layouts below match include/ashrt.h at this version
+ABI_VERSION = 5  # struct layouts below match include/ashrt.h at this version
 
 
 def lib():

@@ -57,8 +57,9 @@ class _Desc:
     """Owns the host arrays a descriptor points to."""
 
     def __init__(self, nt, nx, dt, dx, vel, tau0=None, scale=None, ntp=0, nxp=0, fmin=0.0,
-                 fmax=0.0, half_width=4, wavelet=None):
+                 fmax=0.0, half_width=4, wavelet=None, xpos=None):
         self.vel = np.ascontiguousarray(np.asarray(vel, np.float64).ravel())
+        self.xpos = None if xpos is None else np.ascontiguousarray(np.asarray(xpos, np.float64).ravel())
         P = len(self.vel)
         self.tau0 = None if tau0 is None else np.ascontiguousarray(np.asarray(tau0, np.int32).ravel())
         self.scale = None if scale is None else np.ascontiguousarray(np.asarray(scale, np.float64).ravel())
@@ -74,6 +75,9 @@ class _Desc:
         d.fmin_hz, d.fmax_hz = float(fmin), float(fmax)
         d.half_width = int(half_width)
         d.wavelet_amp = _dptr(self.wavelet, C.c_double) if self.wavelet is not None else None
+        if self.xpos is not None:
+            assert self.xpos.size == int(nx), "xpos needs one position per trace"
+        d.x_pos = _dptr(self.xpos, C.c_double) if self.xpos is not None else None
         self.c = d
 
 
@@ -82,9 +86,9 @@ def validate_desc(**kw) -> int:
     return L.lib().ashrt_desc_validate(C.byref(_Desc(**kw).c))
 
 
-def _desc_kwargs(nt, nx, dt, dx, vel, tau0, scale, ntp, nxp, fmin, fmax, half_width, wavelet):
+def _desc_kwargs(nt, nx, dt, dx, vel, tau0, scale, ntp, nxp, fmin, fmax, half_width, wavelet, xpos=None):
     return dict(nt=nt, nx=nx, dt=dt, dx=dx, vel=vel, tau0=tau0, scale=scale, ntp=ntp, nxp=nxp, fmin=fmin,
-                fmax=fmax, half_width=half_width, wavelet=wavelet)
+                fmax=fmax, half_width=half_width, wavelet=wavelet, xpos=xpos)
 
 
 def _tuning(t):
@@ -108,14 +112,15 @@ class Plan:
     """One gather geometry and its panel list (velocity, asymptote shift, scale)."""
 
     def __init__(self, nt, nx, dt, dx, vel, tau0=None, scale=None, ntp=0, nxp=0, fmin=0.0,
-                 fmax=0.0, half_width=4, wavelet=None, device=0, tuning=None):
+                 fmax=0.0, half_width=4, wavelet=None, device=0, tuning=None, xpos=None):
         """tuning: None (built-in tiling), "auto" (run the autotuner, cached
         per geometry) or a dict with tile_model / tile_data / nchunk."""
-        self._desc = _Desc(nt, nx, dt, dx, vel, tau0, scale, ntp, nxp, fmin, fmax, half_width, wavelet)
+        self._desc = _Desc(nt, nx, dt, dx, vel, tau0, scale, ntp, nxp, fmin, fmax, half_width, wavelet, xpos)
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         if isinstance(tuning, str) and tuning == "auto":
             tuning = autotune(device=self.device.index or 0, **_desc_kwargs(nt, nx, dt, dx, vel, tau0, scale, ntp,
-                                                                          nxp, fmin, fmax, half_width, wavelet))
+                                                                          nxp, fmin, fmax, half_width, wavelet,
+                                                                          xpos))
         self.tuning = tuning
         tn = _tuning(tuning)
         h = C.c_void_p()

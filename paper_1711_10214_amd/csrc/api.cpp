@@ -182,6 +182,7 @@ struct GatherHost {
   int nrows, tileT, ntiles, tileTd, ntilesd, nchunk;
   std::vector<PanelDev> panels;
   std::vector<float> wav;
+  std::vector<double> xpos;  // irregular data-trace positions (m), empty = regular
   long long d_off, m_off, mask_off, X_off, H_off, Dp_off;
   long long nd() const { return (long long)z.nx * z.nt; }
   long long nm() const { return (long long)z.P * z.nx * z.nt; }
@@ -296,6 +297,12 @@ static int build_gather(const ashrt_desc* d, const ashrt_tuning* tn, GatherHost*
     gh->panels[p].c2 = c * c;
     gh->panels[p].scale = d->panel_scale ? (float)d->panel_scale[p] : 1.0f;
     gh->panels[p].n0 = d->tau0_samples ? d->tau0_samples[p] : 0;
+  }
+  gh->xpos.clear();
+  if (d->x_pos) {
+    for (int i = 0; i < z.nx; ++i)
+      if (!std::isfinite(d->x_pos[i])) return fail(ASHRT_E_INVALID_ARG, "x_pos must be finite");
+    gh->xpos.assign(d->x_pos, d->x_pos + z.nx);
   }
   gh->wav.clear();
   if (d->wavelet_amp) {
@@ -454,6 +461,21 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
       wav.insert(wav.end(), gh.wav.begin(), gh.wav.end());
     } else {
       G.wav_off = -1;
+    }
+    G.nudft_off = -1;
+    if (!gh.xpos.empty()) {
+      // exp(-2 pi i r x / (nxp dx)), r = 0..nrows-1; the phase in turns is
+      // reduced in FP64 before the FP32 rounding
+      if (tw.size() + (size_t)gh.nrows * gh.z.nx > (size_t)INT32_MAX)
+        return fail(ASHRT_E_UNSUPPORTED_SIZE, "irregular-trace tables too large");
+      G.nudft_off = (int)tw.size();
+      const double period = (double)gh.z.nxp * descs[gi].dx;
+      for (int r = 0; r < gh.nrows; ++r)
+        for (int x = 0; x < gh.z.nx; ++x) {
+          double turns = std::fmod((double)r * gh.xpos[x] / period, 1.0);
+          const double a = -2.0 * M_PI * turns;
+          tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+        }
     }
     G.tileT = gh.tileT;
     G.ntiles = gh.ntiles;
@@ -1430,6 +1452,8 @@ extern "C" int ashrt_adjoint(const ashrt_plan* plan, const float* d, float* m, c
 extern "C" int ashrt_td_forward(const ashrt_plan* plan, const float* m, float* d, const uint8_t* mask, void* stream) {
   if (!plan || !m || !d) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
   const PlanImpl& P = plan->impl;
+  if (!P.g[0].xpos.empty())
+    return fail(ASHRT_E_NOT_IMPLEMENTED, "the time-domain pair takes regular traces only (plan has x_pos)");
   DeviceGuard dg(P.device);
   if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
   TdArgs a{P.d_gd, P.d_pan, const_cast<float*>(m), d, mask, (long long)P.g[0].nd()};
@@ -1440,6 +1464,8 @@ extern "C" int ashrt_td_forward(const ashrt_plan* plan, const float* m, float* d
 extern "C" int ashrt_td_adjoint(const ashrt_plan* plan, const float* d, float* m, const uint8_t* mask, void* stream) {
   if (!plan || !m || !d) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
   const PlanImpl& P = plan->impl;
+  if (!P.g[0].xpos.empty())
+    return fail(ASHRT_E_NOT_IMPLEMENTED, "the time-domain pair takes regular traces only (plan has x_pos)");
   DeviceGuard dg(P.device);
   if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the plan's device");
   TdArgs a{P.d_gd, P.d_pan, m, const_cast<float*>(d), mask, (long long)P.g[0].nm()};
@@ -1490,7 +1516,7 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
   // phase ramps or bin weights -- not on the velocity values beyond that
   char key[192];
   std::snprintf(key, sizeof key, "%d:%d,%d,%d,%d,%d,%d,%d,%d,%d", device, z.nt, z.nx, z.ntp, z.nxp, z.P, z.R, z.jlo,
-                z.jhi, (desc->tau0_samples || desc->wavelet_amp) ? 1 : 0);
+                z.jhi, ((desc->tau0_samples || desc->wavelet_amp) ? 1 : 0) + (desc->x_pos ? 2 : 0));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);

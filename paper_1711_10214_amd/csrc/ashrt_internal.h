@@ -44,7 +44,8 @@ struct GatherDev {
   int dit_lo, dit_hi;   // data-vector work items of this gather
   int xm_lo, xm_hi;     // model x-FFT tile items of this gather (partial sums)
   int xd_lo, xd_hi;     // data x-FFT tile items of this gather
-  int pad_;
+  int nudft_off;        // float2 offset of the irregular-trace table exp(-2 pi i r x_pos / (nxp dx)),
+                        // [nrows][nx], in the twiddle pool; -1 = regular traces
   long long d_off;      // float offset of the gather in packed data arrays
   long long m_off;      // float offset in packed model arrays
   long long mask_off;   // byte offset in packed trace masks

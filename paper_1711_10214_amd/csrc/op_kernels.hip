@@ -298,6 +298,31 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       buf[i * bs + px<NX>(nx + xx)] = make_float2(0.f, 0.f);
     }
     __syncthreads();
+    if (!A.is_model && G.nudft_off >= 0) {
+      // irregular traces: non-uniform DFT over the trace positions,
+      // H_t[r] = sum_x d_t[x] exp(-2 pi i r x_pos / (nxp dx)); row 0 packs
+      // (H_t[0], 0) (no Nyquist wavenumber off the grid)
+      const float2* __restrict__ E = A.tw + G.nudft_off;
+      float2* __restrict__ dst = A.dst + G.H_off;
+      for (int idx = threadIdx.x; idx < nrows * T; idx += kThreads) {
+        const int r = idx / T, c = idx - r * T, t = t0 + c;
+        if (t >= nt) continue;
+        const float2* Z = buf + (c >> 1) * bs;
+        float2 acc = make_float2(0.f, 0.f);
+        if (r == 0) {
+          for (int x = 0; x < nx; ++x) acc.x += (c & 1) ? Z[px<NX>(x)].y : Z[px<NX>(x)].x;
+        } else {
+          const float2* Er = E + (long long)r * nx;
+          for (int x = 0; x < nx; ++x) {
+            const float v = (c & 1) ? Z[px<NX>(x)].y : Z[px<NX>(x)].x;
+            acc = cfma(v, Er[x], acc);
+          }
+        }
+        dst[(long long)r * nt + t] = acc;
+      }
+      __syncthreads();
+      continue;
+    }
     xfft_tile<NX, false>(buf, nxp, half, bs, twl);
 
     float2* __restrict__ dst = A.dst + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
@@ -340,6 +365,44 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const float2* __restrict__ src = A.src + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
     float2* twl = lds;
     float2* buf = lds + fft_tw_slots(NX, nxp);
+    if (!A.is_model && G.nudft_off >= 0) {
+      // irregular traces: d_t[x] = (1/nxp) (Re H_t[0] + 2 Re sum_{r>=1} H_t[r]
+      // exp(+2 pi i r x_pos / (nxp dx))), the rows staged column by column
+      for (int idx = threadIdx.x; idx < nrows * T; idx += kThreads) {
+        const int l = idx / T, c = idx - l * T, t = t0 + c;
+        buf[c * nrows + l] = (t < nt) ? src[(long long)l * nt + t] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+      const float2* __restrict__ E = A.tw + G.nudft_off;
+      const float inv = 1.0f / (float)nxp;
+      const long long fbase = G.d_off;
+      const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
+      double ss = 0.0;
+      for (int idx = threadIdx.x; idx < nx * T; idx += kThreads) {
+        const int x = idx / T, c = idx - x * T, t = t0 + c;
+        if (t >= nt) continue;
+        const float2* hc = buf + c * nrows;
+        float acc = 0.f;
+        for (int r = 1; r < nrows; ++r) {
+          const float2 e = E[(long long)r * nx + x];
+          acc = fmaf(hc[r].x, e.x, fmaf(hc[r].y, e.y, acc));
+        }
+        float v = (hc[0].x + 2.0f * acc) * inv;
+        const long long o = fbase + (long long)x * nt + t;
+        if (A.raw_out) A.raw_out[o] = v;
+        if (A.sub) v = A.sub[o] - v;
+        if (tm && tm[x] == 0) v = 0.f;
+        if (A.wmul) v *= A.wmul[o];
+        A.out[o] = v;
+        ss += (double)v * (double)v;
+      }
+      if (A.part) {
+        const double tot = block_sum(ss, sh);
+        if (threadIdx.x == 0) A.part[A.item_base + it] = tot;
+      }
+      __syncthreads();
+      continue;
+    }
     stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
 
     for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {

@@ -14,15 +14,15 @@ def rel_l2(a, b):
 
 
 def geom_kwargs(nt, nx, dt, dx, vel, tau0=None, scale=None, ntp=0, nxp=0, fmin=0.0, fmax=0.0,
-                half_width=4, wavelet=None):
+                half_width=4, wavelet=None, xpos=None):
     return dict(nt=nt, nx=nx, dt=dt, dx=dx, vel=vel, tau0=tau0, scale=scale, ntp=ntp, nxp=nxp,
-                fmin=fmin, fmax=fmax, half_width=half_width, wavelet=wavelet)
+                fmin=fmin, fmax=fmax, half_width=half_width, wavelet=wavelet, xpos=xpos)
 
 
 def oracle_geometry(kw):
     return oracle.geometry(kw["nt"], kw["nx"], kw["dt"], kw["dx"], kw["vel"], tau0=kw["tau0"],
                            scale=kw["scale"], ntp=kw["ntp"], nxp=kw["nxp"], fmin=kw["fmin"],
-                           fmax=kw["fmax"], R=kw["half_width"], wavelet=kw["wavelet"])
+                           fmax=kw["fmax"], R=kw["half_width"], wavelet=kw["wavelet"], xpos=kw.get("xpos"))
 
 
 def f32(x):

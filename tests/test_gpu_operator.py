@@ -57,6 +57,13 @@ CASES = {
                                            tau0=[0, 7, 0, 23], scale=[1.0, 0.5, 2.0, 1.5],
                                            fmin=5.0, fmax=80.0), 0.3),
     "half-width-2": (geom_kwargs(160, 40, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0, half_width=2), 0.0),
+    "irregular-jittered": (geom_kwargs(256, 48, 0.004, 12.5, [1500.0, 2200.0, 3100.0], fmax=100.0,
+                                       xpos=list(np.arange(48) * 12.5 + np.random.default_rng(8).uniform(-5, 5, 48))),
+                           0.2),
+    "irregular-aashrt-random": (geom_kwargs(200, 40, 0.004, 10.0, [1700.0, 1700.0, 2600.0], tau0=[0, 9, 0],
+                                            fmax=90.0,
+                                            xpos=list(np.sort(np.random.default_rng(9).uniform(0, 390.0, 40)))),
+                                0.0),
     "half-width-8": (geom_kwargs(160, 40, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0, half_width=8), 0.0),
     "tiny": (geom_kwargs(2, 2, 0.004, 12.5, [2000.0], ntp=8, nxp=4), 0.0),
 }
