@@ -12,7 +12,7 @@
 namespace ashrt {
 
 constexpr int kThreads = 256;          // threads per workgroup (all kernels but the row passes)
-constexpr int kRowThreads = 512;       // threads per workgroup of the forward/adjoint row passes
+constexpr int kRowThreads = 256;       // threads per workgroup of the forward/adjoint row passes
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
 constexpr int kXfftTilePoints = 4096;  // complex points of a model x-FFT tile (T = 2 * this / nxp columns)
