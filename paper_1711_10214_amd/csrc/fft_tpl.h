@@ -198,13 +198,15 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
 
 // PAIRS_IN: the first pass reads the pair layout; PAIRS_OUT: the last pass
 // writes it.
-template <int N, int PASS, int NBN, bool INV, int NT, bool PAIRS_IN = false, bool PAIRS_OUT = false>
+// Passes PASS .. END-1 (END defaults to all of them).
+template <int N, int PASS, int NBN, bool INV, int NT, bool PAIRS_IN = false, bool PAIRS_OUT = false,
+          int END = FftPlan<N>::npass>
 __device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, const float2* twp) {
-  if constexpr (PASS < FftPlan<N>::npass) {
+  if constexpr (PASS < END) {
     constexpr int IO = (PAIRS_IN && PASS == 0) ? 1 : ((PAIRS_OUT && PASS == FftPlan<N>::npass - 1) ? 2 : 0);
     static_assert(!(PAIRS_IN && PAIRS_OUT && FftPlan<N>::npass == 1), "pair input and output need two passes");
     tpl_pass<N, PASS, NBN, INV, NT, IO>(buf, nb, bstride, twp);
-    tpl_passes<N, PASS + 1, NBN, INV, NT, PAIRS_IN, PAIRS_OUT>(buf, nb, bstride, twp);
+    tpl_passes<N, PASS + 1, NBN, INV, NT, PAIRS_IN, PAIRS_OUT, END>(buf, nb, bstride, twp);
   }
 }
 
@@ -218,6 +220,105 @@ __device__ __forceinline__ void fft_tpl(float2* buf, int nb, int bstride, const 
 template <int N, bool INV, int NT>
 __device__ __forceinline__ void fft_tpl_to_pairs(float2* buf, const float2* twp) {
   tpl_passes<N, 0, N, INV, NT, false, true>(buf, 1, fft_padlen(N), twp);
+}
+
+// First-pass inputs of a length-N transform held in registers: the
+// butterfly with id = threadIdx.x + i NT takes x[id + r N/R0], r < R0 (R0 the
+// first radix), so a caller can load them straight from global memory.
+template <int N, int NT>
+struct FftRegsIn {
+  static constexpr int R = FftPlan<N>::radix(0);
+  static constexpr int B = N / R;
+  static constexpr int MAXB = (B + NT - 1) / NT;
+  static_assert(FftPlan<N>::npass >= 2, "register input needs a later pass to write the pair layout");
+  float2 v[MAXB][R];
+  // x[t] = src[t] for t < nt, zero after
+  __device__ __forceinline__ void load(const float2* __restrict__ src, int nt) {
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int id = (int)threadIdx.x + i * NT;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int t = id + r * B;
+        v[i][r] = (id < B && t < nt) ? src[t] : make_float2(0.f, 0.f);
+      }
+    }
+  }
+};
+
+// Transform whose first pass takes its inputs from registers (no twiddles
+// there: its span is 1) and whose output is left in the pair layout, in two
+// calls: regs_pass0 (the caller must have finished every read of buf; the
+// registers are free again when it returns) and rest_to_pairs.
+template <int N, bool INV, int NT>
+__device__ __forceinline__ void fft_tpl_regs_pass0(float2* buf, FftRegsIn<N, NT>& in) {
+  using I = FftRegsIn<N, NT>;
+#pragma unroll
+  for (int i = 0; i < I::MAXB; ++i) {
+    const int id = (int)threadIdx.x + i * NT;
+    if (id < I::B) {
+      dft_r<I::R, INV>(in.v[i]);
+#pragma unroll
+      for (int r = 0; r < I::R; ++r) buf[fft_pad(id * I::R + r)] = in.v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, bool INV, int NT>
+__device__ __forceinline__ void fft_tpl_rest_to_pairs(float2* buf, const float2* twp) {
+  tpl_passes<N, 1, N, INV, NT, false, true>(buf, 1, fft_padlen(N), twp);
+}
+
+// Outputs of a length-N transform's last pass held in registers: the
+// butterfly with id = threadIdx.x + i NT (id < N/RL, RL the last radix) holds
+// output element id + r N/RL in v[i][r], so a caller can store them
+// straight to global memory.
+template <int N, int NT>
+struct FftRegsOut {
+  static constexpr int L = FftPlan<N>::npass - 1;
+  static constexpr int R = FftPlan<N>::radix(L);
+  static constexpr int B = N / R;
+  static constexpr int MAXB = (B + NT - 1) / NT;
+  static_assert(L >= 1 && FftPlan<N>::ns(L) == B, "the last pass spans N/R");
+  float2 v[MAXB][R];
+};
+
+// Passes FIRST .. last of a transform (FIRST reading the pair layout when
+// PAIRS_IN, for FIRST == 0) whose last pass leaves its outputs in
+// registers; buf may be reused once every thread has passed a barrier after
+// this returns.
+template <int N, bool INV, int NT, int FIRST, bool PAIRS_IN>
+__device__ __forceinline__ void fft_tpl_passes_to_regs(float2* buf, const float2* twp, FftRegsOut<N, NT>& out) {
+  using O = FftRegsOut<N, NT>;
+  using P = FftPlan<N>;
+  static_assert(!PAIRS_IN || FIRST == 0, "only the first pass reads pairs");
+  tpl_passes<N, FIRST, N, INV, NT, PAIRS_IN, false, O::L>(buf, 1, fft_padlen(N), twp);
+  constexpr int TW = P::twoff(O::L);
+#pragma unroll
+  for (int i = 0; i < O::MAXB; ++i) {
+    const int id = (int)threadIdx.x + i * NT;
+    if (id < O::B) {
+#pragma unroll
+      for (int r = 0; r < O::R; ++r) out.v[i][r] = buf[fft_pad(id + r * O::B)];
+      float2 w1 = twp[TW + id];
+      if (INV) w1.y = -w1.y;
+      float2 w = w1;
+#pragma unroll
+      for (int r = 1; r < O::R; ++r) {
+        out.v[i][r] = cmul(out.v[i][r], w);
+        if (r + 1 < O::R) w = cmul(w, w1);
+      }
+      dft_r<O::R, INV>(out.v[i]);
+    }
+  }
+}
+
+// Transform whose input is read from the pair layout (bins 0 and N/2 taken
+// as zero) and whose last pass leaves its outputs in registers.
+template <int N, bool INV, int NT>
+__device__ __forceinline__ void fft_tpl_from_pairs_to_regs(float2* buf, const float2* twp, FftRegsOut<N, NT>& out) {
+  fft_tpl_passes_to_regs<N, INV, NT, 0, true>(buf, twp, out);
 }
 
 // One transform of length N whose input is read from the pair layout (bins

@@ -138,6 +138,16 @@ __device__ __forceinline__ void init_tap_trig(float* ct, float* st, int R) {
   }
 }
 
+// Smallest j >= 0 with j^2 >= a2 (in FP64, as make_taps tests it): bins
+// below it have no taps.
+__device__ __forceinline__ int cone_first_bin(double a2) {
+  if (!(a2 > 0.0)) return 0;
+  int j = (int)ceil(sqrt(a2));
+  if (j > 0 && (double)(j - 1) * (double)(j - 1) >= a2) --j;
+  if ((double)j * (double)j < a2) ++j;
+  return j;
+}
+
 template <int R>
 __device__ __forceinline__ Taps taps_of(int j, double a2, int Rrt) {
   if constexpr (R > 0) return make_taps<R>(j, a2);
@@ -533,9 +543,22 @@ __device__ __forceinline__ void pairs_to_natural(float2* buf, int n) {
 // (the +l and -l spectra); row 0 separates the packed kx = 0 / Nyquist
 // spectra so that the same reading gives them.
 template <int N, int NT>
+__device__ __forceinline__ void row_spectrum_lds(float2* buf, int r, int ntp, const float2* twl);
+
+template <int N, int NT>
 __device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restrict__ src, int r, int nt,
                                              int ntp, const float2* twl) {
   for (int t = threadIdx.x; t < ntp; t += NT) buf[px<N>(t)] = (t < nt) ? src[t] : make_float2(0.f, 0.f);
+  row_spectrum_lds<N, NT>(buf, r, ntp, twl);
+}
+
+// Forward time FFT of the row held in buf (natural order, zero-padded to
+// ntp), leaving the pair layout described above.
+template <int N, int NT>
+__device__ __forceinline__ void row0_separate(float2* buf, int ntp);
+
+template <int N, int NT>
+__device__ __forceinline__ void row_spectrum_lds(float2* buf, int r, int ntp, const float2* twl) {
   __syncthreads();
   if constexpr (N > 0) {
     fft_tpl_to_pairs<N, false, NT>(buf, twl);
@@ -543,7 +566,14 @@ __device__ __forceinline__ void row_spectrum(float2* buf, const float2* __restri
     fft_lds<NT, kRowMaxN, false>(buf, ntp, 1, ntp, twl);
     natural_to_pairs<NT>(buf, ntp);
   }
-  if (r == 0) {
+  if (r == 0) row0_separate<N, NT>(buf, ntp);
+}
+
+// Row 0 holds the kx = 0 and Nyquist spectra packed as M(0) + i M(N):
+// separate them in place so the pair reading gives the two halves.
+template <int N, int NT>
+__device__ __forceinline__ void row0_separate(float2* buf, int ntp) {
+  {
     float4* P = reinterpret_cast<float4*>(buf);
     for (int k = 1 + threadIdx.x; k < ntp / 2; k += NT) {
       const float4 q = P[k];
@@ -600,12 +630,41 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
   const double lup2 = (double)lu * (double)lu;
   const double llo2 = (double)ll * (double)ll;
 
+  const float2* __restrict__ xrow = A.X + G.X_off + (long long)r * nt;  // panel p's row at + p nrows nt
+  const long long pstride = (long long)nrows * nt;
+  // compile-time lengths: the next panel's row and panel constants are
+  // loaded while this panel is transformed and mapped
+  // (the first FFT pass takes them straight from registers)
+  FftRegsIn<(N > 0 ? N : kRowMaxN), NT> pf;
+  PanelDev pdn;
+  if constexpr (N > 0) {
+    if (p0 < p1) {
+      pf.load(xrow + p0 * pstride, nt);
+      pdn = A.panels[G.panel_off + p0];
+    }
+  }
+
   for (int p = p0; p < p1; ++p) {
-    row_spectrum<N, NT>(buf, A.X + G.X_off + ((long long)p * nrows + r) * nt, r, nt, ntp, twl);
-    const PanelDev PD = A.panels[G.panel_off + p];
+    PanelDev PD;
+    if constexpr (N > 0) {
+      PD = pdn;
+      fft_tpl_regs_pass0<N, false, NT>(buf, pf);
+      if (p + 1 < p1) {
+        pf.load(xrow + (p + 1) * pstride, nt);
+        pdn = A.panels[G.panel_off + p + 1];
+      }
+      fft_tpl_rest_to_pairs<N, false, NT>(buf, twl);
+      if (r == 0) row0_separate<N, NT>(buf, ntp);
+    } else {
+      row_spectrum<N, NT>(buf, xrow + p * pstride, r, nt, ntp, twl);
+      PD = A.panels[G.panel_off + p];
+    }
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
+    // rows >= 1 map only bins inside the cone (the rest add zero); row 0's
+    // l = 0 half covers the whole band
+    const int jstart = (r != 0) ? max(jlo, cone_first_bin(PD.c2 * lup2)) : jlo;
 #pragma unroll 1
-    for (int j = jlo + (int)threadIdx.x; j <= jhi; j += NT) {
+    for (int j = jstart + (int)threadIdx.x; j <= jhi; j += NT) {
       const Taps tu = taps_of<RC>(j, PD.c2 * lup2, R);
       float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
       if (r != 0) {
@@ -689,7 +748,8 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
   float2* twl = lds;
   float2* buf = lds + fft_tw_slots(N, ntp);
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
-  for (int k = threadIdx.x; k < ntp; k += NT) {
+  // time-spectrum bin k of the row: the chunk sums, Hermitian completion
+  auto bin = [&](int k) {
     float2 v = make_float2(0.f, 0.f);
     const int j = (k >= jlo && k <= jhi) ? k : ((ntp - k >= jlo && ntp - k <= jhi) ? ntp - k : -1);
     if (j >= 0) {
@@ -705,13 +765,39 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
         v = (r == 0) ? make_float2(su.x + sl.y, -su.y + sl.x) : cconj(sl);
       }
     }
-    buf[px<N>(k)] = v;
-  }
-  __syncthreads();
-  row_inverse<N, NT>(buf, ntp, twl);
+    return v;
+  };
   const float inv = 1.0f / (float)ntp;
   float2* __restrict__ dst = A.H + G.H_off + (long long)r * nt;
-  for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(buf[px<N>(t)], inv);
+  if constexpr (N > 0) {
+    // first pass from registers, last pass to global memory
+    FftRegsIn<N, NT> in;
+#pragma unroll
+    for (int i = 0; i < FftRegsIn<N, NT>::MAXB; ++i) {
+      const int id = (int)threadIdx.x + i * NT;
+#pragma unroll
+      for (int q = 0; q < FftRegsIn<N, NT>::R; ++q)
+        in.v[i][q] = id < FftRegsIn<N, NT>::B ? bin(id + q * FftRegsIn<N, NT>::B) : make_float2(0.f, 0.f);
+    }
+    fft_tpl_regs_pass0<N, true, NT>(buf, in);
+    using O = FftRegsOut<N, NT>;
+    O o;
+    fft_tpl_passes_to_regs<N, true, NT, 1, false>(buf, twl, o);
+#pragma unroll
+    for (int i = 0; i < O::MAXB; ++i) {
+      const int id = (int)threadIdx.x + i * NT;
+#pragma unroll
+      for (int q = 0; q < O::R; ++q) {
+        const int t = id + q * O::B;
+        if (id < O::B && t < nt) dst[t] = cscale(o.v[i][q], inv);
+      }
+    }
+  } else {
+    for (int k = threadIdx.x; k < ntp; k += NT) buf[px<N>(k)] = bin(k);
+    __syncthreads();
+    row_inverse<N, NT>(buf, ntp, twl);
+    for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(buf[px<N>(t)], inv);
+  }
   __syncthreads();
 }
 
@@ -747,6 +833,55 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd_fin(RowsArgs A) {
 //
 // LDS: twiddles [ntp], data row spectrum bufD and model spectrum bufM
 // (padded lengths).
+// One data bin of the adjoint scatter: its taps and the two values it adds
+// (k0 = kNoTap when j is past jmax or outside the cone).  The tap adds
+// wgt * e1 at k and wgt * e2 at ntp - k of the model spectrum:
+//   rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l)
+//   row 0:     Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
+struct ScatterBin {
+  int k0;
+  float4 trig;
+  float2 e1, e2;
+};
+
+template <int RC>
+__device__ __forceinline__ ScatterBin scatter_bin(const RowsArgs& A, const GatherDev& G, const PanelDev& PD,
+                                                  bool plain, const float2* bufD, int r, int pass, double a2, int R,
+                                                  int j, int jmax) {
+  ScatterBin b;
+  b.k0 = kNoTap;
+  b.trig = make_float4(0.f, 0.f, 1.f, 0.f);
+  b.e1 = b.e2 = make_float2(0.f, 0.f);
+  if (j > jmax) return b;
+  const Taps T = taps_of<RC>(j, a2, R);
+  if (T.k0 == kNoTap) return b;
+  b.k0 = T.k0;
+  b.trig = T.trig;
+  // spectrum values of bin j, ramped and scaled
+  const float4 dq = reinterpret_cast<const float4*>(bufD)[j];
+  float2 du = make_float2(dq.x, dq.y);
+  float2 dl = make_float2(dq.z, -dq.w);
+  if (plain) {
+    du = cscale(du, PD.scale);
+    dl = cscale(dl, PD.scale);
+  } else {
+    const float2 c = bin_factor(G, PD, A.tw, A.wav, j);
+    du = cmulconj(du, c);
+    dl = cmulconj(dl, c);
+  }
+  if (r != 0) {
+    b.e1 = du;
+    b.e2 = cconj(dl);
+  } else if (pass == 0) {
+    b.e1 = du;
+    b.e2 = cconj(du);
+  } else {
+    b.e1 = make_float2(-dl.y, dl.x);
+    b.e2 = make_float2(dl.y, dl.x);
+  }
+  return b;
+}
+
 template <int N, int RC, int NT>
 __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
                                               float2* lds, const float* ctab, const float* stab) {
@@ -754,9 +889,8 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
   const int R = RC > 0 ? RC : A.R;
   const int r = w.a, chunk = w.b;
   const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows, P = G.npanel;
-  const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
+  const int jlo = G.jlo, jhi = G.jhi;
   const int hmax = ntp / 2 - 1;
-  const int nseg = (nband + 63) >> 6;
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int p0 = (int)((long long)chunk * P / G.nchunk);
   const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
@@ -789,65 +923,55 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
     for (int pass = 0; pass < npass; ++pass) {
       const int l = (r == 0) ? (pass == 0 ? 0 : nrows) : r;
       const double a2 = PD.c2 * (double)l * (double)l;
+      // segments start at the cone edge (bins below it have no taps)
+      const int jb = max(jlo, cone_first_bin(a2));
+      const int nseg = jb <= jhi ? (jhi - jb + 64) >> 6 : 0;
       for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll 1
         for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
-          const int j = jlo + sg * 64 + lane;
-          if (j <= jhi) {
-            const Taps T = taps_of<RC>(j, a2, R);
-            if (T.k0 != kNoTap) {
-              // spectrum values of bin j, ramped and scaled; the tap adds
-              // wgt * e1 at k and wgt * e2 at ntp - k of the model spectrum:
-              //   rows >= 1: Q[k] = M(+l), Q[ntp-k] = conj M(-l)
-              //   row 0:     Q[k] = M(0) + i M(N), Q[ntp-k] = conj M(0) + i conj M(N)
-              const float4 dq = reinterpret_cast<const float4*>(bufD)[j];
-              float2 du = make_float2(dq.x, dq.y);
-              float2 dl = make_float2(dq.z, -dq.w);
-              if (plain) {
-                du = cscale(du, PD.scale);
-                dl = cscale(dl, PD.scale);
-              } else {
-                const float2 c = bin_factor(G, PD, A.tw, A.wav, j);
-                du = cmulconj(du, c);
-                dl = cmulconj(dl, c);
-              }
-              float2 e1, e2;
-              if (r != 0) {
-                e1 = du;
-                e2 = cconj(dl);
-              } else if (pass == 0) {
-                e1 = du;
-                e2 = cconj(du);
-              } else {
-                e1 = make_float2(-dl.y, dl.x);
-                e2 = make_float2(dl.y, dl.x);
-              }
+          const ScatterBin sb = scatter_bin<RC>(A, G, PD, plain, bufD, r, pass, a2, R, jb + sg * 64 + lane, jhi);
+          if (sb.k0 != kNoTap) {
 #pragma unroll
-              for (int t = -R + 1; t <= R; ++t) {
-                const int k = T.k0 + t;
-                if (k >= 1 && k <= hmax) {
-                  const float wt = RC > 0 ? tap_weight(T.trig, t, cr[(t + R - 1) % (2 * RT)], sr[(t + R - 1) % (2 * RT)])
-                                          : tap_weight(T.trig, t, ctab[t + R - 1], stab[t + R - 1]);
-                  float4* q = reinterpret_cast<float4*>(bufM) + k;
-                  float4 v = *q;
-                  v.x = fmaf(wt, e1.x, v.x);
-                  v.y = fmaf(wt, e1.y, v.y);
-                  v.z = fmaf(wt, e2.x, v.z);
-                  v.w = fmaf(wt, e2.y, v.w);
-                  *q = v;
-                }
-                __builtin_amdgcn_wave_barrier();
+            for (int t = -R + 1; t <= R; ++t) {
+              const int k = sb.k0 + t;
+              if (k >= 1 && k <= hmax) {
+                const float wt = RC > 0 ? tap_weight(sb.trig, t, cr[(t + R - 1) % (2 * RT)], sr[(t + R - 1) % (2 * RT)])
+                                        : tap_weight(sb.trig, t, ctab[t + R - 1], stab[t + R - 1]);
+                float4* q = reinterpret_cast<float4*>(bufM) + k;
+                float4 v = *q;
+                v.x = fmaf(wt, sb.e1.x, v.x);
+                v.y = fmaf(wt, sb.e1.y, v.y);
+                v.z = fmaf(wt, sb.e2.x, v.z);
+                v.w = fmaf(wt, sb.e2.y, v.w);
+                *q = v;
               }
+              __builtin_amdgcn_wave_barrier();
             }
           }
         }
         __syncthreads();
       }
     }
-    row_inverse_from_pairs<N, NT>(bufM, ntp, twl);
     const float inv_n = 1.0f / (float)ntp;
     float2* __restrict__ dst = A.X + G.X_off + ((long long)p * nrows + r) * nt;
-    for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(bufM[px<N>(t)], inv_n);
+    if constexpr (N > 0) {
+      // the last pass's outputs go from registers to global memory
+      using O = FftRegsOut<N, NT>;
+      O o;
+      fft_tpl_from_pairs_to_regs<N, true, NT>(bufM, twl, o);
+#pragma unroll
+      for (int i = 0; i < O::MAXB; ++i) {
+        const int id = (int)threadIdx.x + i * NT;
+#pragma unroll
+        for (int rr = 0; rr < O::R; ++rr) {
+          const int t = id + rr * O::B;
+          if (id < O::B && t < nt) dst[t] = cscale(o.v[i][rr], inv_n);
+        }
+      }
+    } else {
+      row_inverse_from_pairs<N, NT>(bufM, ntp, twl);
+      for (int t = threadIdx.x; t < nt; t += NT) dst[t] = cscale(bufM[px<N>(t)], inv_n);
+    }
     __syncthreads();
   }
 }
