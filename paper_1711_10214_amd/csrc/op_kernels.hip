@@ -199,6 +199,17 @@ __device__ __forceinline__ void xfft_tile(float2* buf, int n, int nb, int bstrid
   }
 }
 
+// Division by a workgroup-uniform d >= 1 through a precomputed reciprocal:
+// m = floor((2^32 - 1) / d) + 1 gives floor(n / d) = mulhi(n, m) whenever
+// n d < 2^32 (the tile loops below stay far inside that: the LDS limit keeps
+// tile width times nxp under 2^16).
+struct UDiv {
+  unsigned m;
+  int d;
+  __device__ __forceinline__ explicit UDiv(int dd) : m(dd > 1 ? 0xffffffffu / (unsigned)dd + 1u : 0u), d(dd) {}
+  __device__ __forceinline__ int div(int n) const { return d == 1 ? n : (int)__umulhi((unsigned)n, m); }
+};
+
 // Work-item order for a one-item-per-workgroup launch of n items on the 8
 // XCDs.  Workgroup b runs on XCD b mod 8; this gives XCD x the consecutive
 // items [x q + min(x, r), ...) (q = n div 8, r = n mod 8), so neighbouring
@@ -255,8 +266,9 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     const bool even = (nt & 1) == 0;
 
+    const UDiv dh(half);
     for (int idx = threadIdx.x; idx < nx * half; idx += kThreads) {
-      const int x = idx / half;
+      const int x = dh.div(idx);
       const int i = idx - x * half;
       const int t = t0 + 2 * i;
       const long long o = (long long)x * nt + t;
@@ -303,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       buf[i * bs + px<NX>(x)] = make_float2(a, b);
     }
     for (int idx = threadIdx.x; idx < (nxp - nx) * half; idx += kThreads) {
-      const int xx = idx / half;
+      const int xx = dh.div(idx);
       const int i = idx - xx * half;
       buf[i * bs + px<NX>(nx + xx)] = make_float2(0.f, 0.f);
     }
@@ -335,24 +347,34 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     }
     xfft_tile<NX, false>(buf, nxp, half, bs, twl);
 
+    // column pair i holds the packed spectra of columns t0 + 2i (real part)
+    // and t0 + 2i + 1 (imaginary part); both outputs of a row are written
+    // together (one 16-byte store when nt is even)
     float2* __restrict__ dst = A.dst + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
-    for (int idx = threadIdx.x; idx < nrows * T; idx += kThreads) {
-      const int r = idx / T;
-      const int c = idx - r * T;
-      const int t = t0 + c;
+    for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
+      const int r = dh.div(idx);
+      const int i = idx - r * half;
+      const int t = t0 + 2 * i;
       if (t >= nt) continue;
-      const float2* Z = buf + (c >> 1) * bs;
-      float2 out;
+      const float2* Z = buf + i * bs;
+      float2 o0, o1;
       if (r == 0) {
         const float2 z0 = Z[0], zn = Z[px<NX>(nrows)];
-        out = (c & 1) ? make_float2(z0.y, zn.y) : make_float2(z0.x, zn.x);
+        o0 = make_float2(z0.x, zn.x);
+        o1 = make_float2(z0.y, zn.y);
       } else {
         const float2 a = Z[px<NX>(r)];
         const float2 b = cconj(Z[px<NX>(nxp - r)]);
-        out = (c & 1) ? make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x))
-                      : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
+        o0 = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
+        o1 = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
       }
-      dst[(long long)r * nt + t] = out;
+      float2* d = dst + (long long)r * nt + t;
+      if (even) {
+        *reinterpret_cast<float4*>(d) = make_float4(o0.x, o0.y, o1.x, o1.y);
+      } else {
+        d[0] = o0;
+        if (t + 1 < nt) d[1] = o1;
+      }
     }
     __syncthreads();
   }
@@ -415,13 +437,22 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     }
     stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
 
+    const UDiv dh(half);
+    const bool even = (nt & 1) == 0;
     for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
-      const int l = idx / half;
+      const int l = dh.div(idx);
       const int i = idx - l * half;
       const int t = t0 + 2 * i;
       float2 h1 = make_float2(0.f, 0.f), h2 = make_float2(0.f, 0.f);
-      if (t < nt) h1 = src[(long long)l * nt + t];
-      if (t + 1 < nt) h2 = src[(long long)l * nt + t + 1];
+      if (even && t < nt) {
+        // nt even: (t, t+1) is an aligned pair inside the row
+        const float4 h = *reinterpret_cast<const float4*>(src + (long long)l * nt + t);
+        h1 = make_float2(h.x, h.y);
+        h2 = make_float2(h.z, h.w);
+      } else {
+        if (t < nt) h1 = src[(long long)l * nt + t];
+        if (t + 1 < nt) h2 = src[(long long)l * nt + t + 1];
+      }
       float2* Z = buf + i * bs;
       if (l == 0) {
         Z[0] = make_float2(h1.x, h2.x);
@@ -438,9 +469,8 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     double ss = 0.0;
-    const bool even = (nt & 1) == 0;
     for (int idx = threadIdx.x; idx < nx * half; idx += kThreads) {
-      const int x = idx / half;
+      const int x = dh.div(idx);
       const int i = idx - x * half;
       const int t = t0 + 2 * i;
       if (t >= nt) continue;
