@@ -37,16 +37,16 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # writes x 1.0); valid only for the kernel sources with this digest.
 _MIB = 1024.0 * 1024.0
 MEASURED_TRAFFIC = {
-    "digest": "c37eb4423b2a650f",
+    "digest": "0ed1251ddda72a04",
     "workload": "crg-1024x256-nv32",
     "bytes": {
-        "k_xfft_fwd(model)": (32.20 + 64.00) * _MIB,
-        "k_xfft_fwd(data)": (3.10 + 2.95) * _MIB,
-        "k_rows_fwd": (64.53 + 12.81) * _MIB,
-        "k_rows_fwd_fin": (13.14 + 2.00) * _MIB,
-        "k_xfft_inv(data)": (3.12 + 1.05) * _MIB,
-        "k_rows_adj": (8.51 + 64.00) * _MIB,
-        "k_xfft_inv(model)": (64.18 + 32.02) * _MIB,
+        "k_xfft_fwd(model)": (32.19 + 64.00) * _MIB,
+        "k_xfft_fwd(data)": (1.13 + 2.00) * _MIB,
+        "k_rows_fwd": (64.35 + 12.81) * _MIB,
+        "k_rows_fwd_fin": (13.03 + 2.00) * _MIB,
+        "k_xfft_inv(data)": (2.13 + 1.00) * _MIB,
+        "k_rows_adj": (8.39 + 64.00) * _MIB,
+        "k_xfft_inv(model)": (64.19 + 32.03) * _MIB,
     },
 }
 _KERNEL_SOURCES = ["ashrt_internal.h", "block_reduce.h", "fft_lds.h", "fft_tpl.h", "kernels.h", "op_kernels.hip"]
