@@ -152,6 +152,32 @@ def test_production_solve_matches_stored_oracle(A):
     np.testing.assert_allclose(rep["eps_r"], ref["eps_r"], rtol=1e-3)
 
 
+def test_aashrt_production_solve_matches_stored_oracle(A):
+    """Full 10 x 20 solve of the decimated diffraction gather (1024 x 256,
+    24 velocities x 16 asymptote shifts = 384 panels, half the traces
+    missing, p = 2, q = 1) against the FP64 oracle's per-iteration misfits,
+    model clips and separated-signal SNR stored by
+    tests/golden/make_oracle_values.py (which calls only the oracle)."""
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_separation.json")))
+    ref = gold["aashrt-1024x256-nv24x16"]
+    w = workload("aashrt-1024x256-nv24x16")
+    gth = make_gather(w)
+    assert (ref["p"], ref["q"], ref["n_outer"], ref["n_inner"]) == (w.p, w.q, w.n_outer, w.n_inner)
+    plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax)
+    d = torch.tensor(gth.d_blend, dtype=torch.float32, device="cuda")
+    mask = torch.tensor(gth.mask, device="cuda")
+    print("[gpu] invert parity aashrt-1024x256-nv24x16 10x20 vs stored oracle", flush=True)
+    _, drec, rep = plan.robust_invert(d, A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner), mask=mask)
+    q_r = oracle.q_db(gth.d_clean, drec.cpu().numpy())
+    print(f"  Q_R gpu {q_r:.6f} dB oracle {ref['q_r_db']:.6f} dB", flush=True)
+    print(f"  misfit rel err {np.max(np.abs(np.array(rep['misfit']) / np.array(ref['misfit']) - 1)):.2e}", flush=True)
+    assert q_r >= ref["q_r_db"] - 0.05
+    assert abs(q_r - ref["q_r_db"]) < 0.01
+    np.testing.assert_allclose(rep["misfit"], ref["misfit"], rtol=1e-4)
+    np.testing.assert_allclose(rep["eps_m"][1:], ref["eps_m"], rtol=1e-3)
+
+
 @pytest.mark.parametrize("pq_inner", [(1, 2, 7), (1, 1, 6)])
 def test_cg_graph_replays_match_eager_launches(A, pq_inner):
     """CG iterations replayed from the captured hipGraph give bit-identical
