@@ -78,14 +78,21 @@ def _geometry_numbers(plan, nx, nt, P, R):
     f4, c8 = 4, 8
     model_b = P * nx * nt * f4
     data_b = nx * nt * f4
-    X_b = P * nrows * nt * c8
+    # x-spectrum rows that can reach the band (c2 r^2 <= jhi^2, row 0 always):
+    # the only ones written and read
+    bin_ = ntp * plan.dt / (nxp * plan.dx)
+    live_rows = 0
+    for v in plan.vel:
+        c2 = (v * bin_) ** 2
+        rl = nrows if c2 <= 0 else min(nrows, 1 + sum(1 for r in range(1, nrows) if c2 * r * r <= jhi * jhi * (1 + 1e-9)))
+        live_rows += rl
+    X_b = live_rows * nt * c8
     H_b = nrows * nt * c8
     Dp_b = nchunk * nrows * 2 * nband * c8
     fft_t = 5.0 * ntp * math.log2(ntp)          # one complex time FFT
     fft_x = 5.0 * nxp * math.log2(nxp)          # one complex x FFT (two real columns)
     # in-cone map outputs: for each panel, row and band bin with j >= a (up and lo rows)
     vel = plan.vel
-    bin_ = ntp * plan.dt / (nxp * plan.dx)
     j = np.arange(jlo, jhi + 1, dtype=np.float64)
     l = np.arange(nrows, dtype=np.float64)
     cone = 0
@@ -97,10 +104,10 @@ def _geometry_numbers(plan, nx, nt, P, R):
     return {
         "k_xfft_fwd(model)": (model_b + X_b, P * math.ceil(nt / 2) * fft_x),
         "k_xfft_fwd(data)": (data_b + H_b, math.ceil(nt / 2) * fft_x),
-        "k_rows_fwd": (X_b + Dp_b, P * nrows * fft_t + map_flops),
+        "k_rows_fwd": (X_b + Dp_b, live_rows * fft_t + map_flops),
         "k_rows_fwd_fin": (Dp_b + H_b, nrows * fft_t),
         "k_xfft_inv(data)": (H_b + data_b, math.ceil(nt / 2) * fft_x),
-        "k_rows_adj": (nchunk * H_b + X_b, (nchunk + P) * nrows * fft_t + map_flops),
+        "k_rows_adj": (nchunk * H_b + X_b, (nchunk * nrows + live_rows) * fft_t + map_flops),
         "k_xfft_inv(model)": (X_b + model_b, P * math.ceil(nt / 2) * fft_x),
     }
 

@@ -297,6 +297,17 @@ static int build_gather(const ashrt_desc* d, const ashrt_tuning* tn, GatherHost*
     gh->panels[p].c2 = c * c;
     gh->panels[p].scale = d->panel_scale ? (float)d->panel_scale[p] : 1.0f;
     gh->panels[p].n0 = d->tau0_samples ? d->tau0_samples[p] : 0;
+    // live rows: row 0 (its l = 0 half covers the band) and every row whose
+    // cone edge c2 r^2 is at most jhi^2 (with a relative margin, so that a
+    // row declared dead has no tap whichever way its a^2 is rounded)
+    int rl = gh->nrows;
+    if (z.jhi >= z.jlo && c * c > 0.0) {
+      const double lim = (double)z.jhi * (double)z.jhi * (1.0 + 1e-9);
+      rl = 1;
+      while (rl < gh->nrows && c * c * (double)rl * (double)rl <= lim) ++rl;
+    }
+    gh->panels[p].rlive = rl;
+    gh->panels[p].pad_ = 0;
   }
   gh->xpos.clear();
   if (d->x_pos) {
@@ -863,6 +874,7 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
     xa.mul = mul_m;
     xa.dst = c.X();
     xa.tw = P.d_tw;
+    xa.panels = P.d_pan;
     e = timed(ASHRT_K_XFFT_MODEL, c.s, [&] { return launch_xfft_fwd(sg.key, xa, sg.lds, c.s); });
     if (e != hipSuccess) return e;
   }
@@ -891,6 +903,7 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
     ia.raw_out = raw_out;
     ia.tmask = tmask;
     ia.tw = P.d_tw;
+    ia.panels = P.d_pan;
     ia.part = part;
     e = timed(ASHRT_K_XINV_DATA, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
     if (e != hipSuccess) return e;
@@ -924,6 +937,7 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     xa.tmask = tmask;
     xa.dst = c.H();
     xa.tw = P.d_tw;
+    xa.panels = P.d_pan;
     if (cg) {
       xa.s_inout = cg->s_inout;
       xa.qv = cg->qv;
@@ -950,6 +964,7 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     ia.out = m_out;
     ia.wmul = wmul;
     ia.tw = P.d_tw;
+    ia.panels = P.d_pan;
     ia.part = part;
     e = timed(ASHRT_K_XINV_MODEL, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
     if (e != hipSuccess) return e;

@@ -59,6 +59,9 @@ struct PanelDev {
   double c2;     // (v * ntp * dt / (nxp * dx))^2, so a^2 = c2 * l'^2
   float scale;   // s_p
   int n0;        // asymptote shift in samples
+  int rlive;     // rows r < rlive can reach the band (c2 r^2 <= jhi^2); rows at and above it have
+                 // no in-cone bin, so their x-spectra are neither written nor read
+  int pad_;
 };
 
 // Work item: gather g plus up to three stage-specific indices.

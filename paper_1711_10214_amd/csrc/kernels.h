@@ -16,6 +16,7 @@ struct XfwdArgs {
   const uint8_t* tmask;   // optional trace mask (data only)
   float2* dst;
   const float2* tw;
+  const PanelDev* panels; // live-row counts of the model panels
   // CG step (data input only): before the transform, s -= alpha q with
   // alpha = gamma[par] / delta, delta summed from the forward's partials
   // (every workgroup sums them in the same order; the first one stores it).
@@ -39,6 +40,7 @@ struct XinvArgs {
   float* raw_out;         // data: y before the epilogue when set
   const uint8_t* tmask;   // data: out *= mask
   const float2* tw;
+  const PanelDev* panels; // live-row counts of the model panels
   double* part;           // per work item: sum of out^2 (or NULL)
   int item_base;          // index of items[0] in the plan's full list
 };

@@ -351,7 +351,9 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     // and t0 + 2i + 1 (imaginary part); both outputs of a row are written
     // together (one 16-byte store when nt is even)
     float2* __restrict__ dst = A.dst + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
-    for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
+    // model panels: rows at or above the panel's live-row count are never read
+    const int nrw = A.is_model ? min(nrows, A.panels[G.panel_off + p].rlive) : nrows;
+    for (int idx = threadIdx.x; idx < nrw * half; idx += kThreads) {
       const int r = dh.div(idx);
       const int i = idx - r * half;
       const int t = t0 + 2 * i;
@@ -439,12 +441,16 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
 
     const UDiv dh(half);
     const bool even = (nt & 1) == 0;
+    // model panels: rows at or above the panel's live-row count are zero (not stored)
+    const int nrw = A.is_model ? min(nrows, A.panels[G.panel_off + p].rlive) : nrows;
     for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
       const int l = dh.div(idx);
       const int i = idx - l * half;
       const int t = t0 + 2 * i;
       float2 h1 = make_float2(0.f, 0.f), h2 = make_float2(0.f, 0.f);
-      if (even && t < nt) {
+      if (l >= nrw) {
+        // zero row
+      } else if (even && t < nt) {
         // nt even: (t, t+1) is an aligned pair inside the row
         const float4 h = *reinterpret_cast<const float4*>(src + (long long)l * nt + t);
         h1 = make_float2(h.x, h.y);
@@ -645,8 +651,10 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
   const int r = w.a, chunk = w.b;
   const int nt = G.nt, ntp = N > 0 ? N : G.ntp, nrows = G.nrows, P = G.npanel;
   const int jlo = G.jlo, jhi = G.jhi, nband = jhi - jlo + 1;
-  const int p0 = (int)((long long)chunk * P / G.nchunk);
-  const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
+  // chunk c takes panels c, c + nchunk, ... (interleaved, so chunks of one
+  // row see a similar mix of slow and fast panels); panels whose live rows
+  // end at or below r are skipped
+  const int S = G.nchunk;
   const int hmax = ntp / 2 - 1;
   const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
@@ -662,32 +670,38 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 
   const float2* __restrict__ xrow = A.X + G.X_off + (long long)r * nt;  // panel p's row at + p nrows nt
   const long long pstride = (long long)nrows * nt;
-  // compile-time lengths: the next panel's row and panel constants are
-  // loaded while this panel is transformed and mapped
-  // (the first FFT pass takes them straight from registers)
+  // compile-time lengths: the next panel's row is loaded while this panel
+  // is transformed and mapped (the first FFT pass takes it straight from
+  // registers), and the panel constants one panel further ahead, so that the
+  // liveness of the row to load is known without a wait
   FftRegsIn<(N > 0 ? N : kRowMaxN), NT> pf;
-  PanelDev pdn;
+  PanelDev pdc, pdn;  // constants of the panel whose row is in pf, and of the one after
   if constexpr (N > 0) {
-    if (p0 < p1) {
-      pf.load(xrow + p0 * pstride, nt);
-      pdn = A.panels[G.panel_off + p0];
+    if (chunk < P) {
+      pdc = A.panels[G.panel_off + chunk];
+      if (r < pdc.rlive) pf.load(xrow + chunk * pstride, nt);
+      if (chunk + S < P) pdn = A.panels[G.panel_off + chunk + S];
     }
   }
 
-  for (int p = p0; p < p1; ++p) {
+  for (int p = chunk; p < P; p += S) {
     PanelDev PD;
     if constexpr (N > 0) {
-      PD = pdn;
-      fft_tpl_regs_pass0<N, false, NT>(buf, pf);
-      if (p + 1 < p1) {
-        pf.load(xrow + (p + 1) * pstride, nt);
-        pdn = A.panels[G.panel_off + p + 1];
+      PD = pdc;
+      const bool live = r < PD.rlive;
+      if (live) fft_tpl_regs_pass0<N, false, NT>(buf, pf);
+      if (p + S < P) {
+        pdc = pdn;
+        if (r < pdc.rlive) pf.load(xrow + (p + S) * pstride, nt);
+        if (p + 2 * S < P) pdn = A.panels[G.panel_off + p + 2 * S];
       }
+      if (!live) continue;
       fft_tpl_rest_to_pairs<N, false, NT>(buf, twl);
       if (r == 0) row0_separate<N, NT>(buf, ntp);
     } else {
-      row_spectrum<N, NT>(buf, xrow + p * pstride, r, nt, ntp, twl);
       PD = A.panels[G.panel_off + p];
+      if (r >= PD.rlive) continue;
+      row_spectrum<N, NT>(buf, xrow + p * pstride, r, nt, ntp, twl);
     }
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
     // rows >= 1 map only bins inside the cone (the rest add zero); row 0's
@@ -922,8 +936,6 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
   const int jlo = G.jlo, jhi = G.jhi;
   const int hmax = ntp / 2 - 1;
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-  const int p0 = (int)((long long)chunk * P / G.nchunk);
-  const int p1 = (int)((long long)(chunk + 1) * P / G.nchunk);
   const int plen = N > 0 ? fft_padlen(N) : ntp;
   float2* twl = lds;
   float2* bufD = lds + fft_tw_slots(N, ntp);
@@ -945,8 +957,11 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
   }
 
   const int npass = (r == 0) ? 2 : 1;
-  for (int p = p0; p < p1; ++p) {
+  // panels chunk, chunk + nchunk, ... as in the forward; rows at or above a
+  // panel's live-row count get no taps and their x-spectra are not written
+  for (int p = chunk; p < P; p += G.nchunk) {
     const PanelDev PD = A.panels[G.panel_off + p];
+    if (r >= PD.rlive) continue;
     const bool plain = (PD.n0 == 0) && (G.wav_off < 0);
     for (int k = threadIdx.x; k < ntp / 2; k += NT) reinterpret_cast<float4*>(bufM)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
