@@ -857,10 +857,22 @@ RowsArgs rows_args(const Ctx& c, const WorkItem* items, int n) {
   return a;
 }
 
+// The previous CG iteration's vector update, fused into the next forward's
+// model transform (which then reads pdir after the update).
+struct CgUpd {
+  float* u = nullptr;
+  float* pdir = nullptr;
+  const float* g = nullptr;
+  const double* part_gamma = nullptr;
+  double* sc = nullptr;
+  int par = 0;  // gamma slot of the previous iteration
+};
+
 // d_out = epilogue(L (mul_m * m)); the epilogue is: raw_out = y; y = sub - y;
 // y *= mask; y *= wmul.
 hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* d_out, const float* sub,
-                       const float* wmul, float* raw_out, const uint8_t* tmask, double* part = nullptr) {
+                       const float* wmul, float* raw_out, const uint8_t* tmask, double* part = nullptr,
+                       const CgUpd* upd = nullptr) {
   const PlanImpl& P = *c.P;
   hipError_t e = hipSuccess;
   for (const auto& sg : P.s_xm) {
@@ -875,6 +887,15 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
     xa.dst = c.X();
     xa.tw = P.d_tw;
     xa.panels = P.d_pan;
+    if (upd) {
+      xa.cg_upd = 1;
+      xa.cg_par = upd->par;
+      xa.cg_p = upd->pdir;
+      xa.cg_u = upd->u;
+      xa.cg_g = upd->g;
+      xa.part_gamma = upd->part_gamma;
+      xa.sc = upd->sc;
+    }
     e = timed(ASHRT_K_XFFT_MODEL, c.s, [&] { return launch_xfft_fwd(sg.key, xa, sg.lds, c.s); });
     if (e != hipSuccess) return e;
   }
@@ -1130,10 +1151,20 @@ struct Solver {
 
 // One CG iteration on A = W_r S L W_m^-1, all on S.c.s:
 //   q = A pdir (per-tile partials of |q|^2); alpha = gamma / |q|^2;
-//   s -= alpha q; g = A' s (partials of |g|^2); beta; u += alpha pdir;
-//   pdir = g + beta pdir.  par selects the gamma slot pair.
-hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par) {
-  hipError_t e = run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel);
+//   s -= alpha q; g = A' s (partials of |g|^2).  Its vector update (beta,
+//   u += alpha pdir, pdir = g + beta pdir) runs inside the next iteration's
+//   model transform (fused: this iteration applies the previous one's), or
+//   as k_cg after the last iteration.  par selects the gamma slot pair.
+hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fused) {
+  CgUpd up;
+  up.u = S.u;
+  up.pdir = S.pdir;
+  up.g = S.g;
+  up.part_gamma = S.pgam;
+  up.sc = S.sc;
+  up.par = par ^ 1;
+  hipError_t e =
+      run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel, fused ? &up : nullptr);
   if (e != hipSuccess) return e;
   CgStep st;
   st.s_inout = S.s;
@@ -1141,15 +1172,14 @@ hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par) {
   st.part_delta = S.pdel;
   st.sc = S.sc;
   st.par = par;
-  e = run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st);
-  if (e != hipSuccess) return e;
-  return S.cg(0, par);
+  return run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st);
 }
 
 constexpr size_t kMaxCgGraphs = 8;
 
-// The executable graph of two CG iterations (parities 0 and 1) for these
-// buffers: captured on a private stream the first time, then cached.
+// The executable graph of two fused CG iterations (parities 1 then 0, each
+// applying the other's update) for these buffers: captured on a private
+// stream the first time, then cached.
 int cg_graph_get(const PlanImpl& P, const Solver& S, const uint8_t* mask, int q, hipGraphExec_t* out) {
   std::lock_guard<std::mutex> lk(P.graph_mu);
   const float* mkey = S.u;
@@ -1170,8 +1200,8 @@ int cg_graph_get(const PlanImpl& P, const Solver& S, const uint8_t* mask, int q,
   S2.c.s = cs;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    e = cg_iteration(S2, mask, 0);
-    if (e == hipSuccess) e = cg_iteration(S2, mask, 1);
+    e = cg_iteration(S2, mask, 1, true);
+    if (e == hipSuccess) e = cg_iteration(S2, mask, 0, true);
     hipGraph_t graph = nullptr;
     const hipError_t e_end = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = e_end;
@@ -1213,7 +1243,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
   const hipStream_t s = c.s;
   const bool q1 = prm->q == 1, p1 = prm->p == 1;
   hipGraphExec_t cg_exec = nullptr;
-  if (prm->cg_graph && prm->n_inner >= 2 && g_prof.mask == 0) {
+  if (prm->cg_graph && prm->n_inner >= 3 && g_prof.mask == 0) {
     st = cg_graph_get(P, S, mask, prm->q, &cg_exec);
     if (st) return st;
   }
@@ -1275,10 +1305,16 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
     }
     E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam));
     E_TRY(S.cg(1, 0));
-    int i = 0;
-    if (cg_exec)
-      for (; i + 1 < prm->n_inner; i += 2) E_TRY(hipGraphLaunch(cg_exec, s));
-    for (; i < prm->n_inner; ++i) E_TRY(cg_iteration(S, mask, i & 1));
+    if (prm->n_inner > 0) {
+      // iteration 0 starts from pdir = g; iterations 1.. apply their
+      // predecessor's update in their model transform; k_cg applies the last
+      E_TRY(cg_iteration(S, mask, 0, false));
+      int i = 1;
+      if (cg_exec)
+        for (; i + 1 < prm->n_inner; i += 2) E_TRY(hipGraphLaunch(cg_exec, s));
+      for (; i < prm->n_inner; ++i) E_TRY(cg_iteration(S, mask, i & 1, true));
+      E_TRY(S.cg(0, (prm->n_inner - 1) & 1));
+    }
     E_TRY(S.scalar(ST_REPORT_INNER, k));
     if (q1) {
       EwArgs a = S.ew(EW_MUL, true);

@@ -138,10 +138,12 @@ __device__ __forceinline__ void pair_put(float2* buf, int o, float2 v) {
 // One pass of a batch of nb transforms (nb * N <= NBN) at buf + b*bstride,
 // run by a workgroup of NT threads.  IO = 1: this pass reads its input from
 // the pair layout; IO = 2: it writes its output in the pair layout (bins 0
-// and N/2 dropped); IO = 0: padded layout both ways.  Reads complete before
-// the barrier and writes follow it, so the layouts may share memory.
+// and N/2 dropped); IO = 3: inputs at index >= nvalid are taken as zero (and
+// never read); IO = 4: outputs at index >= nvalid are dropped; IO = 0:
+// padded layout both ways.  Reads complete before the barrier and writes
+// follow it, so the layouts may share memory.
 template <int N, int PASS, int NBN, bool INV, int NT = kThreads, int IO = 0>
-__device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const float2* twp) {
+__device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const float2* twp, int nvalid = N) {
   using P = FftPlan<N>;
   constexpr int R = P::radix(PASS);
   constexpr int Ns = P::ns(PASS);
@@ -164,6 +166,7 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (IO == 1) v[i][r] = pair_get<N>(src, j + r * B);
+        else if constexpr (IO == 3) v[i][r] = (j + r * B < nvalid) ? src[fft_pad(j + r * B)] : make_float2(0.f, 0.f);
         else v[i][r] = src[fft_pad(j + r * B)];
       }
       if constexpr (Ns > 1) {
@@ -188,8 +191,13 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
     if (dst[i] >= 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if constexpr (IO == 2) pair_put<N>(buf + dst[i], bq[i] + r * Ns, v[i][r]);
-        else buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+        if constexpr (IO == 2) {
+          pair_put<N>(buf + dst[i], bq[i] + r * Ns, v[i][r]);
+        } else if constexpr (IO == 4) {
+          if (bq[i] + r * Ns < nvalid) buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+        } else {
+          buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+        }
       }
     }
   }
@@ -198,15 +206,23 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
 
 // PAIRS_IN: the first pass reads the pair layout; PAIRS_OUT: the last pass
 // writes it.
-// Passes PASS .. END-1 (END defaults to all of them).
+// Passes PASS .. END-1 (END defaults to all of them).  MASK_IN: the first
+// pass reads only indices < nvalid (the rest is zero); MASK_OUT: the last
+// pass writes only indices < nvalid.
 template <int N, int PASS, int NBN, bool INV, int NT, bool PAIRS_IN = false, bool PAIRS_OUT = false,
-          int END = FftPlan<N>::npass>
-__device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, const float2* twp) {
+          int END = FftPlan<N>::npass, bool MASK_IN = false, bool MASK_OUT = false>
+__device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, const float2* twp, int nvalid = N) {
   if constexpr (PASS < END) {
-    constexpr int IO = (PAIRS_IN && PASS == 0) ? 1 : ((PAIRS_OUT && PASS == FftPlan<N>::npass - 1) ? 2 : 0);
+    constexpr bool last = PASS == FftPlan<N>::npass - 1;
+    constexpr int IO = (PAIRS_IN && PASS == 0)   ? 1
+                       : (PAIRS_OUT && last)     ? 2
+                       : (MASK_IN && PASS == 0)  ? 3
+                       : (MASK_OUT && last)      ? 4
+                                                 : 0;
     static_assert(!(PAIRS_IN && PAIRS_OUT && FftPlan<N>::npass == 1), "pair input and output need two passes");
-    tpl_pass<N, PASS, NBN, INV, NT, IO>(buf, nb, bstride, twp);
-    tpl_passes<N, PASS + 1, NBN, INV, NT, PAIRS_IN, PAIRS_OUT, END>(buf, nb, bstride, twp);
+    static_assert(!(MASK_IN && MASK_OUT && FftPlan<N>::npass == 1), "masked input and output need two passes");
+    tpl_pass<N, PASS, NBN, INV, NT, IO>(buf, nb, bstride, twp, nvalid);
+    tpl_passes<N, PASS + 1, NBN, INV, NT, PAIRS_IN, PAIRS_OUT, END, MASK_IN, MASK_OUT>(buf, nb, bstride, twp, nvalid);
   }
 }
 
@@ -214,6 +230,14 @@ __device__ __forceinline__ void tpl_passes(float2* buf, int nb, int bstride, con
 template <int N, int NBN, bool INV, int NT = kThreads>
 __device__ __forceinline__ void fft_tpl(float2* buf, int nb, int bstride, const float2* twp) {
   tpl_passes<N, 0, NBN, INV, NT>(buf, nb, bstride, twp);
+}
+
+// Full transform(s) of inputs that are zero at index >= nvalid (MASK_IN:
+// those slots are never read, so they need not be filled) or of which only
+// outputs < nvalid are wanted (MASK_OUT: the others are not written).
+template <int N, int NBN, bool INV, bool MASK_IN, bool MASK_OUT, int NT = kThreads>
+__device__ __forceinline__ void fft_tpl_masked(float2* buf, int nb, int bstride, const float2* twp, int nvalid) {
+  tpl_passes<N, 0, NBN, INV, NT, false, false, FftPlan<N>::npass, MASK_IN, MASK_OUT>(buf, nb, bstride, twp, nvalid);
 }
 
 // One transform of length N whose output is left in the pair layout.

@@ -26,6 +26,18 @@ struct XfwdArgs {
   double* sc;
   int par;
   int item_base;          // index of items[0] in the plan's full list (partials, first-item checks)
+  // Model input with the previous CG iteration's update fused in (cg_upd):
+  // beta = gamma_new / gamma[cg_par] (gamma_new summed from the adjoint's
+  // per-tile partials part_gamma, each workgroup in the same order),
+  // alpha = sc[SC_ALPHA] (both 0 once done); u += alpha pdir,
+  // pdir = g + beta pdir (cg_p, updated in place), and the new pdir is the
+  // transform's input; the gather's first item stores gamma[cg_par ^ 1].
+  int cg_upd;
+  int cg_par;
+  float* cg_p;
+  float* cg_u;
+  const float* cg_g;
+  const double* part_gamma;
 };
 
 struct XinvArgs {

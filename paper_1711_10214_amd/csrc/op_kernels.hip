@@ -184,13 +184,15 @@ __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __rest
 // Batched x-axis FFTs of a tile: nb transforms of length n at stride
 // bstride, run in groups of at most kXfftBatch points per call (bounded
 // registers).  N > 0: compile-time length; N == 0: generic runtime FFT.
+// Compile-time lengths: the forward reads only the nx trace slots (the pad
+// to nxp is zero and never filled), the inverse writes only the nx traces.
 template <int N, bool INV>
-__device__ __forceinline__ void xfft_tile(float2* buf, int n, int nb, int bstride, const float2* twl) {
+__device__ __forceinline__ void xfft_tile(float2* buf, int n, int nb, int bstride, const float2* twl, int nx) {
   if constexpr (N > 0) {
     static_assert(N <= kXfftBatch, "compile-time x-FFT longer than one batch");
     constexpr int per = kXfftBatch / N;
     for (int b0 = 0; b0 < nb; b0 += per)
-      fft_tpl<N, kXfftBatch, INV>(buf + b0 * bstride, min(per, nb - b0), bstride, twl);
+      fft_tpl_masked<N, kXfftBatch, INV, !INV, INV>(buf + b0 * bstride, min(per, nb - b0), bstride, twl, nx);
   } else {
     // generic: n <= 4096 = kXfftGenericBatch, so per >= 1
     const int per = max(1, kXfftGenericBatch / n);
@@ -225,6 +227,7 @@ template <int NX>
 __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float s_alpha;
+  __shared__ float s_ab[2];
   __shared__ double s_red[kThreads / 64];
   for (int it0 = blockIdx.x; it0 < A.nitems; it0 += gridDim.x) {
     const int it = (int)gridDim.x == A.nitems ? xcd_item(it0, A.nitems) : it0;
@@ -252,6 +255,27 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       __syncthreads();
       alpha = s_alpha;
     }
+    float cg_a = 0.f, cg_b = 0.f;
+    if (A.cg_upd) {
+      double part = 0.0;
+      for (int i = G.xm_lo + (int)threadIdx.x; i < G.xm_hi; i += kThreads) part += A.part_gamma[i];
+      const double gnew = block_sum(part, s_red);
+      if (threadIdx.x == 0) {
+        double* sc = A.sc + (long long)w.g * kNScal;
+        const bool done = sc[SC_DONE] != 0.0;
+        const double gold = sc[SC_GAMMA0 + A.cg_par];
+        const double beta = (done || gold == 0.0) ? 0.0 : gnew / gold;
+        s_ab[0] = done ? 0.f : (float)sc[SC_ALPHA];
+        s_ab[1] = (float)beta;
+        if (A.item_base + it == G.xm_lo) {
+          sc[SC_GAMMA0 + (A.cg_par ^ 1)] = gnew;
+          sc[SC_BETA] = beta;
+        }
+      }
+      __syncthreads();
+      cg_a = s_ab[0];
+      cg_b = s_ab[1];
+    }
     const int p = w.a;
     const int nx = G.nx, nt = G.nt, nxp = G.nxp, nrows = G.nrows;
     const int T = A.is_model ? G.tileT : G.tileTd, half = T >> 1;
@@ -273,7 +297,39 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       const int t = t0 + 2 * i;
       const long long o = (long long)x * nt + t;
       float a = 0.f, b = 0.f;
-      if (A.s_inout) {
+      if (A.cg_upd) {
+        // the previous iteration's CG update of this element pair; the new
+        // search direction is the input
+        float* pp = A.cg_p + fbase;
+        float* uu = A.cg_u + fbase;
+        const float* gg = A.cg_g + fbase;
+        if (even && t < nt) {
+          const float2 pv = *reinterpret_cast<const float2*>(pp + o);
+          const float2 gv = *reinterpret_cast<const float2*>(gg + o);
+          const float2 uv = *reinterpret_cast<const float2*>(uu + o);
+          *reinterpret_cast<float2*>(uu + o) = make_float2(fmaf(cg_a, pv.x, uv.x), fmaf(cg_a, pv.y, uv.y));
+          a = fmaf(cg_b, pv.x, gv.x);
+          b = fmaf(cg_b, pv.y, gv.y);
+          *reinterpret_cast<float2*>(pp + o) = make_float2(a, b);
+        } else {
+          if (t < nt) {
+            const float pv = pp[o];
+            uu[o] = fmaf(cg_a, pv, uu[o]);
+            a = fmaf(cg_b, pv, gg[o]);
+            pp[o] = a;
+          }
+          if (t + 1 < nt) {
+            const float pv = pp[o + 1];
+            uu[o + 1] = fmaf(cg_a, pv, uu[o + 1]);
+            b = fmaf(cg_b, pv, gg[o + 1]);
+            pp[o + 1] = b;
+          }
+        }
+        if (mul) {
+          a *= (t < nt) ? mul[o] : 0.f;
+          b *= (t + 1 < nt) ? mul[o + 1] : 0.f;
+        }
+      } else if (A.s_inout) {
         float* sv = A.s_inout + fbase;
         const float* qv = A.qv + fbase;
         if (t < nt) {
@@ -314,10 +370,12 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       }
       buf[i * bs + px<NX>(x)] = make_float2(a, b);
     }
-    for (int idx = threadIdx.x; idx < (nxp - nx) * half; idx += kThreads) {
-      const int xx = dh.div(idx);
-      const int i = idx - xx * half;
-      buf[i * bs + px<NX>(nx + xx)] = make_float2(0.f, 0.f);
+    if constexpr (NX == 0) {  // the generic FFT reads the pad
+      for (int idx = threadIdx.x; idx < (nxp - nx) * half; idx += kThreads) {
+        const int xx = dh.div(idx);
+        const int i = idx - xx * half;
+        buf[i * bs + px<NX>(nx + xx)] = make_float2(0.f, 0.f);
+      }
     }
     __syncthreads();
     if (!A.is_model && G.nudft_off >= 0) {
@@ -345,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
       __syncthreads();
       continue;
     }
-    xfft_tile<NX, false>(buf, nxp, half, bs, twl);
+    xfft_tile<NX, false>(buf, nxp, half, bs, twl, nx);
 
     // column pair i holds the packed spectra of columns t0 + 2i (real part)
     // and t0 + 2i + 1 (imaginary part); both outputs of a row are written
@@ -469,7 +527,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       }
     }
     __syncthreads();
-    xfft_tile<NX, true>(buf, nxp, half, bs, twl);
+    xfft_tile<NX, true>(buf, nxp, half, bs, twl, nx);
 
     const float inv = 1.0f / (float)nxp;
     const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
