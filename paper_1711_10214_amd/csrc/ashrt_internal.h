@@ -13,6 +13,10 @@ namespace ashrt {
 
 constexpr int kThreads = 256;          // threads per workgroup (all kernels but the row passes)
 constexpr int kRowThreads = 256;       // threads per workgroup of the forward/adjoint row passes
+// Compile-time row lengths of 3072 and 4096 need 60-75 KB of LDS per
+// workgroup (two per CU): they run 512 threads (8 waves) so that each SIMD
+// still holds four waves; shorter lengths run kRowThreads.
+constexpr int row_threads(int n) { return n >= 3072 ? 512 : kRowThreads; }
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
 constexpr int kXfftTilePoints = 4096;  // complex points of a model x-FFT tile (T = 2 * this / nxp columns)

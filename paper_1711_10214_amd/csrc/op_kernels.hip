@@ -825,7 +825,7 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 }
 
 template <int N, int RC>
-__global__ __launch_bounds__(kRowThreads) void k_rows_fwd(RowsArgs A) {
+__global__ __launch_bounds__(row_threads(N)) void k_rows_fwd(RowsArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
@@ -833,7 +833,7 @@ __global__ __launch_bounds__(kRowThreads) void k_rows_fwd(RowsArgs A) {
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    rows_fwd_item<N, RC, kRowThreads>(A, w, G, lds, ctab, stab);
+    rows_fwd_item<N, RC, row_threads(N)>(A, w, G, lds, ctab, stab);
   }
 }
 
@@ -1080,7 +1080,7 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
 }
 
 template <int N, int RC>
-__global__ __launch_bounds__(kRowThreads) void k_rows_adj(RowsArgs A) {
+__global__ __launch_bounds__(row_threads(N)) void k_rows_adj(RowsArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
@@ -1088,7 +1088,7 @@ __global__ __launch_bounds__(kRowThreads) void k_rows_adj(RowsArgs A) {
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    rows_adj_item<N, RC, kRowThreads>(A, w, G, lds, ctab, stab);
+    rows_adj_item<N, RC, row_threads(N)>(A, w, G, lds, ctab, stab);
   }
 }
 
@@ -1176,7 +1176,7 @@ hipError_t launch_rows_fwd(int key, const RowsArgs& a, size_t lds, hipStream_t s
   switch (key) {
 #define L_(S)                                                                                  \
   case S:                                                                                      \
-    hipLaunchKernelGGL((k_rows_fwd<S, 4>), dim3(a.nitems), dim3(kRowThreads), lds, s, a); \
+    hipLaunchKernelGGL((k_rows_fwd<S, 4>), dim3(a.nitems), dim3(row_threads(S)), lds, s, a); \
     break;
     ASHRT_ROW_SIZES(L_)
 #undef L_
@@ -1208,7 +1208,7 @@ hipError_t launch_rows_adj(int key, const RowsArgs& a, size_t lds, hipStream_t s
   switch (key) {
 #define L_(S)                                                                                  \
   case S:                                                                                      \
-    hipLaunchKernelGGL((k_rows_adj<S, 4>), dim3(a.nitems), dim3(kRowThreads), lds, s, a); \
+    hipLaunchKernelGGL((k_rows_adj<S, 4>), dim3(a.nitems), dim3(row_threads(S)), lds, s, a); \
     break;
     ASHRT_ROW_SIZES(L_)
 #undef L_

@@ -73,6 +73,21 @@ def test_small_crg_solve_matches_oracle(A, pq):
         np.testing.assert_allclose(rep["eps_m"][1:], rep_r["eps_m"], rtol=1e-4)
 
 
+def test_long_trace_solve_matches_oracle(A):
+    """1536-sample traces (3072-point time FFTs, 512-thread row workgroups)
+    through the fused CG iterations."""
+    w = workload("crg-256x64-nv8", nt=1536, nx=24, vel=(1500.0, 2200.0, 3300.0))
+    gth = make_gather(w)
+    kw = geom_kwargs(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
+    prm = IrlsParams(p=1, q=2, n_outer=2, n_inner=5)
+    print("[gpu] invert parity long traces nt=1536", flush=True)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm)
+    e_d = rel_l2(d_g, d_r)
+    print(f"  d_rec rel-L2 {e_d:.2e}", flush=True)
+    assert e_d <= 1e-4
+    np.testing.assert_allclose(rep["misfit"], rep_r["misfit"], rtol=1e-4)
+
+
 def test_separation_quality_matches_oracle(A):
     w, gth, kw = _cfg1()
     prm = IrlsParams(p=1, q=2, n_outer=w.n_outer, n_inner=w.n_inner)

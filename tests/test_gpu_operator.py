@@ -66,6 +66,10 @@ CASES = {
                                 0.0),
     "half-width-8": (geom_kwargs(160, 40, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0, half_width=8), 0.0),
     "tiny": (geom_kwargs(2, 2, 0.004, 12.5, [2000.0], ntp=8, nxp=4), 0.0),
+    # long traces: the 3072- and 4096-point row kernels (512-thread workgroups)
+    "long-ntp3072": (geom_kwargs(1536, 16, 0.004, 12.5, [1500.0, 2600.0, 3800.0], fmax=110.0), 0.0),
+    "long-ntp4096-ragged-mask": (geom_kwargs(1900, 10, 0.004, 12.5, [1500.0, 2600.0, 3800.0], tau0=[0, 11, 3],
+                                             fmax=110.0), 0.2),
 }
 
 
