@@ -17,6 +17,10 @@ constexpr int kRowThreads = 256;       // threads per workgroup of the forward/a
 // workgroup (two per CU): they run 512 threads (8 waves) so that each SIMD
 // still holds four waves; shorter lengths run kRowThreads.
 constexpr int row_threads(int n) { return n >= 3072 ? 512 : kRowThreads; }
+// Compile-time row kernels fit four waves per SIMD in LDS (four 256-thread or
+// two 512-thread workgroups per CU); they are held to the 128 VGPRs that
+// allows.  Generic lengths keep their registers.
+constexpr int row_waves_per_eu(int n) { return n > 0 ? 4 : 1; }
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
 constexpr int kXfftTilePoints = 4096;  // complex points of a model x-FFT tile (T = 2 * this / nxp columns)

@@ -825,7 +825,7 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 }
 
 template <int N, int RC>
-__global__ __launch_bounds__(row_threads(N)) void k_rows_fwd(RowsArgs A) {
+__global__ __launch_bounds__(row_threads(N)) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu(N)))) void k_rows_fwd(RowsArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
@@ -1037,7 +1037,11 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
 #pragma unroll
             for (int t = -R + 1; t <= R; ++t) {
               const int k = sb.k0 + t;
-              if (k >= 1 && k <= hmax) {
+              // compile-time lengths skip the test: taps below bin 1 land in
+              // the padding that ends bufD (never read after its transform),
+              // taps past N/2-1 in bufM's own padding (overwritten by its
+              // transform), and pair 0 is never read by the inverse transform
+              if (N > 0 || (k >= 1 && k <= hmax)) {
                 const float wt = RC > 0 ? tap_weight(sb.trig, t, cr[(t + R - 1) % (2 * RT)], sr[(t + R - 1) % (2 * RT)])
                                         : tap_weight(sb.trig, t, ctab[t + R - 1], stab[t + R - 1]);
                 float4* q = reinterpret_cast<float4*>(bufM) + k;
@@ -1080,7 +1084,7 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
 }
 
 template <int N, int RC>
-__global__ __launch_bounds__(row_threads(N)) void k_rows_adj(RowsArgs A) {
+__global__ __launch_bounds__(row_threads(N)) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu(N)))) void k_rows_adj(RowsArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
