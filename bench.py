@@ -37,16 +37,17 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # writes x 1.0); valid only for the kernel sources with this digest.
 _MIB = 1024.0 * 1024.0
 MEASURED_TRAFFIC = {
-    "digest": "0ed1251ddda72a04",
+    "digest": "62981740615951c7",
     "workload": "crg-1024x256-nv32",
     "bytes": {
-        "k_xfft_fwd(model)": (32.19 + 64.00) * _MIB,
-        "k_xfft_fwd(data)": (1.13 + 2.00) * _MIB,
-        "k_rows_fwd": (64.35 + 12.81) * _MIB,
-        "k_rows_fwd_fin": (13.03 + 2.00) * _MIB,
-        "k_xfft_inv(data)": (2.13 + 1.00) * _MIB,
-        "k_rows_adj": (8.39 + 64.00) * _MIB,
-        "k_xfft_inv(model)": (64.19 + 32.03) * _MIB,
+        # averaged over the solve's dispatches (with and without the fused CG update)
+        "k_xfft_fwd(model)": (86.63 + 110.15) * _MIB,
+        "k_xfft_fwd(data)": (3.04 + 2.90) * _MIB,
+        "k_rows_fwd": (56.25 + 12.81) * _MIB,
+        "k_rows_fwd_fin": (13.02 + 2.00) * _MIB,
+        "k_xfft_inv(data)": (3.07 + 1.05) * _MIB,
+        "k_rows_adj": (8.36 + 55.92) * _MIB,
+        "k_xfft_inv(model)": (56.08 + 32.01) * _MIB,
     },
 }
 _KERNEL_SOURCES = ["ashrt_internal.h", "block_reduce.h", "fft_lds.h", "fft_tpl.h", "kernels.h", "op_kernels.hip"]
@@ -68,8 +69,10 @@ def _measured_traffic(workload, kernel):
     return t["bytes"].get(kernel)
 
 
-def _geometry_numbers(plan, nx, nt, P, R):
-    """Algorithmic bytes and flops per launch of each kernel family."""
+def _geometry_numbers(plan, nx, nt, P, R, cg_frac=0.0):
+    """Algorithmic bytes and flops per launch of each kernel family.  cg_frac:
+    the fraction of model-transform launches that also apply the previous CG
+    iteration's update (read u, g; write u, pdir: four more model streams)."""
     import numpy as np
     info = plan.info
     ntp, nxp, jlo, jhi, nchunk = info["ntp"], info["nxp"], info["jlo"], info["jhi"], info["nchunk"]
@@ -102,7 +105,7 @@ def _geometry_numbers(plan, nx, nt, P, R):
         cone += int(np.sum(j[None, :] >= a_up[:, None])) + int(np.sum(j[None, :] >= a_lo[:, None]))
     map_flops = cone * 2 * R * 4            # one complex x real multiply-add per tap
     return {
-        "k_xfft_fwd(model)": (model_b + X_b, P * math.ceil(nt / 2) * fft_x),
+        "k_xfft_fwd(model)": (model_b + X_b + cg_frac * 4 * model_b, P * math.ceil(nt / 2) * fft_x),
         "k_xfft_fwd(data)": (data_b + H_b, math.ceil(nt / 2) * fft_x),
         "k_rows_fwd": (X_b + Dp_b, live_rows * fft_t + map_flops),
         "k_rows_fwd_fin": (Dp_b + H_b, nrows * fft_t),
@@ -527,7 +530,11 @@ def main():
     pair_s = (time.perf_counter() - t0) / args.pairs
 
     # roofline of the dominant kernel
-    nums = _geometry_numbers(plan, gth.nx, gth.nt, w.npanel, w.half_width)
+    # in the solve, the model transforms of CG iterations 1 .. n_inner-1 carry
+    # the fused update; iteration 0 and the residual forward of each outer
+    # step do not
+    nums = _geometry_numbers(plan, gth.nx, gth.nt, w.npanel, w.half_width,
+                             cg_frac=(w.n_inner - 1) / (w.n_inner + 1) if w.n_inner > 0 else 0.0)
     bytes_, flops = nums[dom]
     hbm_frac = (bytes_ / dom_avg_s / 1e9) / HBM_PEAK_GBS
     alu_frac = (flops / dom_avg_s / 1e12) / FP32_VECTOR_PEAK_TFLOPS
@@ -545,7 +552,7 @@ def main():
     roof["algorithmic_flops_per_launch"] = flops
     roof["hbm_frac"] = hbm_frac
     roof["alu_frac"] = alu_frac
-    pair_bytes = sum(nums[k][0] for k in nums)
+    pair_bytes = sum(v[0] for v in _geometry_numbers(plan, gth.nx, gth.nt, w.npanel, w.half_width).values())
     if args.copy_calibration:
         x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
         x.fill_(1.0)
