@@ -863,16 +863,17 @@ struct CgUpd {
   float* u = nullptr;
   float* pdir = nullptr;
   const float* g = nullptr;
-  const double* part_gamma = nullptr;
   double* sc = nullptr;
   int par = 0;  // gamma slot of the previous iteration
 };
 
 // d_out = epilogue(L (mul_m * m)); the epilogue is: raw_out = y; y = sub - y;
 // y *= mask; y *= wmul.
+// part: per-tile partials of sum y^2 over the data tiles; with sc they are
+// also summed per gather into sc[SC_DELTA].
 hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* d_out, const float* sub,
                        const float* wmul, float* raw_out, const uint8_t* tmask, double* part = nullptr,
-                       const CgUpd* upd = nullptr) {
+                       const CgUpd* upd = nullptr, double* sc = nullptr) {
   const PlanImpl& P = *c.P;
   hipError_t e = hipSuccess;
   for (const auto& sg : P.s_xm) {
@@ -893,7 +894,6 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
       xa.cg_p = upd->pdir;
       xa.cg_u = upd->u;
       xa.cg_g = upd->g;
-      xa.part_gamma = upd->part_gamma;
       xa.sc = upd->sc;
     }
     e = timed(ASHRT_K_XFFT_MODEL, c.s, [&] { return launch_xfft_fwd(sg.key, xa, sg.lds, c.s); });
@@ -929,6 +929,8 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
     e = timed(ASHRT_K_XINV_DATA, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
     if (e != hipSuccess) return e;
   }
+  if (part && sc)
+    return timed(ASHRT_K_REDUCE, c.s, [&] { return launch_sum_items(P.d_gd, P.ngather, part, 0, sc, SC_DELTA, c.s); });
   return hipSuccess;
 }
 
@@ -936,14 +938,15 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
 struct CgStep {
   float* s_inout = nullptr;
   const float* qv = nullptr;
-  const double* part_delta = nullptr;
   double* sc = nullptr;
   int par = 0;
 };
 
-// m_out = wmul * L' (mask * mul_d * d); part: per-tile sums of m_out^2
+// m_out = wmul * L' (mask * mul_d * d); part: per-tile sums of m_out^2,
+// with sc also summed per gather into sc[SC_GNEW]
 hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const uint8_t* tmask, float* m_out,
-                       const float* wmul, double* part = nullptr, const CgStep* cg = nullptr) {
+                       const float* wmul, double* part = nullptr, const CgStep* cg = nullptr,
+                       double* sc = nullptr) {
   const PlanImpl& P = *c.P;
   hipError_t e = hipSuccess;
   for (const auto& sg : P.s_xd) {
@@ -962,7 +965,6 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     if (cg) {
       xa.s_inout = cg->s_inout;
       xa.qv = cg->qv;
-      xa.part_delta = cg->part_delta;
       xa.sc = cg->sc;
       xa.par = cg->par;
     }
@@ -990,6 +992,8 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     e = timed(ASHRT_K_XINV_MODEL, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
     if (e != hipSuccess) return e;
   }
+  if (part && sc)
+    return timed(ASHRT_K_REDUCE, c.s, [&] { return launch_sum_items(P.d_gd, P.ngather, part, 1, sc, SC_GNEW, c.s); });
   return hipSuccess;
 }
 
@@ -1123,7 +1127,6 @@ struct Solver {
     a.u = u;
     a.pdir = pdir;
     a.g = g;
-    a.part_gamma = pgam;
     a.sc = sc;
     return timed(ASHRT_K_VECTOR, c.s, [&] { return launch_cg(a, c.s); });
   }
@@ -1160,19 +1163,17 @@ hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fuse
   up.u = S.u;
   up.pdir = S.pdir;
   up.g = S.g;
-  up.part_gamma = S.pgam;
   up.sc = S.sc;
   up.par = par ^ 1;
-  hipError_t e =
-      run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel, fused ? &up : nullptr);
+  hipError_t e = run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel,
+                             fused ? &up : nullptr, S.sc);
   if (e != hipSuccess) return e;
   CgStep st;
   st.s_inout = S.s;
   st.qv = S.q;
-  st.part_delta = S.pdel;
   st.sc = S.sc;
   st.par = par;
-  return run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st);
+  return run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st, S.sc);
 }
 
 constexpr size_t kMaxCgGraphs = 8;
@@ -1303,7 +1304,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       a.z = S.r;
       E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
     }
-    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam));
+    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, nullptr, S.sc));
     E_TRY(S.cg(1, 0));
     if (prm->n_inner > 0) {
       // iteration 0 starts from pdir = g; iterations 1.. apply their

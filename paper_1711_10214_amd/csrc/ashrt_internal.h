@@ -93,7 +93,9 @@ enum ScalIdx {
   // FISTA: power-method sum of squares, Lipschitz constant, mu, step 2 / Lf,
   // threshold mu / Lf (misfit and ||m||_1 reuse SC_MISFIT and SC_HUBER)
   SC_POW_SS, SC_LIP, SC_MU, SC_FSTEP, SC_FTHR,
-  kNScal = 24
+  // CG: |g|^2 of the latest adjoint (its per-tile partials summed once per gather)
+  SC_GNEW,
+  kNScal = 25
 };
 
 // Radix-select state per gather: two order statistics (the two middle ranks).

@@ -18,17 +18,15 @@ struct XfwdArgs {
   const float2* tw;
   const PanelDev* panels; // live-row counts of the model panels
   // CG step (data input only): before the transform, s -= alpha q with
-  // alpha = gamma[par] / delta, delta summed from the forward's partials
-  // (every workgroup sums them in the same order; the first one stores it).
+  // alpha = gamma[par] / delta, delta = sc[SC_DELTA] (the forward's per-tile
+  // partials, summed by k_sum_items); the gather's first item stores alpha.
   float* s_inout;
   const float* qv;
-  const double* part_delta;
   double* sc;
   int par;
   int item_base;          // index of items[0] in the plan's full list (partials, first-item checks)
   // Model input with the previous CG iteration's update fused in (cg_upd):
-  // beta = gamma_new / gamma[cg_par] (gamma_new summed from the adjoint's
-  // per-tile partials part_gamma, each workgroup in the same order),
+  // beta = gamma_new / gamma[cg_par] (gamma_new = sc[SC_GNEW]),
   // alpha = sc[SC_ALPHA] (both 0 once done); u += alpha pdir,
   // pdir = g + beta pdir (cg_p, updated in place), and the new pdir is the
   // transform's input; the gather's first item stores gamma[cg_par ^ 1].
@@ -37,7 +35,6 @@ struct XfwdArgs {
   float* cg_p;
   float* cg_u;
   const float* cg_g;
-  const double* part_gamma;
 };
 
 struct XinvArgs {
@@ -160,9 +157,9 @@ struct SelArgs {
   int shift, width;        // digit = (key >> shift) & ((1 << width) - 1)
 };
 
-// CG initialisation and update over model-vector items.  Both reduce the
-// adjoint's per-tile partials of |g|^2 (each workgroup in the same order).
-//   init:   pdir = g ; gamma[0] = |g|^2, done = 0, ninner = 0
+// CG initialisation and update over model-vector items; gamma_new = |g|^2 of
+// the latest adjoint is sc[SC_GNEW].
+//   init:   pdir = g ; gamma[0] = gamma_new, done = 0, ninner = 0
 //   update: beta = gamma_new / gamma[par] ; u += alpha pdir ; pdir = g + beta pdir ;
 //           gamma[par ^ 1] = gamma_new
 struct CgArgs {
@@ -174,7 +171,6 @@ struct CgArgs {
   float* u;
   float* pdir;
   const float* g;
-  const double* part_gamma;
   double* sc;
 };
 
@@ -216,5 +212,9 @@ hipError_t launch_count_live(const GatherDev* gd, int ngather, const uint8_t* tm
                              hipStream_t s);
 hipError_t launch_select_median(SelArgs a, double* sc, int dst, hipStream_t s);
 hipError_t launch_cg(const CgArgs& a, hipStream_t s);
+// sc[g][dst] = sum of the per-tile partials of gather g's model (xm) or data
+// (xd) x-transform items, in a fixed order (one workgroup per gather).
+hipError_t launch_sum_items(const GatherDev* gd, int ngather, const double* part, int is_model, double* sc,
+                            int dst, hipStream_t s);
 
 }  // namespace ashrt

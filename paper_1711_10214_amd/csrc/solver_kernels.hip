@@ -376,18 +376,30 @@ __global__ __launch_bounds__(kThreads) void k_count_live(const GatherDev* gd, in
 }
 
 // CG initialisation / update over model-vector items (see CgArgs).
+// Per-gather sum of per-tile partials, in the fixed order of block_sum over
+// a thread-strided loop.
+__global__ __launch_bounds__(kThreads) void k_sum_items(const GatherDev* gd, int ngather, const double* part,
+                                                        int is_model, double* sc, int dst) {
+  __shared__ double sh[kThreads / 64];
+  const int g = blockIdx.x;
+  if (g >= ngather) return;
+  const GatherDev G = gd[g];
+  const int lo = is_model ? G.xm_lo : G.xd_lo;
+  const int hi = is_model ? G.xm_hi : G.xd_hi;
+  double a = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += kThreads) a += part[i];
+  const double r = block_sum(a, sh);
+  if (threadIdx.x == 0) sc[(long long)g * kNScal + dst] = r;
+}
+
 __global__ __launch_bounds__(kThreads) void k_cg(CgArgs A) {
   __shared__ float s_ab[2];
-  __shared__ double sh[kThreads / 64];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const VecItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
-    double part = 0.0;
-    for (int i = G.xm_lo + (int)threadIdx.x; i < G.xm_hi; i += kThreads) part += A.part_gamma[i];
-    const double gsum = block_sum(part, sh);
     if (threadIdx.x == 0) {
       double* sc = A.sc + (long long)w.g * kNScal;
-      const double gnew = gsum;
+      const double gnew = sc[SC_GNEW];
       if (A.init) {
         if (it == G.mit_lo) {
           sc[SC_GAMMA0] = gnew;
@@ -481,6 +493,13 @@ hipError_t launch_zero_words(void* p, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(kThreads), 0, s, (unsigned*)p, n);
   return hipGetLastError();
 }
+hipError_t launch_sum_items(const GatherDev* gd, int ngather, const double* part, int is_model, double* sc,
+                            int dst, hipStream_t s) {
+  if (ngather <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_items, dim3(ngather), dim3(kThreads), 0, s, gd, ngather, part, is_model, sc, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_cg(const CgArgs& a, hipStream_t s) {
   if (a.nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_cg, dim3(grid_of(a.nitems)), dim3(kThreads), 0, s, a);
