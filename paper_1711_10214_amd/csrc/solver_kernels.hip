@@ -376,19 +376,27 @@ __global__ __launch_bounds__(kThreads) void k_count_live(const GatherDev* gd, in
 }
 
 // CG initialisation / update over model-vector items (see CgArgs).
-// Per-gather sum of per-tile partials, in the fixed order of block_sum over
-// a thread-strided loop.
-__global__ __launch_bounds__(kThreads) void k_sum_items(const GatherDev* gd, int ngather, const double* part,
-                                                        int is_model, double* sc, int dst) {
-  __shared__ double sh[kThreads / 64];
+// Per-gather sum of per-tile partials in a fixed order: four interleaved
+// thread-strided partial sums per thread (loads in flight), then block_sum.
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void k_sum_items(const GatherDev* gd, int ngather, const double* part,
+                                                           int is_model, double* sc, int dst) {
+  __shared__ double sh[kSumThreads / 64];
   const int g = blockIdx.x;
   if (g >= ngather) return;
   const GatherDev G = gd[g];
   const int lo = is_model ? G.xm_lo : G.xd_lo;
   const int hi = is_model ? G.xm_hi : G.xd_hi;
-  double a = 0.0;
-  for (int i = lo + (int)threadIdx.x; i < hi; i += kThreads) a += part[i];
-  const double r = block_sum(a, sh);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = lo + (int)threadIdx.x;
+  for (; i + 3 * kSumThreads < hi; i += 4 * kSumThreads) {
+    a0 += part[i];
+    a1 += part[i + kSumThreads];
+    a2 += part[i + 2 * kSumThreads];
+    a3 += part[i + 3 * kSumThreads];
+  }
+  for (; i < hi; i += kSumThreads) a0 += part[i];
+  const double r = block_sum((a0 + a1) + (a2 + a3), sh);
   if (threadIdx.x == 0) sc[(long long)g * kNScal + dst] = r;
 }
 
@@ -496,7 +504,7 @@ hipError_t launch_zero_words(void* p, long long n, hipStream_t s) {
 hipError_t launch_sum_items(const GatherDev* gd, int ngather, const double* part, int is_model, double* sc,
                             int dst, hipStream_t s) {
   if (ngather <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sum_items, dim3(ngather), dim3(kThreads), 0, s, gd, ngather, part, is_model, sc, dst);
+  hipLaunchKernelGGL(k_sum_items, dim3(ngather), dim3(kSumThreads), 0, s, gd, ngather, part, is_model, sc, dst);
   return hipGetLastError();
 }
 
