@@ -67,6 +67,9 @@ static long long align_up(long long v, long long a) { return (v + a - 1) / a * a
 // Dynamic LDS a kernel may request (gfx950: 160 KB per workgroup, minus a
 // margin for the kernels' static LDS).
 static constexpr size_t kMaxDynLds = 150 * 1024;
+// Largest sum over gathers of (per-tile partials)^2 that the consuming
+// transform reduces in every workgroup (8 M doubles of cached reads per launch).
+static constexpr double kInKernelSumLimit = 8.0 * 1024 * 1024;
 
 // ------------------------------------------------------------ C ABI: defaults/validation
 extern "C" void ashrt_desc_default(ashrt_desc* d) {
@@ -207,6 +210,10 @@ struct PlanImpl {
   float* d_wav = nullptr;
   WorkItem *d_xm = nullptr, *d_xd = nullptr, *d_rf = nullptr, *d_rfin = nullptr, *d_ra = nullptr;
   int n_xm = 0, n_xd = 0, n_rf = 0, n_rfin = 0, n_ra = 0;
+  // CG reductions of per-tile partials: summed by every consuming workgroup
+  // (no extra launch) while that costs little (sum over gathers of items^2
+  // below kInKernelSumLimit), else once per gather by k_sum_items
+  bool sum_model_in_kernel = false, sum_data_in_kernel = false;
   // Work-list segments: items [first, first + count) share one kernel
   // instantiation (FFT length class `key`, 0 = generic) and LDS size.
   struct Seg {
@@ -579,6 +586,15 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   };
   P.n_xm = (int)xm.size();
   P.n_xd = (int)xd.size();
+  {
+    double cm = 0.0, cd = 0.0;
+    for (const auto& G : gd) {
+      cm += (double)(G.xm_hi - G.xm_lo) * (double)(G.xm_hi - G.xm_lo);
+      cd += (double)(G.xd_hi - G.xd_lo) * (double)(G.xd_hi - G.xd_lo);
+    }
+    P.sum_model_in_kernel = cm <= kInKernelSumLimit;
+    P.sum_data_in_kernel = cd <= kInKernelSumLimit;
+  }
   P.n_rf = (int)rf.size();
   P.n_rfin = (int)rfin.size();
   P.n_ra = (int)ra.size();
@@ -863,6 +879,7 @@ struct CgUpd {
   float* u = nullptr;
   float* pdir = nullptr;
   const float* g = nullptr;
+  const double* part_gamma = nullptr;  // the adjoint's per-tile partials of |g|^2
   double* sc = nullptr;
   int par = 0;  // gamma slot of the previous iteration
 };
@@ -894,6 +911,7 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
       xa.cg_p = upd->pdir;
       xa.cg_u = upd->u;
       xa.cg_g = upd->g;
+      xa.part_red = P.sum_model_in_kernel ? upd->part_gamma : nullptr;
       xa.sc = upd->sc;
     }
     e = timed(ASHRT_K_XFFT_MODEL, c.s, [&] { return launch_xfft_fwd(sg.key, xa, sg.lds, c.s); });
@@ -929,7 +947,7 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
     e = timed(ASHRT_K_XINV_DATA, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
     if (e != hipSuccess) return e;
   }
-  if (part && sc)
+  if (part && sc && !P.sum_data_in_kernel)
     return timed(ASHRT_K_REDUCE, c.s, [&] { return launch_sum_items(P.d_gd, P.ngather, part, 0, sc, SC_DELTA, c.s); });
   return hipSuccess;
 }
@@ -938,6 +956,7 @@ hipError_t run_forward(const Ctx& c, const float* m, const float* mul_m, float* 
 struct CgStep {
   float* s_inout = nullptr;
   const float* qv = nullptr;
+  const double* part_delta = nullptr;  // the forward's per-tile partials of |q|^2
   double* sc = nullptr;
   int par = 0;
 };
@@ -965,6 +984,7 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     if (cg) {
       xa.s_inout = cg->s_inout;
       xa.qv = cg->qv;
+      xa.part_red = P.sum_data_in_kernel ? cg->part_delta : nullptr;
       xa.sc = cg->sc;
       xa.par = cg->par;
     }
@@ -992,7 +1012,7 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     e = timed(ASHRT_K_XINV_MODEL, c.s, [&] { return launch_xfft_inv(sg.key, ia, sg.lds, c.s); });
     if (e != hipSuccess) return e;
   }
-  if (part && sc)
+  if (part && sc && !P.sum_model_in_kernel)
     return timed(ASHRT_K_REDUCE, c.s, [&] { return launch_sum_items(P.d_gd, P.ngather, part, 1, sc, SC_GNEW, c.s); });
   return hipSuccess;
 }
@@ -1127,6 +1147,7 @@ struct Solver {
     a.u = u;
     a.pdir = pdir;
     a.g = g;
+    a.part_gamma = P.sum_model_in_kernel ? pgam : nullptr;
     a.sc = sc;
     return timed(ASHRT_K_VECTOR, c.s, [&] { return launch_cg(a, c.s); });
   }
@@ -1163,6 +1184,7 @@ hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fuse
   up.u = S.u;
   up.pdir = S.pdir;
   up.g = S.g;
+  up.part_gamma = S.pgam;
   up.sc = S.sc;
   up.par = par ^ 1;
   hipError_t e = run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel,
@@ -1171,6 +1193,7 @@ hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fuse
   CgStep st;
   st.s_inout = S.s;
   st.qv = S.q;
+  st.part_delta = S.pdel;
   st.sc = S.sc;
   st.par = par;
   return run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st, S.sc);

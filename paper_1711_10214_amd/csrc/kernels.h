@@ -18,15 +18,19 @@ struct XfwdArgs {
   const float2* tw;
   const PanelDev* panels; // live-row counts of the model panels
   // CG step (data input only): before the transform, s -= alpha q with
-  // alpha = gamma[par] / delta, delta = sc[SC_DELTA] (the forward's per-tile
-  // partials, summed by k_sum_items); the gather's first item stores alpha.
+  // alpha = gamma[par] / delta; delta is the sum of the forward's per-tile
+  // partials, reduced here from part_red (every workgroup in the same
+  // order) when set, else read from sc[SC_DELTA] (summed by k_sum_items);
+  // the gather's first item stores alpha.
   float* s_inout;
   const float* qv;
+  const double* part_red;
   double* sc;
   int par;
   int item_base;          // index of items[0] in the plan's full list (partials, first-item checks)
   // Model input with the previous CG iteration's update fused in (cg_upd):
-  // beta = gamma_new / gamma[cg_par] (gamma_new = sc[SC_GNEW]),
+  // beta = gamma_new / gamma[cg_par] (gamma_new reduced from part_red as
+  // above when set, else sc[SC_GNEW]),
   // alpha = sc[SC_ALPHA] (both 0 once done); u += alpha pdir,
   // pdir = g + beta pdir (cg_p, updated in place), and the new pdir is the
   // transform's input; the gather's first item stores gamma[cg_par ^ 1].
@@ -158,7 +162,8 @@ struct SelArgs {
 };
 
 // CG initialisation and update over model-vector items; gamma_new = |g|^2 of
-// the latest adjoint is sc[SC_GNEW].
+// the latest adjoint is reduced from its per-tile partials part_gamma when
+// set (every workgroup in the same order), else read from sc[SC_GNEW].
 //   init:   pdir = g ; gamma[0] = gamma_new, done = 0, ninner = 0
 //   update: beta = gamma_new / gamma[par] ; u += alpha pdir ; pdir = g + beta pdir ;
 //           gamma[par ^ 1] = gamma_new
@@ -171,6 +176,7 @@ struct CgArgs {
   float* u;
   float* pdir;
   const float* g;
+  const double* part_gamma;
   double* sc;
 };
 

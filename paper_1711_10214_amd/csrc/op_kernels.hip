@@ -228,15 +228,22 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
   extern __shared__ float2 lds[];
   __shared__ float s_alpha;
   __shared__ float s_ab[2];
+  __shared__ double s_red[kThreads / 64];
   for (int it0 = blockIdx.x; it0 < A.nitems; it0 += gridDim.x) {
     const int it = (int)gridDim.x == A.nitems ? xcd_item(it0, A.nitems) : it0;
     const WorkItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
     float alpha = 0.f;
     if (A.s_inout) {
+      double dsum = 0.0;
+      if (A.part_red) {
+        double part = 0.0;
+        for (int i = G.xd_lo + (int)threadIdx.x; i < G.xd_hi; i += kThreads) part += A.part_red[i];
+        dsum = block_sum(part, s_red);
+      }
       if (threadIdx.x == 0) {
         double* sc = A.sc + (long long)w.g * kNScal;
-        const double delta = sc[SC_DELTA];
+        const double delta = A.part_red ? dsum : sc[SC_DELTA];
         const double gm = sc[SC_GAMMA0 + A.par];
         const bool stop = sc[SC_DONE] != 0.0 || gm == 0.0 || delta == 0.0 || !isfinite(gm) || !isfinite(delta);
         const double al = stop ? 0.0 : gm / delta;
@@ -252,9 +259,15 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     }
     float cg_a = 0.f, cg_b = 0.f;
     if (A.cg_upd) {
+      double gsum = 0.0;
+      if (A.part_red) {
+        double part = 0.0;
+        for (int i = G.xm_lo + (int)threadIdx.x; i < G.xm_hi; i += kThreads) part += A.part_red[i];
+        gsum = block_sum(part, s_red);
+      }
       if (threadIdx.x == 0) {
         double* sc = A.sc + (long long)w.g * kNScal;
-        const double gnew = sc[SC_GNEW];
+        const double gnew = A.part_red ? gsum : sc[SC_GNEW];
         const bool done = sc[SC_DONE] != 0.0;
         const double gold = sc[SC_GAMMA0 + A.cg_par];
         const double beta = (done || gold == 0.0) ? 0.0 : gnew / gold;

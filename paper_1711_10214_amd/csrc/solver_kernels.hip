@@ -402,12 +402,19 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_items(const GatherDev* gd, 
 
 __global__ __launch_bounds__(kThreads) void k_cg(CgArgs A) {
   __shared__ float s_ab[2];
+  __shared__ double sh[kThreads / 64];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const VecItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
+    double gsum = 0.0;
+    if (A.part_gamma) {
+      double part = 0.0;
+      for (int i = G.xm_lo + (int)threadIdx.x; i < G.xm_hi; i += kThreads) part += A.part_gamma[i];
+      gsum = block_sum(part, sh);
+    }
     if (threadIdx.x == 0) {
       double* sc = A.sc + (long long)w.g * kNScal;
-      const double gnew = sc[SC_GNEW];
+      const double gnew = A.part_gamma ? gsum : sc[SC_GNEW];
       if (A.init) {
         if (it == G.mit_lo) {
           sc[SC_GAMMA0] = gnew;
