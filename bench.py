@@ -103,7 +103,9 @@ def _geometry_numbers(plan, nx, nt, P, R, cg_frac=0.0):
         a_up = v * bin_ * l
         a_lo = v * bin_ * np.where(l == 0, nrows, l)
         cone += int(np.sum(j[None, :] >= a_up[:, None])) + int(np.sum(j[None, :] >= a_lo[:, None]))
-    map_flops = cone * 2 * R * 4            # one complex x real multiply-add per tap
+    # per in-cone output: one complex x real multiply-add per tap, plus ~40
+    # flops to evaluate the bin's tap weights (the survey's per-unit figure)
+    map_flops = cone * (2 * R * 4 + 40)
     return {
         "k_xfft_fwd(model)": (model_b + X_b + cg_frac * 4 * model_b, P * math.ceil(nt / 2) * fft_x),
         "k_xfft_fwd(data)": (data_b + H_b, math.ceil(nt / 2) * fft_x),
