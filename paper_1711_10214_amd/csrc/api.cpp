@@ -44,11 +44,7 @@ int set_error(int code, const std::string& msg) { return fail(code, msg); }
 // ------------------------------------------------------------ sizes
 static bool is_fft_len(int n) {
   if (n < 2) return false;
-  int s = 0;
-  while ((n & 1) == 0) {
-    n >>= 1;
-    ++s;
-  }
+  while ((n & 1) == 0) n >>= 1;
   return n == 1 || n == 3;
 }
 

@@ -73,6 +73,24 @@ def test_small_crg_solve_matches_oracle(A, pq):
         np.testing.assert_allclose(rep["eps_m"][1:], rep_r["eps_m"], rtol=1e-4)
 
 
+@pytest.mark.parametrize("nt_nx_inner", [(203, 37, 5), (256, 64, 1), (256, 64, 2)])
+def test_solve_edge_shapes_match_oracle(A, nt_nx_inner):
+    """Odd nt (the element-pair tails of the fused CG update) and one or two
+    CG iterations per outer step (no fused update / one, no graph), q = 1."""
+    nt, nx, n_inner = nt_nx_inner
+    w = workload("crg-256x64-nv8", nt=nt, nx=nx)
+    gth = make_gather(w)
+    kw = geom_kwargs(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
+    prm = IrlsParams(p=1, q=1, n_outer=3, n_inner=n_inner)
+    print(f"[gpu] invert parity nt={nt} nx={nx} n_inner={n_inner}", flush=True)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm)
+    e_d = rel_l2(d_g, d_r)
+    print(f"  d_rec rel-L2 {e_d:.2e}", flush=True)
+    assert rep["inner"] == rep_r["inner"]
+    assert e_d <= 1e-4
+    np.testing.assert_allclose(rep["misfit"], rep_r["misfit"], rtol=1e-4)
+
+
 def test_long_trace_solve_matches_oracle(A):
     """1536-sample traces (3072-point time FFTs, 512-thread row workgroups)
     through the fused CG iterations."""
