@@ -413,8 +413,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs one gather solve per GPU and has no "
-              "multi-GPU path (gathers are independent; see the sharding notes). Use --gpus 1.",
+        print("bench.py measures one GPU: the library solves each gather on one GPU and has no "
+              "multi-GPU path (gathers are independent, so a larger job shards by gather). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
