@@ -67,6 +67,9 @@ CASES = {
     "half-width-8": (geom_kwargs(160, 40, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0, half_width=8), 0.0),
     "tiny": (geom_kwargs(2, 2, 0.004, 12.5, [2000.0], ntp=8, nxp=4), 0.0),
     # long traces: the 3072- and 4096-point row kernels (512-thread workgroups)
+    # widest x transforms the plans take (nxp 4096, and 3072 = 3 * 2^10)
+    "wide-nxp4096": (geom_kwargs(48, 2048, 0.004, 12.5, [1500.0, 3000.0], fmax=100.0), 0.0),
+    "wide-nxp3072-mask": (geom_kwargs(40, 1500, 0.004, 12.5, [1800.0, 2900.0, 4200.0], fmax=100.0, nxp=3072), 0.15),
     "long-ntp3072": (geom_kwargs(1536, 16, 0.004, 12.5, [1500.0, 2600.0, 3800.0], fmax=110.0), 0.0),
     "long-ntp4096-ragged-mask": (geom_kwargs(1900, 10, 0.004, 12.5, [1500.0, 2600.0, 3800.0], tau0=[0, 11, 3],
                                              fmax=110.0), 0.2),
