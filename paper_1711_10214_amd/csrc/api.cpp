@@ -1,6 +1,6 @@
 // Host runtime of libashrt: argument validation, plans (small device tables
 // and work lists), workspace layout, the operator pipelines and the IRLS-CG
-// driver, behind the C ABI declared in include/ashrt.h.
+// solver loop, behind the C ABI declared in include/ashrt.h.
 //
 // Nothing here allocates large buffers: the caller's workspace holds every
 // intermediate spectrum and solver vector.  All launches go to the caller's
@@ -1061,7 +1061,7 @@ int adjoint_impl(const PlanImpl& P, const float* d, float* m, const uint8_t* mas
   return ASHRT_OK;
 }
 
-// ------------------------------------------------------------ IRLS-CG driver
+// ------------------------------------------------------------ IRLS-CG solver loop
 struct Solver {
   Ctx c;
   const PlanImpl& P;
@@ -1390,7 +1390,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
   return ASHRT_OK;
 }
 
-// ------------------------------------------------------------ FISTA driver
+// ------------------------------------------------------------ FISTA solver loop
 // Workspace: the solver layout with q = 1 (vectors r: residual; pdir: y;
 // g: gradient; u: power-method vector).
 int fista_impl(const PlanImpl& P, const fista_params* prm, const float* d, const uint8_t* mask, float* m,
