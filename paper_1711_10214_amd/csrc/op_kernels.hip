@@ -212,6 +212,117 @@ struct UDiv {
   __device__ __forceinline__ int div(int n) const { return d == 1 ? n : (int)__umulhi((unsigned)n, m); }
 };
 
+// A workgroup-uniform 64-bit value moved to scalar registers (values read
+// through vector loads are not known to be uniform), so that addresses built
+// from it take a scalar base plus one 32-bit VGPR offset.
+__device__ __forceinline__ long long uniform64(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <class V, class T>
+__device__ __forceinline__ V& at_byte(T* base, unsigned off) {
+  return *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + off);
+}
+template <class V, class T>
+__device__ __forceinline__ const V& at_byte(const T* base, unsigned off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// Input of a full model tile (nt even, t0 + T <= nt): the element pairs
+// (t, t+1) of the nx columns go to the LDS column pairs.  CG: the previous
+// CG iteration's update of the pair (u += ca p, p = g + cb p) comes first
+// and the new p is the input; MUL: the input is scaled by mul.  The loads
+// of kXLoadBatch loop iterations are issued before any of them is used (one
+// iteration at a time leaves a wave with a single load in flight); indices
+// past the tile are clamped for the loads and skipped for the stores.
+template <int NX, bool CG, bool MUL>
+__device__ __forceinline__ void xfwd_model_full_tile(float2* buf, int bs, const UDiv& dh, int half, int nx,
+                                                     int nt, int t0, const float* __restrict__ src,
+                                                     const float* __restrict__ mul, float* pp, float* uu,
+                                                     const float* gg, float ca, float cb) {
+  const int nin = nx * half;
+  for (int base = threadIdx.x; base < nin; base += kXLoadBatch * kThreads) {
+    float2 va[kXLoadBatch], vg[kXLoadBatch], vu[kXLoadBatch], vm[kXLoadBatch];
+    unsigned off[kXLoadBatch];  // byte offsets in the panel (4 nx nt < 2^32)
+#pragma unroll
+    for (int u = 0; u < kXLoadBatch; ++u) {
+      const int idx = min(base + u * kThreads, nin - 1);
+      const int x = dh.div(idx);
+      off[u] = 4u * (unsigned)(x * nt + t0 + 2 * (idx - x * half));
+      if constexpr (CG) {
+        va[u] = at_byte<float2>(pp, off[u]);
+        vg[u] = at_byte<float2>(gg, off[u]);
+        vu[u] = at_byte<float2>(uu, off[u]);
+      } else {
+        va[u] = at_byte<float2>(src, off[u]);
+      }
+      if constexpr (MUL) vm[u] = at_byte<float2>(mul, off[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kXLoadBatch; ++u) {
+      const int idx = base + u * kThreads;
+      if (idx < nin) {
+        const int x = dh.div(idx);
+        const int i = idx - x * half;
+        float2 v = va[u];
+        if constexpr (CG) {
+          at_byte<float2>(uu, off[u]) = make_float2(fmaf(ca, v.x, vu[u].x), fmaf(ca, v.y, vu[u].y));
+          v = make_float2(fmaf(cb, v.x, vg[u].x), fmaf(cb, v.y, vg[u].y));
+          at_byte<float2>(pp, off[u]) = v;
+        }
+        if constexpr (MUL) v = make_float2(v.x * vm[u].x, v.y * vm[u].y);
+        buf[i * bs + px<NX>(x)] = v;
+      }
+    }
+  }
+}
+
+// Input of a full tile of the x-spectrum rows (nt even, t0 + T <= nt) into
+// the LDS column pairs, Hermitian-completed: rows l >= 1 fill slots l and
+// nxp - l, row 0 packs (DC, Nyquist).  Rows nrw .. nrows-1 are zero and not
+// read.  Loads batched as in xfwd_model_full_tile.
+template <int NX>
+__device__ __forceinline__ void xinv_rows_full_tile(float2* buf, int bs, const UDiv& dh, int half, int nrows,
+                                                    int nrw, int nxp, int nt, int t0,
+                                                    const float2* __restrict__ src) {
+  const int nin = nrw * half;
+  for (int base = threadIdx.x; base < nin; base += kXLoadBatch * kThreads) {
+    float4 hv[kXLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kXLoadBatch; ++u) {
+      const int idx = min(base + u * kThreads, nin - 1);
+      const int l = dh.div(idx);
+      // byte offset in the panel's rows (8 nrows nt < 2^32)
+      hv[u] = at_byte<float4>(src, 8u * (unsigned)(l * nt + t0 + 2 * (idx - l * half)));
+    }
+#pragma unroll
+    for (int u = 0; u < kXLoadBatch; ++u) {
+      const int idx = base + u * kThreads;
+      if (idx < nin) {
+        const int l = dh.div(idx);
+        const int i = idx - l * half;
+        const float2 h1 = make_float2(hv[u].x, hv[u].y), h2 = make_float2(hv[u].z, hv[u].w);
+        float2* Z = buf + i * bs;
+        if (l == 0) {
+          Z[0] = make_float2(h1.x, h2.x);
+          Z[px<NX>(nrows)] = make_float2(h1.y, h2.y);
+        } else {
+          Z[px<NX>(l)] = make_float2(h1.x - h2.y, h1.y + h2.x);
+          Z[px<NX>(nxp - l)] = make_float2(h1.x + h2.y, -h1.y + h2.x);
+        }
+      }
+    }
+  }
+  for (int idx = nin + (int)threadIdx.x; idx < nrows * half; idx += kThreads) {
+    const int l = dh.div(idx);  // >= nrw >= 1
+    const int i = idx - l * half;
+    float2* Z = buf + i * bs;
+    Z[px<NX>(l)] = make_float2(0.f, 0.f);
+    Z[px<NX>(nxp - l)] = make_float2(0.f, 0.f);
+  }
+}
+
 // Work-item order for a one-item-per-workgroup launch of n items on the 8
 // XCDs.  Workgroup b runs on XCD b mod 8; this gives XCD x the consecutive
 // items [x q + min(x, r), ...) (q = n div 8, r = n mod 8), so neighbouring
@@ -290,13 +401,26 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     float2* twl = lds;                          // x twiddles
     float2* buf = lds + fft_tw_slots(NX, nxp);  // T/2 packed column pairs, odd slot stride bs
     stage_twiddles<NX>(twl, A.tw, G.tw_x_off, G.twp_x_off, nxp);
-    const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
+    const long long fbase = uniform64(A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off);
     const float* __restrict__ src = A.src + fbase;
     const float* __restrict__ mul = A.mul ? A.mul + fbase : nullptr;
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     const bool even = (nt & 1) == 0;
 
     const UDiv dh(half);
+    if (A.is_model && even && t0 + T <= nt) {
+      // a full model tile (all but a ragged last one)
+      float* pp = A.cg_upd ? A.cg_p + fbase : nullptr;
+      float* uu = A.cg_upd ? A.cg_u + fbase : nullptr;
+      const float* gg = A.cg_upd ? A.cg_g + fbase : nullptr;
+      if (A.cg_upd) {
+        if (mul) xfwd_model_full_tile<NX, true, true>(buf, bs, dh, half, nx, nt, t0, src, mul, pp, uu, gg, cg_a, cg_b);
+        else xfwd_model_full_tile<NX, true, false>(buf, bs, dh, half, nx, nt, t0, src, mul, pp, uu, gg, cg_a, cg_b);
+      } else {
+        if (mul) xfwd_model_full_tile<NX, false, true>(buf, bs, dh, half, nx, nt, t0, src, mul, pp, uu, gg, 0.f, 0.f);
+        else xfwd_model_full_tile<NX, false, false>(buf, bs, dh, half, nx, nt, t0, src, mul, pp, uu, gg, 0.f, 0.f);
+      }
+    } else
     for (int idx = threadIdx.x; idx < nx * half; idx += kThreads) {
       const int x = dh.div(idx);
       const int i = idx - x * half;
@@ -460,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const int T = A.is_model ? G.tileT : G.tileTd, half = T >> 1;
     const int bs = ((NX > 0 ? fft_padlen(nxp) : nxp) | 1);  // odd slot stride between columns
     const int t0 = w.b * T;
-    const float2* __restrict__ src = A.src + (A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
+    const float2* __restrict__ src = A.src + uniform64(A.is_model ? G.X_off + (long long)p * nrows * nt : G.H_off);
     float2* twl = lds;
     float2* buf = lds + fft_tw_slots(NX, nxp);
     if (!A.is_model && G.nudft_off >= 0) {
@@ -507,6 +631,10 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const bool even = (nt & 1) == 0;
     // model panels: rows at or above the panel's live-row count are zero (not stored)
     const int nrw = A.is_model ? min(nrows, A.panels[G.panel_off + p].rlive) : nrows;
+    if (even && t0 + T <= nt) {
+      // a full tile (all but a ragged last one)
+      xinv_rows_full_tile<NX>(buf, bs, dh, half, nrows, nrw, nxp, nt, t0, src);
+    } else
     for (int idx = threadIdx.x; idx < nrows * half; idx += kThreads) {
       const int l = dh.div(idx);
       const int i = idx - l * half;
@@ -536,9 +664,39 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     xfft_tile<NX, true>(buf, nxp, half, bs, twl, nx);
 
     const float inv = 1.0f / (float)nxp;
-    const long long fbase = A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off;
+    const long long fbase = uniform64(A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off);
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     double ss = 0.0;
+    if (A.is_model && A.wmul && even && t0 + T <= nt) {
+      // a full model tile scaled by wmul: the wmul loads of kXLoadBatch loop
+      // iterations are issued together (indices past the tile clamped)
+      const float* __restrict__ wm = A.wmul + fbase;
+      float* __restrict__ out = A.out + fbase;
+      const int nin = nx * half;
+      for (int base = threadIdx.x; base < nin; base += kXLoadBatch * kThreads) {
+        float2 wv[kXLoadBatch];
+        unsigned off[kXLoadBatch];  // byte offsets in the panel (4 nx nt < 2^32)
+#pragma unroll
+        for (int u = 0; u < kXLoadBatch; ++u) {
+          const int idx = min(base + u * kThreads, nin - 1);
+          const int x = dh.div(idx);
+          off[u] = 4u * (unsigned)(x * nt + t0 + 2 * (idx - x * half));
+          wv[u] = at_byte<float2>(wm, off[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kXLoadBatch; ++u) {
+          const int idx = base + u * kThreads;
+          if (idx < nin) {
+            const int x = dh.div(idx);
+            const int i = idx - x * half;
+            const float2 z = buf[i * bs + px<NX>(x)];
+            const float2 v = make_float2(z.x * inv * wv[u].x, z.y * inv * wv[u].y);
+            at_byte<float2>(out, off[u]) = v;
+            ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          }
+        }
+      }
+    } else
     for (int idx = threadIdx.x; idx < nx * half; idx += kThreads) {
       const int x = dh.div(idx);
       const int i = idx - x * half;
