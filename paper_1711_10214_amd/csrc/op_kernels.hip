@@ -1014,36 +1014,80 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
   float2* twl = lds;
   float2* buf = lds + fft_tw_slots(N, ntp);
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
-  // time-spectrum bin k of the row: the chunk sums, Hermitian completion
+  // time-spectrum bin k of the row: the chunk sums, Hermitian completion.
+  // Branch-free (bins outside the band read the band's first entry and are
+  // zeroed by a select), so the loads of all of a thread's bins can be in
+  // flight together.
+  const float2* __restrict__ dp0 = A.Dp + uniform64(G.Dp_off + (long long)r * 2 * nband);
+  const long long cstride = uniform64((long long)nrows * 2 * nband);
   auto bin = [&](int k) {
-    float2 v = make_float2(0.f, 0.f);
-    const int j = (k >= jlo && k <= jhi) ? k : ((ntp - k >= jlo && ntp - k <= jhi) ? ntp - k : -1);
-    if (j >= 0) {
-      float2 su = make_float2(0.f, 0.f), sl = make_float2(0.f, 0.f);
-      for (int c = 0; c < G.nchunk; ++c) {
-        const float2* dp = A.Dp + G.Dp_off + ((long long)c * nrows + r) * 2 * nband;
-        su = cadd(su, dp[j - jlo]);
-        sl = cadd(sl, dp[nband + j - jlo]);
-      }
-      if (j == k) {
-        v = (r == 0) ? make_float2(su.x - sl.y, su.y + sl.x) : su;
-      } else {
-        v = (r == 0) ? make_float2(su.x + sl.y, -su.y + sl.x) : cconj(sl);
-      }
+    const bool up = k >= jlo && k <= jhi;
+    const bool dn = !up && ntp - k >= jlo && ntp - k <= jhi;
+    const int jj = (up ? k : (dn ? ntp - k : jlo)) - jlo;
+    float2 su = make_float2(0.f, 0.f), sl = make_float2(0.f, 0.f);
+    for (int c = 0; c < G.nchunk; ++c) {
+      su = cadd(su, dp0[c * cstride + jj]);
+      sl = cadd(sl, dp0[c * cstride + nband + jj]);
     }
-    return v;
+    const float2 vu = (r == 0) ? make_float2(su.x - sl.y, su.y + sl.x) : su;
+    const float2 vd = (r == 0) ? make_float2(su.x + sl.y, -su.y + sl.x) : cconj(sl);
+    return up ? vu : (dn ? vd : make_float2(0.f, 0.f));
   };
   const float inv = 1.0f / (float)ntp;
   float2* __restrict__ dst = A.H + G.H_off + (long long)r * nt;
   if constexpr (N > 0) {
     // first pass from registers, last pass to global memory
-    FftRegsIn<N, NT> in;
+    // the chunk loop outside, the thread's bins inside: all of a chunk's
+    // loads are issued together
+    using I = FftRegsIn<N, NT>;
+    I in;
+    float2 sl[I::MAXB][I::R];
+    int jj[I::MAXB][I::R];
 #pragma unroll
-    for (int i = 0; i < FftRegsIn<N, NT>::MAXB; ++i) {
+    for (int i = 0; i < I::MAXB; ++i) {
+#pragma unroll
+      for (int q = 0; q < I::R; ++q) {
+        const int k = min((int)threadIdx.x + i * NT, I::B - 1) + q * I::B;
+        const bool up = k >= jlo && k <= jhi;
+        const bool dn = !up && ntp - k >= jlo && ntp - k <= jhi;
+        jj[i][q] = 8 * ((up ? k : (dn ? ntp - k : jlo)) - jlo);  // byte offset
+        in.v[i][q] = make_float2(0.f, 0.f);
+        sl[i][q] = make_float2(0.f, 0.f);
+      }
+    }
+    for (int c = 0; c < G.nchunk; ++c) {
+      const float2* __restrict__ dpc = dp0 + c * cstride;
+      float2 lu[I::MAXB][I::R], ld[I::MAXB][I::R];
+#pragma unroll
+      for (int i = 0; i < I::MAXB; ++i) {
+#pragma unroll
+        for (int q = 0; q < I::R; ++q) {
+          lu[i][q] = at_byte<float2>(dpc, (unsigned)jj[i][q]);
+          ld[i][q] = at_byte<float2>(dpc + nband, (unsigned)jj[i][q]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < I::MAXB; ++i) {
+#pragma unroll
+        for (int q = 0; q < I::R; ++q) {
+          in.v[i][q] = cadd(in.v[i][q], lu[i][q]);
+          sl[i][q] = cadd(sl[i][q], ld[i][q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < I::MAXB; ++i) {
       const int id = (int)threadIdx.x + i * NT;
 #pragma unroll
-      for (int q = 0; q < FftRegsIn<N, NT>::R; ++q)
-        in.v[i][q] = id < FftRegsIn<N, NT>::B ? bin(id + q * FftRegsIn<N, NT>::B) : make_float2(0.f, 0.f);
+      for (int q = 0; q < I::R; ++q) {
+        const int k = id + q * I::B;
+        const bool up = k >= jlo && k <= jhi;
+        const bool dn = !up && ntp - k >= jlo && ntp - k <= jhi;
+        const float2 su = in.v[i][q], sd = sl[i][q];
+        const float2 vu = (r == 0) ? make_float2(su.x - sd.y, su.y + sd.x) : su;
+        const float2 vd = (r == 0) ? make_float2(su.x + sd.y, -su.y + sd.x) : cconj(sd);
+        in.v[i][q] = (id < I::B && up) ? vu : ((id < I::B && dn) ? vd : make_float2(0.f, 0.f));
+      }
     }
     fft_tpl_regs_pass0<N, true, NT>(buf, in);
     using O = FftRegsOut<N, NT>;
@@ -1068,7 +1112,9 @@ __device__ __forceinline__ void rows_fin_item(const RowsArgs& A, const WorkItem&
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_rows_fwd_fin(RowsArgs A) {
+// one workgroup per row and a few hundred rows: occupancy is low anyway, so the
+// register budget goes to loads in flight
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_rows_fwd_fin(RowsArgs A) {
   extern __shared__ float2 lds[];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const WorkItem w = A.items[it];

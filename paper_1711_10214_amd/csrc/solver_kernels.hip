@@ -440,22 +440,37 @@ __global__ __launch_bounds__(kThreads) void k_cg(CgArgs A) {
     float* __restrict__ u = A.u + w.start;
     float* __restrict__ p = A.pdir + w.start;
     const float* __restrict__ g = A.g + w.start;
-    if (((w.start | w.len) & 3) == 0) {
+    if (((w.start | w.len) & 3) == 0 && w.len > 0) {
       float4* u4 = reinterpret_cast<float4*>(u);
       float4* p4 = reinterpret_cast<float4*>(p);
       const float4* g4 = reinterpret_cast<const float4*>(g);
-      for (long long i = threadIdx.x; i < (w.len >> 2); i += kThreads) {
-        const float4 gv = g4[i];
-        if (A.init) {
-          p4[i] = gv;
-        } else {
-          const float4 pv = p4[i];
-          float4 uv = u4[i];
-          uv = make_float4(fmaf(alpha, pv.x, uv.x), fmaf(alpha, pv.y, uv.y), fmaf(alpha, pv.z, uv.z),
-                           fmaf(alpha, pv.w, uv.w));
-          u4[i] = uv;
-          p4[i] = make_float4(fmaf(beta, pv.x, gv.x), fmaf(beta, pv.y, gv.y), fmaf(beta, pv.z, gv.z),
-                              fmaf(beta, pv.w, gv.w));
+      // the loads of kBatch loop iterations are issued before any is used
+      // (indices past the item clamped for the loads, skipped for the stores)
+      constexpr int kBatch = 4;
+      const int n4 = (int)(w.len >> 2);
+      for (int base = threadIdx.x; base < n4; base += kBatch * kThreads) {
+        float4 gv[kBatch], pv[kBatch], uv[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int i = min(base + b * kThreads, n4 - 1);
+          gv[b] = g4[i];
+          if (!A.init) {
+            pv[b] = p4[i];
+            uv[b] = u4[i];
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int i = base + b * kThreads;
+          if (i >= n4) break;
+          if (A.init) {
+            p4[i] = gv[b];
+          } else {
+            u4[i] = make_float4(fmaf(alpha, pv[b].x, uv[b].x), fmaf(alpha, pv[b].y, uv[b].y),
+                                fmaf(alpha, pv[b].z, uv[b].z), fmaf(alpha, pv[b].w, uv[b].w));
+            p4[i] = make_float4(fmaf(beta, pv[b].x, gv[b].x), fmaf(beta, pv[b].y, gv[b].y),
+                                fmaf(beta, pv[b].z, gv[b].z), fmaf(beta, pv[b].w, gv[b].w));
+          }
         }
       }
     } else {
