@@ -278,6 +278,62 @@ __device__ __forceinline__ void xfwd_model_full_tile(float2* buf, int bs, const 
   }
 }
 
+// Input of a full data tile (nt even, t0 + T <= nt), loads batched as in
+// xfwd_model_full_tile.  SCG: the CG step s -= alpha q first (s is written
+// back) and the new s is the input; MUL: times mul; traces with tm[x] == 0
+// (tm non-null) give zero.
+template <int NX, bool SCG, bool MUL>
+__device__ __forceinline__ void xfwd_data_full_tile(float2* buf, int bs, const UDiv& dh, int half, int nx,
+                                                    int nt, int t0, const float* __restrict__ src,
+                                                    const float* __restrict__ mul,
+                                                    const uint8_t* __restrict__ tm, float* sv,
+                                                    const float* qv, float alpha) {
+  const int nin = nx * half;
+  for (int base = threadIdx.x; base < nin; base += kXLoadBatch * kThreads) {
+    float2 va[kXLoadBatch], vq[kXLoadBatch], vm[kXLoadBatch];
+    int live[kXLoadBatch];  // trace index, then its mask byte
+    unsigned off[kXLoadBatch];  // byte offsets in the gather (4 nx nt < 2^32)
+#pragma unroll
+    for (int u = 0; u < kXLoadBatch; ++u) {
+      const int idx = min(base + u * kThreads, nin - 1);
+      const int x = dh.div(idx);
+      off[u] = 4u * (unsigned)(x * nt + t0 + 2 * (idx - x * half));
+      if constexpr (SCG) {
+        va[u] = at_byte<float2>(sv, off[u]);
+        vq[u] = at_byte<float2>(qv, off[u]);
+      } else {
+        va[u] = at_byte<float2>(src, off[u]);
+      }
+      if constexpr (MUL) vm[u] = at_byte<float2>(mul, off[u]);
+      live[u] = x;
+    }
+    // mask bytes after every other load of the batch is issued
+    if (tm) {
+#pragma unroll
+      for (int u = 0; u < kXLoadBatch; ++u) live[u] = tm[live[u]];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kXLoadBatch; ++u) live[u] = 1;
+    }
+#pragma unroll
+    for (int u = 0; u < kXLoadBatch; ++u) {
+      const int idx = base + u * kThreads;
+      if (idx < nin) {
+        const int x = dh.div(idx);
+        const int i = idx - x * half;
+        float2 v = va[u];
+        if constexpr (SCG) {
+          v = make_float2(fmaf(-alpha, vq[u].x, v.x), fmaf(-alpha, vq[u].y, v.y));
+          at_byte<float2>(sv, off[u]) = v;
+        }
+        if constexpr (MUL) v = make_float2(v.x * vm[u].x, v.y * vm[u].y);
+        if (live[u] == 0) v = make_float2(0.f, 0.f);
+        buf[i * bs + px<NX>(x)] = v;
+      }
+    }
+  }
+}
+
 // Input of a full tile of the x-spectrum rows (nt even, t0 + T <= nt) into
 // the LDS column pairs, Hermitian-completed: rows l >= 1 fill slots l and
 // nxp - l, row 0 packs (DC, Nyquist).  Rows nrw .. nrows-1 are zero and not
@@ -408,7 +464,18 @@ __global__ __launch_bounds__(kThreads) void k_xfft_fwd(XfwdArgs A) {
     const bool even = (nt & 1) == 0;
 
     const UDiv dh(half);
-    if (A.is_model && even && t0 + T <= nt) {
+    if (!A.is_model && even && t0 + T <= nt && G.nudft_off < 0) {
+      // a full data tile (all but a ragged last one)
+      float* sv = A.s_inout ? A.s_inout + fbase : nullptr;
+      const float* qv = A.s_inout ? A.qv + fbase : nullptr;
+      if (A.s_inout) {
+        if (mul) xfwd_data_full_tile<NX, true, true>(buf, bs, dh, half, nx, nt, t0, src, mul, tm, sv, qv, alpha);
+        else xfwd_data_full_tile<NX, true, false>(buf, bs, dh, half, nx, nt, t0, src, mul, tm, sv, qv, alpha);
+      } else {
+        if (mul) xfwd_data_full_tile<NX, false, true>(buf, bs, dh, half, nx, nt, t0, src, mul, tm, sv, qv, alpha);
+        else xfwd_data_full_tile<NX, false, false>(buf, bs, dh, half, nx, nt, t0, src, mul, tm, sv, qv, alpha);
+      }
+    } else if (A.is_model && even && t0 + T <= nt) {
       // a full model tile (all but a ragged last one)
       float* pp = A.cg_upd ? A.cg_p + fbase : nullptr;
       float* uu = A.cg_upd ? A.cg_u + fbase : nullptr;
@@ -667,21 +734,35 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
     const long long fbase = uniform64(A.is_model ? (G.m_off + (long long)p * nx * nt) : G.d_off);
     const uint8_t* __restrict__ tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     double ss = 0.0;
-    if (A.is_model && A.wmul && even && t0 + T <= nt) {
-      // a full model tile scaled by wmul: the wmul loads of kXLoadBatch loop
-      // iterations are issued together (indices past the tile clamped)
-      const float* __restrict__ wm = A.wmul + fbase;
+    if (even && t0 + T <= nt && (A.wmul || A.sub)) {
+      // a full tile whose epilogue reads memory (wmul, sub): the loads of
+      // kXLoadBatch loop iterations are issued together (indices past the
+      // tile clamped)
+      const float* __restrict__ wm = A.wmul ? A.wmul + fbase : nullptr;
+      const float* __restrict__ sb = A.sub ? A.sub + fbase : nullptr;
+      float* __restrict__ raw = A.raw_out ? A.raw_out + fbase : nullptr;
       float* __restrict__ out = A.out + fbase;
       const int nin = nx * half;
       for (int base = threadIdx.x; base < nin; base += kXLoadBatch * kThreads) {
-        float2 wv[kXLoadBatch];
-        unsigned off[kXLoadBatch];  // byte offsets in the panel (4 nx nt < 2^32)
+        float2 wv[kXLoadBatch], sv[kXLoadBatch];
+        int live[kXLoadBatch];  // trace index, then its mask byte
+        unsigned off[kXLoadBatch];  // byte offsets (4 nx nt < 2^32)
 #pragma unroll
         for (int u = 0; u < kXLoadBatch; ++u) {
           const int idx = min(base + u * kThreads, nin - 1);
           const int x = dh.div(idx);
           off[u] = 4u * (unsigned)(x * nt + t0 + 2 * (idx - x * half));
-          wv[u] = at_byte<float2>(wm, off[u]);
+          if (wm) wv[u] = at_byte<float2>(wm, off[u]);
+          if (sb) sv[u] = at_byte<float2>(sb, off[u]);
+          live[u] = x;
+        }
+        // mask bytes after every other load of the batch is issued
+        if (tm) {
+#pragma unroll
+          for (int u = 0; u < kXLoadBatch; ++u) live[u] = tm[live[u]];
+        } else {
+#pragma unroll
+          for (int u = 0; u < kXLoadBatch; ++u) live[u] = 1;
         }
 #pragma unroll
         for (int u = 0; u < kXLoadBatch; ++u) {
@@ -690,7 +771,11 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
             const int x = dh.div(idx);
             const int i = idx - x * half;
             const float2 z = buf[i * bs + px<NX>(x)];
-            const float2 v = make_float2(z.x * inv * wv[u].x, z.y * inv * wv[u].y);
+            float2 v = make_float2(z.x * inv, z.y * inv);
+            if (raw) at_byte<float2>(raw, off[u]) = v;
+            if (sb) v = make_float2(sv[u].x - v.x, sv[u].y - v.y);
+            if (live[u] == 0) v = make_float2(0.f, 0.f);
+            if (wm) v = make_float2(v.x * wv[u].x, v.y * wv[u].y);
             at_byte<float2>(out, off[u]) = v;
             ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
           }
