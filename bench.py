@@ -31,23 +31,21 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
 
-# HBM bytes per launch of each operator kernel on the production gather,
-# from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch)
-# scaled by what the counters read for a 512 MiB device copy (reads x 2.0,
-# writes x 1.0); valid only for the kernel sources with this digest.
+# HBM bytes per launch of the row kernels on the production gather, by the
+# plan's panel-chunk count (which sets their grid), from rocprofv3 --pmc
+# FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch) scaled by what the
+# counters read for a 512 MiB device copy (reads x 2.0, writes x 1.0); valid
+# only for the kernel sources with this digest.
 _MIB = 1024.0 * 1024.0
 MEASURED_TRAFFIC = {
-    "digest": "e7ca35d10b663707",
+    "digest": "af201001afc7d11d",
     "workload": "crg-1024x256-nv32",
     "bytes": {
-        # averaged over the solve's dispatches (with and without the fused CG update)
-        "k_xfft_fwd(model)": (86.82 + 110.15) * _MIB,
-        "k_xfft_fwd(data)": (1.20 + 2.00) * _MIB,
-        "k_rows_fwd": (56.26 + 12.81) * _MIB,
-        "k_rows_fwd_fin": (13.00 + 2.00) * _MIB,
-        "k_xfft_inv(data)": (2.18 + 1.00) * _MIB,
-        "k_rows_adj": (8.36 + 55.92) * _MIB,
-        "k_xfft_inv(model)": (56.13 + 32.01) * _MIB,
+        # nchunk -> read + write
+        "k_rows_fwd": {1: (56.14 + 3.20) * _MIB, 2: (56.18 + 6.41) * _MIB, 4: (56.25 + 12.81) * _MIB,
+                       8: (56.42 + 25.59) * _MIB},
+        "k_rows_adj": {1: (2.27 + 55.92) * _MIB, 2: (4.30 + 55.92) * _MIB, 4: (8.36 + 55.92) * _MIB,
+                       8: (16.51 + 55.92) * _MIB},
     },
 }
 _KERNEL_SOURCES = ["ashrt_internal.h", "block_reduce.h", "fft_lds.h", "fft_tpl.h", "kernels.h", "op_kernels.hip"]
@@ -62,11 +60,11 @@ def _kernel_digest():
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(workload, kernel):
+def _measured_traffic(workload, kernel, nchunk):
     t = MEASURED_TRAFFIC
     if t["workload"] != workload or t["digest"] != _kernel_digest():
         return None
-    return t["bytes"].get(kernel)
+    return t["bytes"].get(kernel, {}).get(nchunk)
 
 
 def _geometry_numbers(plan, nx, nt, P, R, cg_frac=0.0):
@@ -546,7 +544,7 @@ def main():
         roof = {"bound": "alu", "achieved": flops / dom_avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = _measured_traffic(w.name, dom)
+    roof["traffic"] = _measured_traffic(w.name, dom, plan.info["nchunk"])
     roof["kernel"] = dom
     roof["avg_launch_us"] = dom_avg_s * 1e6
     roof["launches_timed"] = n.value
