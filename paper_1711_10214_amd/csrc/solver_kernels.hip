@@ -266,11 +266,16 @@ __device__ __forceinline__ float key_float(unsigned k) {
 }
 
 
+// kSelSplit workgroups per vector item (a gather's residual has only
+// nx nt / 8192 items); each thread issues the loads of four samples before
+// it bins them.
+constexpr int kSelSplit = 4;
 __global__ __launch_bounds__(kThreads) void k_sel_hist(SelArgs A) {
   __shared__ unsigned h[2][kSelBins];
-  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+  for (int b = blockIdx.x; b < A.nitems * kSelSplit; b += gridDim.x) {
     for (int i = threadIdx.x; i < 2 * kSelBins; i += kThreads) (&h[0][0])[i] = 0u;
     __syncthreads();
+    const int it = b / kSelSplit, part = b - it * kSelSplit;
     const VecItem w = A.items[it];
     const GatherDev G = A.gd[w.g];
     const SelState S = A.st[w.g];
@@ -278,15 +283,31 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(SelArgs A) {
     const unsigned dmask = (1u << A.width) - 1u;
     const uint8_t* tm = A.tmask ? A.tmask + G.mask_off : nullptr;
     const double med = A.stage ? A.sc[w.g * kNScal + SC_MED] : 0.0;
-    for (long long i = threadIdx.x; i < w.len; i += kThreads) {
-      const long long o = w.start + i;
-      if (tm && tm[(o - G.d_off) / G.nt] == 0) continue;
-      float v = A.x[o];
-      if (A.stage) v = (float)fabs((double)v - med);
-      const unsigned key = float_key(v);
-      const unsigned dg = (key >> A.shift) & dmask;
-      if ((key & hmask) == (S.prefix[0] & hmask)) atomicAdd(&h[0][dg], 1u);
-      if ((key & hmask) == (S.prefix[1] & hmask)) atomicAdd(&h[1][dg], 1u);
+    const long long lo = w.start + w.len * part / kSelSplit;
+    const int n = (int)(w.start + w.len * (part + 1) / kSelSplit - lo);
+    const unsigned rel0 = (unsigned)(lo - G.d_off);  // sample index in the gather (nx nt < 2^31)
+    for (int base = threadIdx.x; base < n; base += 4 * kThreads) {
+      float v[4];
+      int live[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = A.x[lo + min(base + u * kThreads, n - 1)];
+      if (tm) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) live[u] = tm[(rel0 + (unsigned)min(base + u * kThreads, n - 1)) / (unsigned)G.nt];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) live[u] = 1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (base + u * kThreads >= n || live[u] == 0) continue;
+        float x = v[u];
+        if (A.stage) x = (float)fabs((double)x - med);
+        const unsigned key = float_key(x);
+        const unsigned dg = (key >> A.shift) & dmask;
+        if ((key & hmask) == (S.prefix[0] & hmask)) atomicAdd(&h[0][dg], 1u);
+        if ((key & hmask) == (S.prefix[1] & hmask)) atomicAdd(&h[1][dg], 1u);
+      }
     }
     __syncthreads();
     unsigned* gh = A.hist + (long long)w.g * 2 * kSelBins;
@@ -550,7 +571,7 @@ hipError_t launch_select_median(SelArgs a, double* sc, int dst, hipStream_t s) {
   for (int pass = 0; pass < 3; ++pass) {
     a.shift = shifts[pass];
     a.width = widths[pass];
-    if (a.nitems > 0) hipLaunchKernelGGL(k_sel_hist, dim3(grid_of(a.nitems)), dim3(kThreads), 0, s, a);
+    if (a.nitems > 0) hipLaunchKernelGGL(k_sel_hist, dim3(grid_of(a.nitems * kSelSplit)), dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(k_sel_pick, dim3(grid_of(a.ngather)), dim3(kThreads), 0, s, a);
   }
   hipLaunchKernelGGL(k_sel_final, dim3((a.ngather + 63) / 64), dim3(64), 0, s, a, sc, dst);
