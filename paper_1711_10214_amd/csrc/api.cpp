@@ -507,8 +507,8 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
       vm.push_back(VecItem{gi, 0, gh.m_off + s0, std::min(kVecChunk, gh.nm() - s0)});
     G.mit_hi = (int)vm.size();
     G.dit_lo = (int)vd.size();
-    for (long long s0 = 0; s0 < gh.nd(); s0 += kVecChunk)
-      vd.push_back(VecItem{gi, 0, gh.d_off + s0, std::min(kVecChunk, gh.nd() - s0)});
+    for (long long s0 = 0; s0 < gh.nd(); s0 += kDataVecChunk)
+      vd.push_back(VecItem{gi, 0, gh.d_off + s0, std::min(kDataVecChunk, gh.nd() - s0)});
     G.dit_hi = (int)vd.size();
   }
   // LDS bytes of each kernel family for one gather

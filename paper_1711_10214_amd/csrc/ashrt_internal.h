@@ -29,6 +29,7 @@ constexpr int kXfftBatch = 2048;       // complex points per compile-time x-FFT 
 constexpr int kXfftGenericBatch = 4096;  // complex points per generic x-FFT call (nxp <= 4096)
 constexpr int kMaxSlots = (kRowMaxN / 2 + kThreads - 1) / kThreads;  // per-thread bins
 constexpr long long kVecChunk = 8192;  // elements per vector-kernel work item
+constexpr long long kDataVecChunk = 2048;  // the same for data vectors (a gather's data is P times smaller)
 constexpr int kSelBins = 2048;         // radix-select histogram bins (11 bits)
 
 // One gather's geometry and its offsets into packed buffers.

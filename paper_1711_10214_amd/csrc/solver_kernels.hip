@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_part(RedArgs A) {
       } else {
         bool live = true;
         if (tm) {
-          const long long x = (o - G.d_off) / G.nt;
+          const unsigned x = (unsigned)(o - G.d_off) / (unsigned)G.nt;  // nx nt < 2^31
           live = tm[x] != 0;
         }
         if (!live) continue;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void k_elementwise(EwArgs A) {
         case EW_WR_INIT:
         case EW_WR_UPDATE:
         case EW_WR_MASK: {
-          const bool live = tm ? (tm[(o - G.d_off) / G.nt] != 0) : true;
+          const bool live = tm ? (tm[(unsigned)(o - G.d_off) / (unsigned)G.nt] != 0) : true;
           float v = 0.f;
           if (live) {
             if (A.op == EW_WR_INIT) v = A.x ? A.x[o] : 1.0f;
@@ -266,10 +266,9 @@ __device__ __forceinline__ float key_float(unsigned k) {
 }
 
 
-// kSelSplit workgroups per vector item (a gather's residual has only
-// nx nt / 8192 items); each thread issues the loads of four samples before
-// it bins them.
-constexpr int kSelSplit = 4;
+// kSelSplit workgroups per data-vector item; each thread issues the loads
+// of four samples before it bins them.
+constexpr int kSelSplit = 2;
 __global__ __launch_bounds__(kThreads) void k_sel_hist(SelArgs A) {
   __shared__ unsigned h[2][kSelBins];
   for (int b = blockIdx.x; b < A.nitems * kSelSplit; b += gridDim.x) {
