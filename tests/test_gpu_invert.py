@@ -73,10 +73,12 @@ def test_small_crg_solve_matches_oracle(A, pq):
         np.testing.assert_allclose(rep["eps_m"][1:], rep_r["eps_m"], rtol=1e-4)
 
 
-@pytest.mark.parametrize("nt_nx_inner", [(203, 37, 5), (256, 64, 1), (256, 64, 2)])
+@pytest.mark.parametrize("nt_nx_inner", [(203, 37, 5), (250, 40, 4), (256, 64, 1), (256, 64, 2)])
 def test_solve_edge_shapes_match_oracle(A, nt_nx_inner):
-    """Odd nt (the element-pair tails of the fused CG update) and one or two
-    CG iterations per outer step (no fused update / one, no graph), q = 1."""
+    """Odd nt (the element-pair tails of the fused CG update), even nt with a
+    ragged last model tile (250 = 3 x 64 + 58: full tiles take the batched
+    loads, the last one the per-element path) and one or two CG iterations
+    per outer step (no fused update / one, no graph), q = 1."""
     nt, nx, n_inner = nt_nx_inner
     w = workload("crg-256x64-nv8", nt=nt, nx=nx)
     gth = make_gather(w)
