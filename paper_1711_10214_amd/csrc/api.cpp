@@ -958,10 +958,11 @@ struct CgStep {
 };
 
 // m_out = wmul * L' (mask * mul_d * d); part: per-tile sums of m_out^2,
-// with sc also summed per gather into sc[SC_GNEW]
+// with sc also summed per gather into sc[SC_GNEW].  wmul_sq: m_out gets
+// wmul^2 * L'(...) and the partials sum (wmul * L'(...))^2.
 hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const uint8_t* tmask, float* m_out,
                        const float* wmul, double* part = nullptr, const CgStep* cg = nullptr,
-                       double* sc = nullptr) {
+                       double* sc = nullptr, bool wmul_sq = false) {
   const PlanImpl& P = *c.P;
   hipError_t e = hipSuccess;
   for (const auto& sg : P.s_xd) {
@@ -1002,6 +1003,7 @@ hipError_t run_adjoint(const Ctx& c, const float* d, const float* mul_d, const u
     ia.src = c.X();
     ia.out = m_out;
     ia.wmul = wmul;
+    ia.wmul_sq = wmul_sq ? 1 : 0;
     ia.tw = P.d_tw;
     ia.panels = P.d_pan;
     ia.part = part;
@@ -1169,12 +1171,15 @@ struct Solver {
     if (e_ != hipSuccess) return fail(ASHRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// One CG iteration on A = W_r S L W_m^-1, all on S.c.s:
-//   q = A pdir (per-tile partials of |q|^2); alpha = gamma / |q|^2;
-//   s -= alpha q; g = A' s (partials of |g|^2).  Its vector update (beta,
-//   u += alpha pdir, pdir = g + beta pdir) runs inside the next iteration's
-//   model transform (fused: this iteration applies the previous one's), or
-//   as k_cg after the last iteration.  par selects the gamma slot pair.
+// One CG iteration on A = W_r S L W_m^-1, all on S.c.s, with its vectors
+// kept in model space (u = m, pdir and g scaled by W_m^-1, so the forward
+// needs no weight; the q = 2 case has W_m = 1):
+//   q = W_r S L pdir (per-tile partials of |q|^2); alpha = gamma / |q|^2;
+//   s -= alpha q; g = W_m^-2 L' S W_r s, gamma = |W_m^-1 L' S W_r s|^2.  Its
+//   vector update (beta, m += alpha pdir, pdir = g + beta pdir) runs inside
+//   the next iteration's model transform (fused: this iteration applies the
+//   previous one's), or as k_cg after the last iteration.  par selects the
+//   gamma slot pair.
 hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fused) {
   CgUpd up;
   up.u = S.u;
@@ -1183,7 +1188,7 @@ hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fuse
   up.part_gamma = S.pgam;
   up.sc = S.sc;
   up.par = par ^ 1;
-  hipError_t e = run_forward(S.c, S.pdir, S.Wminv, S.q, nullptr, S.Wr, nullptr, mask, S.pdel,
+  hipError_t e = run_forward(S.c, S.pdir, nullptr, S.q, nullptr, S.Wr, nullptr, mask, S.pdel,
                              fused ? &up : nullptr, S.sc);
   if (e != hipSuccess) return e;
   CgStep st;
@@ -1192,7 +1197,7 @@ hipError_t cg_iteration(const Solver& S, const uint8_t* mask, int par, bool fuse
   st.part_delta = S.pdel;
   st.sc = S.sc;
   st.par = par;
-  return run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st, S.sc);
+  return run_adjoint(S.c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, &st, S.sc, S.Wminv != nullptr);
 }
 
 constexpr size_t kMaxCgGraphs = 8;
@@ -1255,8 +1260,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
   unsigned char* W = c.ws;
   Solver S{c, P, *prm,
            (float*)(W + L.r), (float*)(W + L.s), (float*)(W + L.q), (float*)(W + L.Wr),
-           (float*)(W + L.pdir), (float*)(W + L.g),
-           prm->q == 1 ? (float*)(W + L.u) : m,
+           (float*)(W + L.pdir), (float*)(W + L.g), m,
            prm->q == 1 ? (float*)(W + L.Wminv) : nullptr,
            (double*)(W + L.part), (double*)(W + L.pdel), (double*)(W + L.pgam), (double*)(W + L.sc), (SelState*)(W + L.sel), (unsigned*)(W + L.hist),
            (RepDev*)(W + L.rep)};
@@ -1292,10 +1296,6 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
         f.y = S.Wminv;
         f.value = 1.0f;
         E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(f, s); }));
-        EwArgs cp = S.ew(EW_COPY, true);
-        cp.y = S.u;
-        cp.x = m;
-        E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(cp, s); }));
       }
     } else {
       EwArgs a = S.ew(p1 ? EW_WR_UPDATE : EW_WR_MASK, false);
@@ -1307,15 +1307,18 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       if (q1) {
         E_TRY(S.reduce(RED_ABSMAX, true, m, nullptr, SC_MMAX, -1, true, nullptr, 0));
         E_TRY(S.scalar(ST_EPS_M, k));
+        // W_m^-1 from m (its z_out = W_m m is not needed: pdir, overwritten
+        // by the CG initialisation below, takes it)
         EwArgs w = S.ew(EW_WM_UPDATE, true);
         w.y = S.Wminv;
         w.x = m;
-        w.z_out = S.u;
+        w.z_out = S.pdir;
         w.coef = SC_EPS_M;
         E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(w, s); }));
       }
     }
-    // CGLS on A = W_r S L W_m^-1 from u = W_m m:  s = W_r r ; g = A' s ; pdir = g
+    // CGLS on A = W_r S L W_m^-1 from u = W_m m (in model space, see
+    // cg_iteration):  s = W_r r ; g = W_m^-2 L' S s ; pdir = g
     {
       EwArgs a = S.ew(EW_MUL, false);
       a.y = S.s;
@@ -1323,7 +1326,7 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       a.z = S.r;
       E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
     }
-    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, nullptr, S.sc));
+    E_TRY(run_adjoint(c, S.s, S.Wr, mask, S.g, S.Wminv, S.pgam, nullptr, S.sc, q1));
     E_TRY(S.cg(1, 0));
     if (prm->n_inner > 0) {
       // iteration 0 starts from pdir = g; iterations 1.. apply their
@@ -1336,13 +1339,6 @@ int invert_impl(const PlanImpl& P, const irls_params* prm, const float* d, const
       E_TRY(S.cg(0, (prm->n_inner - 1) & 1));
     }
     E_TRY(S.scalar(ST_REPORT_INNER, k));
-    if (q1) {
-      EwArgs a = S.ew(EW_MUL, true);
-      a.y = m;
-      a.x = S.Wminv;
-      a.z = S.u;
-      E_TRY(timed(ASHRT_K_VECTOR, s, [&] { return launch_elementwise(a, s); }));
-    }
     // residual, separated gather, clip and misfit
     E_TRY(run_forward(c, m, nullptr, S.r, d, nullptr, d_rec, mask));
     if (p1) {

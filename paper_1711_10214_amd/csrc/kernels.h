@@ -50,11 +50,12 @@ struct XinvArgs {
   float* out;             // result (after the epilogue)
   const float* sub;       // data: out = sub - y (residual) when set
   const float* wmul;      // out *= wmul (element-wise) when set
+  int wmul_sq;            // with wmul: out = y wmul^2, and part sums (y wmul)^2
   float* raw_out;         // data: y before the epilogue when set
   const uint8_t* tmask;   // data: out *= mask
   const float2* tw;
   const PanelDev* panels; // live-row counts of the model panels
-  double* part;           // per work item: sum of out^2 (or NULL)
+  double* part;           // per work item: sum of out^2 (or of (y wmul)^2, see wmul_sq)
   int item_base;          // index of items[0] in the plan's full list
 };
 

@@ -739,6 +739,7 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
       // kXLoadBatch loop iterations are issued together (indices past the
       // tile clamped)
       const float* __restrict__ wm = A.wmul ? A.wmul + fbase : nullptr;
+      const bool wsq = A.wmul && A.wmul_sq;
       const float* __restrict__ sb = A.sub ? A.sub + fbase : nullptr;
       float* __restrict__ raw = A.raw_out ? A.raw_out + fbase : nullptr;
       float* __restrict__ out = A.out + fbase;
@@ -776,8 +777,9 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
             if (sb) v = make_float2(sv[u].x - v.x, sv[u].y - v.y);
             if (live[u] == 0) v = make_float2(0.f, 0.f);
             if (wm) v = make_float2(v.x * wv[u].x, v.y * wv[u].y);
-            at_byte<float2>(out, off[u]) = v;
             ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            if (wsq) v = make_float2(v.x * wv[u].x, v.y * wv[u].y);
+            at_byte<float2>(out, off[u]) = v;
           }
         }
       }
@@ -802,9 +804,12 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
         if (A.wmul) {
           const float2 wv = *reinterpret_cast<const float2*>(A.wmul + o);
           v = make_float2(v.x * wv.x, v.y * wv.y);
+          ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          if (A.wmul_sq) v = make_float2(v.x * wv.x, v.y * wv.y);
+        } else {
+          ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
         *reinterpret_cast<float2*>(A.out + o) = v;
-        ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
       } else {
         for (int c = 0; c < 2 && t + c < nt; ++c) {
           float v = (c ? z.y : z.x) * inv;
@@ -812,8 +817,9 @@ __global__ __launch_bounds__(kThreads) void k_xfft_inv(XinvArgs A) {
           if (A.sub) v = A.sub[o + c] - v;
           if (!live) v = 0.f;
           if (A.wmul) v *= A.wmul[o + c];
-          A.out[o + c] = v;
           ss += (double)v * (double)v;
+          if (A.wmul && A.wmul_sq) v *= A.wmul[o + c];
+          A.out[o + c] = v;
         }
       }
     }
