@@ -38,14 +38,14 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # only for the kernel sources with this digest.
 _MIB = 1024.0 * 1024.0
 MEASURED_TRAFFIC = {
-    "digest": "dc4989267cafa4d9",
+    "digest": "58434cb17159bd17",
     "workload": "crg-1024x256-nv32",
     "bytes": {
         # nchunk -> read + write
-        "k_rows_fwd": {1: (56.14 + 3.20) * _MIB, 2: (56.18 + 6.41) * _MIB, 4: (56.25 + 12.81) * _MIB,
-                       8: (56.42 + 25.59) * _MIB},
-        "k_rows_adj": {1: (2.27 + 55.92) * _MIB, 2: (4.30 + 55.92) * _MIB, 4: (8.36 + 55.92) * _MIB,
-                       8: (16.52 + 55.92) * _MIB},
+        "k_rows_fwd": {1: (56.16 + 3.20) * _MIB, 2: (56.19 + 6.41) * _MIB, 4: (56.26 + 12.81) * _MIB,
+                       8: (56.43 + 25.59) * _MIB},
+        "k_rows_adj": {1: (2.28 + 55.92) * _MIB, 2: (4.31 + 55.92) * _MIB, 4: (8.37 + 55.92) * _MIB,
+                       8: (16.53 + 55.92) * _MIB},
     },
 }
 _KERNEL_SOURCES = ["ashrt_internal.h", "block_reduce.h", "fft_lds.h", "fft_tpl.h", "kernels.h", "op_kernels.hip"]
