@@ -70,7 +70,7 @@ def _measured_traffic(workload, kernel, nchunk):
 def _geometry_numbers(plan, nx, nt, P, R, cg_frac=0.0):
     """Algorithmic bytes and flops per launch of each kernel family.  cg_frac:
     the fraction of model-transform launches that also apply the previous CG
-    iteration's update (read u, g; write u, pdir: four more model streams)."""
+    iteration's update (read m, g; write m, pdir: four more model streams)."""
     import numpy as np
     info = plan.info
     ntp, nxp, jlo, jhi, nchunk = info["ntp"], info["nxp"], info["jlo"], info["jhi"], info["nchunk"]
