@@ -57,15 +57,19 @@ def test_batched_operator_matches_oracle(A):
         assert e_f <= 1e-5 and e_a <= 1e-5
 
 
-def test_batched_solve_matches_oracle(A):
-    print("[gpu] batched robust_invert, 3 uneven gathers vs oracle", flush=True)
+@pytest.mark.parametrize("pq", [(1, 2), (2, 1)])
+def test_batched_solve_matches_oracle(A, pq):
+    """Three uneven gathers in one batch; (2, 1) also runs the model weights
+    W_m^-1 of every packed gather."""
+    p, q = pq
+    print(f"[gpu] batched robust_invert p={p} q={q}, 3 uneven gathers vs oracle", flush=True)
     w = workload("crg-256x64-nv8")
     shapes = [(256, 64, 1), (192, 50, 11), (160, 72, 12)]
     gths = [make_gather(w, seed=s, nt=nt, nx=nx) for nt, nx, s in shapes]
     kws = [geom_kwargs(nt, nx, w.dt, w.dx, list(w.vel), fmax=w.fmax) for nt, nx, _ in shapes]
     plan = A.BatchPlan(kws)
-    prm = IrlsParams(p=1, q=2, n_outer=3, n_inner=6)
-    P = A.Params(p=1, q=2, n_outer=3, n_inner=6)
+    prm = IrlsParams(p=p, q=q, n_outer=3, n_inner=6)
+    P = A.Params(p=p, q=q, n_outer=3, n_inner=6)
     d = plan.pack_data([f32(g.d_blend) for g in gths])
     _, drec, reps = plan.robust_invert(d, P)
     for i, (g, kw) in enumerate(zip(gths, kws)):
