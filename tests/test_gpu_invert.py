@@ -239,14 +239,21 @@ def test_cg_graph_replays_match_eager_launches(A, pq_inner):
         assert rep_e["inner"] == rep_g["inner"]
 
 
-def test_irregular_traces_solve_matches_oracle(A):
+@pytest.mark.parametrize("pq_missing", [(1, 2, 0.0), (2, 1, 0.4)])
+def test_irregular_traces_solve_matches_oracle(A, pq_missing):
     """Robust solve on a gather whose traces sit at jittered positions (the
-    data-side x transforms are non-uniform DFTs)."""
+    data-side x transforms are non-uniform DFTs); the second case also drops
+    40 % of the traces and weights the model (interpolation of irregular,
+    incomplete data)."""
+    p, q, missing = pq_missing
     w, gth, kw = _cfg1()
     kw = dict(kw, xpos=list(np.arange(gth.nx) * w.dx + np.random.default_rng(12).uniform(-4, 4, gth.nx)))
-    prm = IrlsParams(p=1, q=2, n_outer=3, n_inner=6)
-    print("[gpu] invert parity irregular traces", flush=True)
-    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm)
+    prm = IrlsParams(p=p, q=q, n_outer=3, n_inner=6)
+    mask = None
+    if missing > 0:
+        mask = (np.random.default_rng(13).uniform(size=gth.nx) >= missing).astype(np.uint8)
+    print(f"[gpu] invert parity irregular traces p={p} q={q} missing={missing}", flush=True)
+    m_g, d_g, rep, m_r, d_r, rep_r = _solve_both(A, kw, f32(gth.d_blend), prm, mask=mask)
     e = rel_l2(d_g, d_r)
     print(f"  d_rec rel-L2 {e:.2e}", flush=True)
     assert e <= 1e-4
