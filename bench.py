@@ -391,6 +391,87 @@ def run_warmstart(args):
     print(json.dumps(rec), flush=True)
 
 
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
+
+
+def _unet_conv_flops(H, W, base=16, cin=1):
+    """Algorithmic FLOPs of the U-Net's fourteen 3x3 convolutions for one
+    sample at H x W (2 * 9 * ci * co per output pixel): forward, input
+    gradient (every layer but the first, whose input is the data) and weight
+    gradient.  Same layer list as the library's graph (four levels, two
+    convolutions each, skip concatenations on the decoder side)."""
+    c1, c2, c3, c4 = base, 2 * base, 4 * base, 8 * base
+    spec = [(cin, c1, 0), (c1, c1, 0), (c1, c2, 1), (c2, c2, 1), (c2, c3, 2), (c3, c3, 2), (c3, c4, 3),
+            (c4, c4, 3), (c4 + c3, c3, 2), (c3, c3, 2), (c3 + c2, c2, 1), (c2, c2, 1), (c2 + c1, c1, 0),
+            (c1, c1, 0)]
+    fwd = igrad = 0
+    for i, (ci, co, lev) in enumerate(spec):
+        f = 2 * 9 * ci * co * (H >> lev) * (W >> lev)
+        fwd += f
+        if i > 0:
+            igrad += f
+    return fwd, igrad, fwd
+
+
+def run_unet(args):
+    """Training steps (forward, backward, AdamW) and inference of the
+    warm-start U-Net at the production gather's shape, against the dense BF16
+    matrix-core peak."""
+    import torch
+    import paper_1711_10214_amd as A
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    dev = torch.device("cuda", 0)
+    B, H, W, P = args.batch, 256, 1024, 32
+    net = A.UNet(P, base=16)
+    net.init_params(seed=0)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = torch.randn((B, H, W), generator=g).to(dev)
+    t_m = (0.1 * torch.randn((B, P, H, W), generator=g)).to(dev)
+    t_w = torch.rand((B, H, W), generator=g).to(dev)
+    tp = A.TrainParams(lr=1e-4)
+    for _ in range(max(args.warmup, 1)):
+        net.train_step(x, t_m, t_w, tp, want_loss=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        net.train_step(x, t_m, t_w, tp, want_loss=False)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_s = e0.elapsed_time(e1) / 1e3 / args.steps
+    x1 = x[:1].contiguous()
+    for _ in range(3):
+        net.forward(x1)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        net.forward(x1)
+    e1.record()
+    torch.cuda.synchronize()
+    inf_s = e0.elapsed_time(e1) / 1e3 / args.steps
+    fwd, igrad, wgrad = _unet_conv_flops(H, W)
+    step_flops = B * (fwd + igrad + wgrad)
+    achieved = step_flops / step_s / 1e12
+    rec = {
+        "metric": "warm-start U-Net training steps/s (batch 4, 256 x 1024 gathers, 32 output panels)",
+        "value": args.steps / wall, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": "unet-train-b4-256x1024-p32", "batch": B, "height": H, "width": W,
+                   "out_panels": P, "params": net.n_params},
+        "inference_ms_per_gather": inf_s * 1e3,
+        "inference_tflops": fwd / inf_s / 1e12,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "whole training step: algorithmic FLOPs of the 3x3 convolutions "
+                               "(forward, input and weight gradients) / step time",
+                     "algorithmic_flops_per_step": step_flops},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,7 +485,7 @@ def main():
     ap.add_argument("--train-gathers", type=int, default=1024, help="warm-start workload: training gathers")
     ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
     ap.add_argument("--epochs", type=int, default=12, help="warm-start workload: training epochs")
-    ap.add_argument("--batch", type=int, default=4, help="warm-start workload: batch size")
+    ap.add_argument("--batch", type=int, default=4, help="warm-start and unet workloads: batch size")
     ap.add_argument("--batch-gathers", type=int, default=512, help="batched workload: number of gathers")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling rule")
     ap.add_argument("--survey-sources", type=int, default=128, help="survey workload: sources (= receivers)")
@@ -424,6 +505,8 @@ def main():
         return run_speedratio(args)
     if args.workload == "survey":
         return run_survey(args)
+    if args.workload == "unet":
+        return run_unet(args)
 
     import numpy as np
     import torch

@@ -54,7 +54,7 @@ int fail(int code, const std::string& m) { return ashrt::set_error(code, m); }
   } while (0)
 
 constexpr int kNConv = 14;
-constexpr int kBiasBlocks = 256;
+constexpr int kBiasBlocks = 1024;
 constexpr int kWgradTargetGroups = 1024;
 
 ConvPack make_pack(int Cin, int Cout) {

@@ -328,15 +328,40 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 
 // Sum the pixel-split partials into the canonical weight gradient
 // [Cout][Cin][3][3] (fixed order over the splits).
+// grad[co][ci][kk] = sum over the pixel splits of the partials.  A
+// workgroup takes E gradient elements and 256 / E thread groups
+// over the splits (split sp -> group sp mod G); the G partial sums of an
+// element are added in group order, so the result does not depend on timing.
+template <int E>
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nsplit, int Cout, int Cin,
                                                      int Cipw, float* __restrict__ grad) {
+  constexpr int G = 256 / E;
+  __shared__ float s[G][E + 1];
+  const int te = (int)threadIdx.x % E, g = (int)threadIdx.x / E;
   const int n = Cout * Cin * 9;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int co = i / (Cin * 9), r = i - co * Cin * 9;
-    const int ci = r / 9, kk = r - ci * 9;
-    float s = 0.f;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[(((long long)sp * Cout + co) * 9 + kk) * Cipw + ci];
-    grad[i] = s;
+  // elements enumerated in the partials' order (co, kk, ci), ci fastest, so
+  // neighbouring threads read neighbouring floats
+  for (int j0 = blockIdx.x * E; j0 < n; j0 += gridDim.x * E) {
+    const int j = j0 + te;
+    float acc = 0.f;
+    int co = 0, kk = 0, ci = 0;
+    if (j < n) {
+      co = j / (9 * Cin);
+      const int r = j - co * 9 * Cin;
+      kk = r / Cin;
+      ci = r - kk * Cin;
+      const long long stride = (long long)Cout * 9 * Cipw;
+      const float* p = part + ((long long)co * 9 + kk) * Cipw + ci;
+      for (int sp = g; sp < nsplit; sp += G) acc += p[sp * stride];
+    }
+    s[g][te] = acc;
+    __syncthreads();
+    if (g == 0 && j < n) {
+      float t = 0.f;
+      for (int q = 0; q < G; ++q) t += s[q][te];
+      grad[((long long)co * Cin + ci) * 9 + kk] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -347,11 +372,21 @@ __global__ __launch_bounds__(256) void k_bias_part(BiasArgs a) {
   __shared__ float s[256];
   const int C = a.C, tid = (int)threadIdx.x, c = tid % C, q = tid / C, Q = 256 / C;
   float sum = 0.f;
-  for (long long p = (long long)blockIdx.x * Q + q; p < a.npix; p += (long long)gridDim.x * Q) {
-    const long long o = p * C + c;
-    float g = a.gY[o];
-    if (a.Y && !relu_on(a.Y[o])) g = 0.f;
-    sum += g;
+  // four pixels' loads in flight per thread (indices past the end clamped
+  // for the loads, skipped in the sum, which keeps the pixel order)
+  const long long stride = (long long)gridDim.x * Q;
+  for (long long p0 = (long long)blockIdx.x * Q + q; p0 < a.npix; p0 += 4 * stride) {
+    float g[4];
+    uint16_t y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long o = min(p0 + u * stride, a.npix - 1) * C + c;
+      g[u] = a.gY[o];
+      y[u] = a.Y ? a.Y[o] : (uint16_t)0x3f80u;  // 1.0 when there is no ReLU mask
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (p0 + u * stride < a.npix) sum += relu_on(y[u]) ? g[u] : 0.f;
   }
   s[tid] = sum;
   __syncthreads();
@@ -362,12 +397,39 @@ __global__ __launch_bounds__(256) void k_bias_part(BiasArgs a) {
   }
 }
 
+// out[e] = sum over k of part[k ne + e]: E consecutive elements per
+// workgroup and 256 / E thread groups over k (k -> group k mod G), the
+// groups' sums added in group order (deterministic).
+template <int E>
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nblk, int ne,
                                                   float* __restrict__ out) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int k = 0; k < nblk; ++k) s += part[(long long)k * ne + e];
-    out[e] = s;
+  constexpr int G = 256 / E;
+  __shared__ float s[G][E + 1];
+  const int te = (int)threadIdx.x % E, g = (int)threadIdx.x / E;
+  for (int e0 = blockIdx.x * E; e0 < ne; e0 += gridDim.x * E) {
+    const int e = e0 + te;
+    float acc = 0.f;
+    if (e < ne)
+      for (int k = g; k < nblk; k += G) acc += part[(long long)k * ne + e];
+    s[g][te] = acc;
+    __syncthreads();
+    if (g == 0 && e < ne) {
+      float t = 0.f;
+      for (int q = 0; q < G; ++q) t += s[q][te];
+      out[e] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// launch: wide element ranges take 16 elements per workgroup, narrow ones 4
+// (more thread groups over k)
+static void sum_parts(const float* part, int nblk, int ne, float* out, hipStream_t s) {
+  if (ne >= 16 * 256) {
+    const long long g = (ne + 15) / 16;
+    hipLaunchKernelGGL(k_sum_parts<16>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, part, nblk, ne, out);
+  } else {
+    hipLaunchKernelGGL(k_sum_parts<4>, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s, part, nblk, ne, out);
   }
 }
 
@@ -618,14 +680,21 @@ hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
 
 hipError_t launch_wgrad_reduce(const float* part, int nsplit, int Cout, int Cin, int Cipw, float* grad,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_for((long long)Cout * Cin * 9)), dim3(256), 0, s, part, nsplit, Cout,
-                     Cin, Cipw, grad);
+  const long long n = (long long)Cout * Cin * 9;
+  if (n >= 16 * 256) {
+    const long long g = (n + 15) / 16;
+    hipLaunchKernelGGL(k_wgrad_reduce<16>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, part, nsplit,
+                       Cout, Cin, Cipw, grad);
+  } else {
+    hipLaunchKernelGGL(k_wgrad_reduce<4>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, part, nsplit, Cout, Cin,
+                       Cipw, grad);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_bias(const BiasArgs& a, int nblk, float* gb, hipStream_t s) {
   hipLaunchKernelGGL(k_bias_part, dim3(nblk), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const float*)a.part, nblk, a.C, gb);
+  sum_parts((const float*)a.part, nblk, a.C, gb, s);
   return hipGetLastError();
 }
 
@@ -649,7 +718,7 @@ hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s) {
   const long long npix = (long long)a.hd.B * a.hd.H * a.hd.W;
   hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), head_bwd_lds(a.hd.P, a.hd.C1), s, a);
-  hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(a.ne)), dim3(256), 0, s, (const float*)a.hpart, nblk, a.ne, ghead);
+  sum_parts((const float*)a.hpart, nblk, a.ne, ghead, s);
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, (const double*)a.lpart, nblk,
                      (double)npix * a.hd.P, (double)npix, lam_w, loss);
   return hipGetLastError();
