@@ -82,10 +82,11 @@ def test_batched_operator_with_irregular_gather_matches_oracle(A):
         assert e_f <= 1e-5 and e_a <= 1e-5
 
 
-@pytest.mark.parametrize("pq", [(1, 2), (2, 1)])
+@pytest.mark.parametrize("pq", [(1, 2), (2, 1), (1, 1)])
 def test_batched_solve_matches_oracle(A, pq):
     """Three uneven gathers in one batch; (2, 1) also runs the model weights
-    W_m^-1 of every packed gather."""
+    W_m^-1 of every packed gather, and (1, 1) adds trace masks (a quarter of
+    the second gather's traces and a third of the third's missing)."""
     p, q = pq
     print(f"[gpu] batched robust_invert p={p} q={q}, 3 uneven gathers vs oracle", flush=True)
     w = workload("crg-256x64-nv8")
@@ -96,9 +97,15 @@ def test_batched_solve_matches_oracle(A, pq):
     prm = IrlsParams(p=p, q=q, n_outer=3, n_inner=6)
     P = A.Params(p=p, q=q, n_outer=3, n_inner=6)
     d = plan.pack_data([f32(g.d_blend) for g in gths])
-    _, drec, reps = plan.robust_invert(d, P)
+    masks = [None, None, None]
+    if pq == (1, 1):
+        rng = np.random.default_rng(31)
+        masks = [None, (rng.uniform(size=shapes[1][1]) >= 0.25).astype(np.uint8),
+                 (rng.uniform(size=shapes[2][1]) >= 0.33).astype(np.uint8)]
+    mk = plan.pack_mask(masks) if any(m is not None for m in masks) else None
+    _, drec, reps = plan.robust_invert(d, P, mask_packed=mk)
     for i, (g, kw) in enumerate(zip(gths, kws)):
-        _, d_ref, rep_ref = oracle.robust_invert(oracle_geometry(kw), f32(g.d_blend), prm)
+        _, d_ref, rep_ref = oracle.robust_invert(oracle_geometry(kw), f32(g.d_blend), prm, mask=masks[i])
         e = rel_l2(plan.unpack_data(drec, i).cpu().numpy(), d_ref)
         print(f"  gather {i} {shapes[i][:2]}: d_rec rel-L2 {e:.2e}", flush=True)
         assert e <= 1e-4
