@@ -225,3 +225,201 @@ def test_l1_misfit_beats_l2_on_blended_small_gather():
         out[p] = oracle.q_db(gth.d_clean, drec)
     assert out[1] > out[2]
     assert out[1] > q_pd
+
+
+# --------------------------------------------------------------------------
+# Pins of the model-weight branch (q = 1) and of the initial weight w0.
+#
+# Chapter 4's reweighted system: CG on A = W_r S L W_m^-1 in u = W_m m,
+# with eps_m = b_m max|m| / 100 and W_m = max(|m|, eps_m)^((q-2)/2).  Run to
+# convergence, CGLS from a start u0 returns u0 + A^+ (b - A u0), so each
+# outer step has a closed form that fixes where every weight goes:
+#
+# * underdetermined, consistent L (more model than data samples): the data
+#   are fitted exactly and the step is the smallest change of m in the
+#   W_m-norm,  m_k = m_{k-1} + D L'(L D L')^-1 (d - L m_{k-1}),
+#   D = W_m^-2 = diag(max(|m_{k-1}|, eps_m)) for q = 1 -- independent of W_r;
+# * overdetermined, full column rank L: m_k is the weighted least-squares
+#   solution argmin |W_r S (d - L m)|, whatever W_m is (a change of
+#   variables does not move the minimiser).
+#
+# Each mistake in the branch changes one of these: eps_m taken from u = W_m m
+# instead of m, a wrong divisor, W_m and W_m^-1 swapped, a start other than
+# u0 = W_m m, a residual weight other than w0 in outer iteration 1.
+
+
+def _explicit_ops(L):
+    # data laid out as nd traces of one sample, so the trace mask selects samples
+    return (lambda u: (L @ np.ravel(u)).reshape(-1, 1)), (lambda r: L.T @ np.ravel(r))
+
+
+def _run_explicit(L, d, prm, m0=None, w0=None, mask=None):
+    Lop, LTop = _explicit_ops(L)
+    return I.robust_invert(None, d.reshape(-1, 1), prm, m0=m0,
+                           w0=None if w0 is None else w0.reshape(-1, 1),
+                           mask=mask, Lop=Lop, LTop=LTop)
+
+
+def test_eps_m_hand_example():
+    # L = identity: one CG step from m0 = 0 reproduces d exactly (alpha = 1),
+    # so outer iteration 2 sees m = d and eps_m = b_m * max|d| / 100 by hand
+    d = np.array([3.0, -200.0, 0.5, 1.0])
+    for b_m, want in ((1.0, 2.0), (3.0, 6.0)):
+        prm = I.IrlsParams(p=2, q=1, n_outer=2, n_inner=1, b_m=b_m)
+        m, _, rep = _run_explicit(np.eye(4), d, prm)
+        assert rep["eps_m"] == [pytest.approx(want, rel=1e-15)]
+        np.testing.assert_allclose(m, d, rtol=1e-15)   # zero residual: no further step
+
+
+def _underdetermined(seed, nd=12, nm=30, rank=None):
+    rng = np.random.default_rng(seed)
+    if rank is None:
+        L = rng.standard_normal((nd, nm))
+    else:   # rank-deficient: no exact fit, and a null space in model space
+        L = rng.standard_normal((nd, rank)) @ rng.standard_normal((rank, nm)) / np.sqrt(rank)
+    d = rng.standard_normal(nd)
+    d[3] += 25.0                                   # an outlier sample (p = 1 reweights it)
+    m0 = rng.standard_normal(nm) * 0.3
+    return L, d, m0
+
+
+@pytest.mark.parametrize("b_m", [1.0, 10.0])
+def test_q1_converged_steps_are_weighted_pseudo_inverse_steps(b_m):
+    # rank-deficient L: every outer step leaves a residual (so the weights of
+    # the next one act) and keeps the start's null-space component, so the
+    # converged step m_k = m_{k-1} + W_m^-1 (W_r S L W_m^-1)^+ W_r S r_{k-1}
+    # depends on eps_r, eps_m, the placement of both weights and u0 = W_m m
+    rank = 8
+    L, d, m0 = _underdetermined(21, nd=14, nm=30, rank=rank)
+    nd, nm = L.shape
+    live = np.ones(nd, bool)
+    live[[6, 11]] = False
+    S = live.astype(float)
+    n_outer = 4
+    prm = I.IrlsParams(p=1, q=1, n_outer=n_outer, n_inner=4 * rank, b_m=b_m)
+    ms = [_run_explicit(L, d, I.IrlsParams(**{**prm.__dict__, "n_outer": k}), m0=m0,
+                        mask=live.astype(np.uint8))[0].ravel()
+          for k in range(1, n_outer + 1)]
+    dmax = np.max(np.abs(d[live]))
+    ref, alt = [m0], [m0]
+    clipped = 0
+    for k in range(1, n_outer + 1):
+        for seq, weighted in ((ref, True), (alt, False)):
+            mp = seq[-1]
+            r = S * (d - L @ mp)
+            if k == 1:
+                wr, wm = S.copy(), np.ones(nm)
+            else:
+                rl = r[live]
+                e = max(prm.b_r * np.median(np.abs(rl - np.median(rl))) / 0.6745,
+                        prm.eps_floor_rel * dmax)
+                wr = S / np.sqrt(np.maximum(np.abs(r), e))
+                em = b_m * np.max(np.abs(mp)) / 100.0
+                wm = 1.0 / np.sqrt(np.maximum(np.abs(mp), em)) if weighted else np.ones(nm)
+                if weighted:
+                    clipped += int(np.sum(np.abs(mp) < em))
+            A = wr[:, None] * L / wm[None, :]
+            seq.append(mp + (np.linalg.pinv(A, rcond=1e-10) @ (wr * r)) / wm)
+    for k in range(n_outer):
+        np.testing.assert_allclose(ms[k], ref[k + 1], rtol=1e-7, atol=1e-9)
+    if b_m > 1.0:
+        assert clipped > 0        # the clip eps_m took part
+    # the model weights matter here: the same steps with W_m = 1 end elsewhere
+    assert np.linalg.norm(ms[-1] - alt[-1]) > 1e-3 * np.linalg.norm(alt[-1])
+
+
+def test_q1_eps_m_follows_the_model_not_u():
+    # the stored eps_m of outer iteration k is b_m max|m_{k-1}| / 100 with
+    # m_{k-1} the model the oracle returned after k-1 iterations
+    L, d, m0 = _underdetermined(22)
+    b_m = 4.0
+    prm = I.IrlsParams(p=1, q=1, n_outer=4, n_inner=5, b_m=b_m)
+    _, _, rep = _run_explicit(L, d, prm, m0=m0)
+    for k in range(2, 5):
+        mk, _, _ = _run_explicit(L, d, I.IrlsParams(**{**prm.__dict__, "n_outer": k - 1}), m0=m0)
+        assert rep["eps_m"][k - 2] == pytest.approx(b_m * np.max(np.abs(mk)) / 100.0, rel=1e-13)
+
+
+def _overdetermined(seed, nd=40, nm=10):
+    rng = np.random.default_rng(seed)
+    L = rng.standard_normal((nd, nm))
+    d = L @ rng.standard_normal(nm) + 0.05 * rng.standard_normal(nd)
+    idx = rng.choice(nd, 6, replace=False)
+    d[idx] += rng.choice([-1, 1], 6) * rng.uniform(5, 20, 6)
+    return L, d
+
+
+@pytest.mark.parametrize("q", [2, 1])
+def test_converged_steps_are_weighted_least_squares(q):
+    L, d = _overdetermined(23)
+    nd, nm = L.shape
+    live = np.ones(nd, bool)
+    live[[5, 17, 30]] = False
+    n_outer = 4
+    prm = I.IrlsParams(p=1, q=q, n_outer=n_outer, n_inner=4 * nm)
+    dmax = np.max(np.abs(d[live]))
+    m = np.zeros(nm)
+    for k in range(1, n_outer + 1):
+        if k == 1:
+            w = live.astype(float)
+        else:
+            r = (d - L @ m)[live]
+            mad = np.median(np.abs(r - np.median(r)))
+            e = max(prm.b_r * mad / 0.6745, prm.eps_floor_rel * dmax)
+            w = np.zeros(nd)
+            w[live] = 1.0 / np.sqrt(np.maximum(np.abs(r), e))
+        m = np.linalg.lstsq(w[:, None] * L, w * d, rcond=None)[0]
+        got = _run_explicit(L, d, I.IrlsParams(**{**prm.__dict__, "n_outer": k}),
+                            mask=live.astype(np.uint8))[0].ravel()
+        np.testing.assert_allclose(got, m, rtol=1e-8, atol=1e-10)
+
+
+def test_w0_weights_the_first_outer_iteration():
+    L, d = _overdetermined(24)
+    nd, nm = L.shape
+    w0 = np.random.default_rng(25).uniform(0.05, 1.0, nd)
+    prm = I.IrlsParams(p=1, q=2, n_outer=1, n_inner=4 * nm)
+    got = _run_explicit(L, d, prm, w0=w0)[0].ravel()
+    want = np.linalg.lstsq(w0[:, None] * L, w0 * d, rcond=None)[0]
+    np.testing.assert_allclose(got, want, rtol=1e-8, atol=1e-10)
+    # W_r = w0, not w0^2 or sqrt(w0): those minimisers differ here
+    for alt in (w0 ** 2, np.sqrt(w0)):
+        other = np.linalg.lstsq(alt[:, None] * L, alt * d, rcond=None)[0]
+        assert np.linalg.norm(other - want) > 1e-4 * np.linalg.norm(want)
+
+
+def _krylov_ls_from(A, b, u0, k):
+    """u0 + argmin over K_k(A'A, A'(b - A u0)) of |b - A u| (dense)."""
+    return u0 + _krylov_ls(A, b - A @ u0, k)
+
+
+def test_q1_partial_cg_equals_krylov_least_squares_on_the_weighted_system():
+    # outer iteration 2 with three CG steps: the oracle's model equals the
+    # Krylov-subspace least-squares solution of the explicitly assembled
+    # W_r S L W_m^-1 system started at u0 = W_m m1
+    L, d, m0 = _underdetermined(26, nd=20, nm=16)     # overdetermined-ish: no exact fit
+    nd, nm = L.shape
+    live = np.ones(nd, bool)
+    live[[2, 9]] = False
+    S = live.astype(float)
+    b_m, k_in = 20.0, 3
+    prm1 = I.IrlsParams(p=1, q=1, n_outer=1, n_inner=k_in, b_m=b_m)
+    prm2 = I.IrlsParams(p=1, q=1, n_outer=2, n_inner=k_in, b_m=b_m)
+    m1 = _run_explicit(L, d, prm1, m0=m0, mask=live.astype(np.uint8))[0].ravel()
+    m2, _, rep = _run_explicit(L, d, prm2, m0=m0, mask=live.astype(np.uint8))
+    # outer 1 (unweighted) against Krylov from m0
+    A1 = S[:, None] * L
+    np.testing.assert_allclose(m1, _krylov_ls_from(A1, S * d, m0, k_in), rtol=1e-9, atol=1e-11)
+    # outer 2: weights from m1 and its residual
+    r = (S * (d - L @ m1))[live]
+    e = max(prm2.b_r * np.median(np.abs(r - np.median(r))) / 0.6745,
+            prm2.eps_floor_rel * np.max(np.abs(d[live])))
+    wr = np.zeros(nd)
+    wr[live] = np.maximum(np.abs(r), e) ** -0.5
+    em = b_m * np.max(np.abs(m1)) / 100.0
+    wm = np.maximum(np.abs(m1), em) ** -0.5
+    assert np.sum(np.abs(m1) < em) > 0
+    A2 = (wr * S)[:, None] * L / wm[None, :]
+    u2 = _krylov_ls_from(A2, wr * S * d, wm * m1, k_in)
+    np.testing.assert_allclose(m2.ravel(), u2 / wm, rtol=1e-9, atol=1e-11)
+    assert rep["eps_m"] == [pytest.approx(em, rel=1e-14)]
