@@ -35,6 +35,18 @@ __device__ __forceinline__ int px(int i) {
   else return i;
 }
 
+// The thread index as a fresh value that the compiler cannot relate to any
+// other use of threadIdx.x.  Every pass derives its LDS indices from its own
+// copy.  With the plain index, the compiler built the address of element
+// j + 384 once, as (j | 384), inside the 96-lane guard of pass 1 of the
+// 768-point transform (where the bits are disjoint), and reused it in the
+// 192-lane radix-4 pass, where lanes 128..191 then read the wrong element.
+__device__ __forceinline__ int pass_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <int N>
 struct FftPlan {
   static constexpr bool three = (N % 3) == 0;
@@ -153,9 +165,10 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
   float2 v[MAXB][R];
   int dst[MAXB], bq[MAXB];
   const int total = B * nb;
+  const int tid = pass_tid();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int id = (int)threadIdx.x + i * NT;
+    const int id = tid + i * NT;
     dst[i] = -1;
     if (id < total) {
       const int b = id / B;
@@ -258,9 +271,10 @@ struct FftRegsIn {
   float2 v[MAXB][R];
   // x[t] = src[t] for t < nt, zero after
   __device__ __forceinline__ void load(const float2* __restrict__ src, int nt) {
+    const int tid = pass_tid();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-      const int id = (int)threadIdx.x + i * NT;
+      const int id = tid + i * NT;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int t = id + r * B;
@@ -277,9 +291,10 @@ struct FftRegsIn {
 template <int N, bool INV, int NT>
 __device__ __forceinline__ void fft_tpl_regs_pass0(float2* buf, FftRegsIn<N, NT>& in) {
   using I = FftRegsIn<N, NT>;
+  const int tid = pass_tid();
 #pragma unroll
   for (int i = 0; i < I::MAXB; ++i) {
-    const int id = (int)threadIdx.x + i * NT;
+    const int id = tid + i * NT;
     if (id < I::B) {
       dft_r<I::R, INV>(in.v[i]);
 #pragma unroll
@@ -319,9 +334,10 @@ __device__ __forceinline__ void fft_tpl_passes_to_regs(float2* buf, const float2
   static_assert(!PAIRS_IN || FIRST == 0, "only the first pass reads pairs");
   tpl_passes<N, FIRST, N, INV, NT, PAIRS_IN, false, O::L>(buf, 1, fft_padlen(N), twp);
   constexpr int TW = P::twoff(O::L);
+  const int tid = pass_tid();
 #pragma unroll
   for (int i = 0; i < O::MAXB; ++i) {
-    const int id = (int)threadIdx.x + i * NT;
+    const int id = tid + i * NT;
     if (id < O::B) {
 #pragma unroll
       for (int r = 0; r < O::R; ++r) out.v[i][r] = buf[fft_pad(id + r * O::B)];

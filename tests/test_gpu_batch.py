@@ -144,6 +144,77 @@ def test_batched_production_shapes_match_single_gather(A):
         np.testing.assert_allclose(reps[i]["misfit"], rep_s["misfit"], rtol=1e-5)
 
 
+def test_batched_solve_with_full_size_gather_matches_oracle(A):
+    """Gather 31 of the 512-gather workload (nt 2048 x nx 318, 24
+    velocities: time FFT 4096, x FFT 768) packed between two smaller gathers
+    drawn by the same law, solved 2 x 5 in one batch.  The big gather's
+    separated gather and misfits are compared with the FP64 oracle's solve
+    stored by tests/golden/make_oracle_values.py (4096 sampled values, the
+    norm and the per-trace norms); the small ones with the oracle run here."""
+    import json
+    import os
+    from synth import make_cfg3_batch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_separation.json")))
+    ref = gold["batch512-crg-nv24:g31:2x5"]
+    w = workload("batch512-crg-nv24")
+    big = make_cfg3_batch(w, 1, 31)[0]
+    assert (big.nt, big.nx) == (ref["nt"], ref["nx"]) == (2048, 318)
+    small = [make_gather(w, seed=5001, nt=512, nx=100), make_gather(w, seed=5002, nt=300, nx=150)]
+    gths = [small[0], big, small[1]]
+    kws = [geom_kwargs(g.nt, g.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax) for g in gths]
+    print(f"[gpu] batched 2x5 solve {[(g.nt, g.nx) for g in gths]} vs oracle", flush=True)
+    plan = A.BatchPlan(kws)
+    P = A.Params(p=1, q=2, n_outer=2, n_inner=5)
+    _, drec, reps = plan.robust_invert(plan.pack_data([f32(g.d_blend) for g in gths]), P)
+    out = plan.unpack_data(drec, 1).cpu().numpy().astype(np.float64)
+    idx = np.asarray(ref["drec_index"])
+    e_s = rel_l2(out.ravel()[idx], np.asarray(ref["drec_value"]))
+    e_n = abs(np.linalg.norm(out) / ref["drec_norm"] - 1.0)
+    e_t = rel_l2(np.linalg.norm(out, axis=1), np.asarray(ref["drec_trace_norm"]))
+    print(f"  gather 31: d_rec sampled rel-L2 {e_s:.2e}, norm {e_n:.2e}, trace norms {e_t:.2e}", flush=True)
+    assert e_s <= 1e-4 and e_n <= 1e-4 and e_t <= 1e-4
+    np.testing.assert_allclose(reps[1]["misfit"], ref["misfit"], rtol=1e-4)
+    prm = IrlsParams(p=1, q=2, n_outer=2, n_inner=5)
+    for i in (0, 2):
+        _, d_ref, rep_ref = oracle.robust_invert(oracle_geometry(kws[i]), f32(gths[i].d_blend), prm)
+        e = rel_l2(plan.unpack_data(drec, i).cpu().numpy(), d_ref)
+        print(f"  gather {i} {(gths[i].nt, gths[i].nx)}: d_rec rel-L2 {e:.2e}", flush=True)
+        assert e <= 1e-4
+        np.testing.assert_allclose(reps[i]["misfit"], rep_ref["misfit"], rtol=1e-4)
+
+
+@pytest.mark.parametrize("pq", [(1, 2), (2, 1)])
+def test_batched_cg_graph_replays_match_eager_launches(A, pq):
+    """Batched CG iterations replayed from the captured hipGraph give
+    bit-identical results to launching them one by one: three uneven gathers
+    (two FFT length classes per stage), an odd CG count (the last iteration
+    of each outer step runs eagerly), and three solves in a row on different
+    data so the cached graph replays against new contents with the solver's
+    eager work between replays."""
+    import torch
+    p, q = pq
+    print(f"[gpu] batched cg graph vs eager p={p} q={q}", flush=True)
+    w = workload("crg-256x64-nv8")
+    shapes = [(256, 64, 1), (192, 50, 11), (600, 40, 12)]
+    gths = [make_gather(w, seed=s, nt=nt, nx=nx) for nt, nx, s in shapes]
+    kws = [geom_kwargs(nt, nx, w.dt, w.dx, list(w.vel), fmax=w.fmax) for nt, nx, _ in shapes]
+    plan = A.BatchPlan(kws)
+    d1 = plan.pack_data([f32(g.d_blend) for g in gths])
+    rng = np.random.default_rng(32)
+    d2 = 0.5 * d1 + torch.tensor(rng.standard_normal(d1.numel()) * 0.05, dtype=torch.float32, device="cuda")
+    for d in (d1, d2, d1):
+        res = {}
+        for graph in (False, True):
+            prm = A.Params(p=p, q=q, n_outer=3, n_inner=7, cg_graph=graph)
+            res[graph] = plan.robust_invert(d, prm)
+        (m_e, dr_e, rep_e), (m_g, dr_g, rep_g) = res[False], res[True]
+        assert torch.equal(m_e, m_g)
+        assert torch.equal(dr_e, dr_g)
+        for a, b in zip(rep_e, rep_g):
+            assert a["misfit"] == b["misfit"]
+            assert a["inner"] == b["inner"]
+
+
 def test_batched_rejects_tolerance_and_empty(A):
     import torch
     plan = A.BatchPlan(GEOMS[:2])

@@ -73,6 +73,13 @@ CASES = {
     "long-ntp3072": (geom_kwargs(1536, 16, 0.004, 12.5, [1500.0, 2600.0, 3800.0], fmax=110.0), 0.0),
     "long-ntp4096-ragged-mask": (geom_kwargs(1900, 10, 0.004, 12.5, [1500.0, 2600.0, 3800.0], tau0=[0, 11, 3],
                                              fmax=110.0), 0.2),
+    # the remaining compile-time lengths: x 256 / time 768, x 384 / time 1024,
+    # x 768 / time 1536 (the batched workload's widest gathers use x 768) and x 1024
+    "x256-t768": (geom_kwargs(300, 100, 0.004, 12.5, [1500.0, 2300.0, 3600.0], fmax=100.0), 0.0),
+    "x384-t1024-ramp": (geom_kwargs(450, 150, 0.004, 12.5, [1400.0, 1400.0, 2900.0], tau0=[0, 13, 0],
+                                    fmax=100.0), 0.0),
+    "x768-t1536-mask": (geom_kwargs(700, 300, 0.004, 12.5, [1600.0, 2500.0, 3900.0], fmax=100.0), 0.2),
+    "x1024-t512": (geom_kwargs(200, 500, 0.004, 12.5, [1500.0, 2600.0], fmax=100.0), 0.0),
 }
 
 
@@ -135,22 +142,28 @@ def test_linearity_and_zero(A):
     assert rel_l2(lhs, rhs) < 1e-6
 
 
-def test_aashrt_full_size_matches_stored_oracle_samples(A):
-    """The asymptote-shifted workload at full size (1024 x 256, 24 velocities
-    x 16 asymptote shifts = 384 panels, half the traces decimated): forward
-    and adjoint of seeded Gaussian inputs against the FP64 oracle's outputs
+def test_full_size_operators_match_stored_oracle_samples(A):
+    """Full-size workloads: the asymptote-shifted gather (1024 x 256, 24
+    velocities x 16 asymptote shifts = 384 panels, half the traces
+    decimated), the production gather (1024 x 256, 32 velocities) and the
+    batched workload's gather 31 (2048 x 318, 24 velocities): forward and
+    adjoint of seeded Gaussian inputs against the FP64 oracle's outputs
     stored by tests/golden/make_oracle_values.py --operator (norms and 512
-    sampled values each; the oracle needs ~20 s for the pair, too slow to run
-    inside the test)."""
+    sampled values each; the oracle needs tens of seconds per pair, too slow
+    to run inside the test)."""
     import json
     import os
     import torch
     from synth import make_gather, random_data, random_model, workload
+    from synth import make_cfg3_batch
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_operator_samples.json")))
-    for name in ("aashrt-1024x256-nv24x16", "crg-1024x256-nv32"):
+    # "batch512-crg-nv24:g31": gather 31 of the 512-gather workload, nt 2048 x
+    # nx 318 with 24 velocities (time FFT 4096, x FFT 768)
+    for name in ("aashrt-1024x256-nv24x16", "crg-1024x256-nv32", "batch512-crg-nv24:g31"):
         ref = gold[name]
-        w = workload(name)
-        gth = make_gather(w)
+        base, _, gi = name.partition(":g")
+        w = workload(base)
+        gth = make_cfg3_batch(w, 1, int(gi))[0] if gi else make_gather(w)
         print(f"[gpu] full-size operator vs stored oracle samples case={name}", flush=True)
         plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
                       half_width=w.half_width)
