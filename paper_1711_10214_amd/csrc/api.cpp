@@ -528,7 +528,9 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
   };
   auto nband_of = [](const GatherHost& gh) { return (size_t)(gh.z.jhi - gh.z.jlo + 1); };
   auto plen_of = [](const GatherHost& gh) { return (size_t)fft_padlen(gh.z.ntp); };
-  auto lds_rf_of = [&](const GatherHost& gh) { return (twt_of(gh) + plen_of(gh)) * 8 + nband_of(gh) * 16; };
+  auto lds_rf_of = [&](const GatherHost& gh) {
+    return (twt_of(gh) + kMapGuardSlots + plen_of(gh)) * 8 + nband_of(gh) * 16;
+  };
   auto lds_fin_of = [&](const GatherHost& gh) { return (twt_of(gh) + plen_of(gh)) * 8; };
   auto lds_ra_of = [&](const GatherHost& gh) { return (twt_of(gh) + 2 * plen_of(gh)) * 8; };
   // work lists grouped by kernel instantiation; a gather's items stay contiguous

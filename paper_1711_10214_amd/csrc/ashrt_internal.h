@@ -22,6 +22,7 @@ constexpr int row_threads(int n) { return n >= 3072 ? 512 : kRowThreads; }
 // allows.  Generic lengths keep their registers.
 constexpr int row_waves_per_eu(int n) { return n > 0 ? 4 : 1; }
 constexpr int kMaxHalfWidth = 8;       // interpolation half-width R supported
+constexpr int kMapGuardSlots = 6;      // zero float2 slots in front of the forward map's spectrum (taps k >= -3)
 constexpr int kRowMaxN = 4096;         // longest time FFT (ntp) the row kernels take
 constexpr int kXLoadBatch = 4;        // x kernels: tile-loop iterations whose global loads are issued together
 constexpr int kXfftTilePoints = 4096;  // complex points of a model x-FFT tile (T = 2 * this / nxp columns)

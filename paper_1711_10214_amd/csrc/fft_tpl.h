@@ -150,7 +150,7 @@ __device__ __forceinline__ void pair_put(float2* buf, int o, float2 v) {
 // One pass of a batch of nb transforms (nb * N <= NBN) at buf + b*bstride,
 // run by a workgroup of NT threads.  IO = 1: this pass reads its input from
 // the pair layout; IO = 2: it writes its output in the pair layout (bins 0
-// and N/2 dropped); IO = 3: inputs at index >= nvalid are taken as zero (and
+// and N/2 dropped; one transform: pair 0 and slots N .. N+7 are zeroed); IO = 3: inputs at index >= nvalid are taken as zero (and
 // never read); IO = 4: outputs at index >= nvalid are dropped; IO = 0:
 // padded layout both ways.  Reads complete before the barrier and writes
 // follow it, so the layouts may share memory.
@@ -199,6 +199,12 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
     }
   }
   __syncthreads();
+  if constexpr (IO == 2) {
+    // pair 0 (bins 0 and N) and pairs N/2 .. N/2 + 3 (slots N .. N + 7, in
+    // the padding) are left zero: a map reading taps there gets zeros
+    static_assert(N >= 128, "pair output needs eight padding slots");
+    if (tid < 10) buf[tid < 2 ? tid : N + tid - 2] = make_float2(0.f, 0.f);
+  }
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     if (dst[i] >= 0) {

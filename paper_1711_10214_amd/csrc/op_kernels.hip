@@ -28,6 +28,7 @@
 #include "block_reduce.h"
 #include "fft_tpl.h"
 #include "kernels.h"
+#include "tap_poly.h"
 
 namespace ashrt {
 
@@ -146,6 +147,79 @@ __device__ __forceinline__ int cone_first_bin(double a2) {
   if (j > 0 && (double)(j - 1) * (double)(j - 1) >= a2) --j;
   if ((double)j * (double)j < a2) ++j;
   return j;
+}
+
+// Half-width 4 (the compile-time row kernels): coordinates in FP32 and the
+// eight weights from polynomials.
+//
+// a^2 of a (panel, wavenumber) row as an exact integer part and an FP32
+// fraction f, so a row's a^2 is taken as a2i + f (within 3e-8 of the FP64
+// value).  For a data bin j in the cone, u^2 = K - f with K = j^2 - a2i an
+// exact integer.  k0 = floor(u) is the FP32 root's integer part corrected
+// by one where needed, with integer tests (k0^2 <= K - [f > 0] <
+// (k0 + 1)^2), so it is exact for this u^2: it rises by at least 1 from one
+// bin to the next (u_{j+1} - u_j = (2j+1) / (u_{j+1} + u_j) >= 1), which the
+// adjoint's ordered scatter relies on.  delta = (K - k0^2 - f) / (u + k0)
+// takes the integer part exactly and the root only in the denominator, so
+// it is good to ~1e-7.  Where u^2 lies within the 3e-8 change of a^2 of a
+// perfect square, k0 may differ by one from the FP64 floor: the taps then
+// shift by one place, and the tap that leaves or enters sits at
+// |u - k| = R, where the weight is ~1e-14.
+struct RowA2 {
+  int i;
+  float f;
+};
+
+__device__ __forceinline__ RowA2 split_a2(double a2) {
+  RowA2 r;
+  if (!(a2 < 1073741824.0)) {  // no bin of such a row is in the cone (j < 2^12)
+    r.i = 1 << 30;
+    r.f = 0.f;
+    return r;
+  }
+  const double f = floor(a2);
+  r.i = (int)f;
+  r.f = (float)(a2 - f);
+  return r;
+}
+
+struct Taps4 {
+  int k0;       // floor(u): the taps are k0 - 3 .. k0 + 4
+  float w[8];   // h(delta - t), t = -3 .. 4
+};
+
+// Data bin j (j^2 >= a^2, j < 2^12) of a row: tap base and weights.  The
+// weight of tap t is a degree-9 polynomial in z = (2 delta - 1) * scale
+// (tap_poly.h); taps t and 1 - t share the even and odd parts.
+__device__ __forceinline__ Taps4 taps4(int j, RowA2 a) {
+  Taps4 T;
+  const int jj = (int)__umul24((unsigned)j, (unsigned)j) - a.i;
+  const float u2 = (float)jj - a.f;
+  const float u = __builtin_amdgcn_sqrtf(fmaxf(u2, 0.f));
+  // exact floor of sqrt(jj - f): k0^2 <= kf < (k0 + 1)^2 with kf = jj - [f > 0]
+  const int kf = jj - (a.f > 0.f ? 1 : 0);
+  int k0 = (int)u;
+  if ((int)__umul24((unsigned)k0, (unsigned)k0) > kf) --k0;
+  else if ((int)__umul24((unsigned)(k0 + 1), (unsigned)(k0 + 1)) <= kf) ++k0;
+  const float rem = (float)(jj - (int)__umul24((unsigned)k0, (unsigned)k0)) - a.f;
+  const float dl = rem * __builtin_amdgcn_rcpf(fmaxf(u + (float)k0, 1e-30f));
+  const float z = fmaf(2.0f * kTapZScale, dl, -kTapZScale);
+  const float z2 = z * z;
+  T.k0 = k0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float e = fmaf(kTapEven[q][4], z2, kTapEven[q][3]);
+    e = fmaf(e, z2, kTapEven[q][2]);
+    e = fmaf(e, z2, kTapEven[q][1]);
+    e = fmaf(e, z2, kTapEven[q][0]);
+    float o = fmaf(kTapOdd[q][4], z2, kTapOdd[q][3]);
+    o = fmaf(o, z2, kTapOdd[q][2]);
+    o = fmaf(o, z2, kTapOdd[q][1]);
+    o = fmaf(o, z2, kTapOdd[q][0]);
+    T.w[4 + q] = fmaf(z, o, e);    // tap t = q + 1
+    T.w[3 - q] = fmaf(-z, o, e);   // tap t = -q
+  }
+  return T;
 }
 
 template <int R>
@@ -970,12 +1044,21 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
   const int S = G.nchunk;
   const int hmax = ntp / 2 - 1;
   const int plen = N > 0 ? fft_padlen(N) : ntp;
+  // compile-time lengths: kMapGuardSlots zero slots in front of the
+  // spectrum, and the FFT's pair output leaves pair 0 and the pairs N/2 ..
+  // N/2 + 3 zero, so taps k = -3 .. 0 and past N/2 - 1 read zeros and the
+  // map needs no bounds test
   float2* twl = lds;
-  float2* buf = lds + fft_tw_slots(N, ntp);
+  float2* buf = lds + fft_tw_slots(N, ntp) + (N > 0 ? kMapGuardSlots : 0);
   float2* acc = buf + plen;
-  const float4* P4 = reinterpret_cast<const float4*>(buf);  // row spectrum, pair layout
+  // row spectrum, pair layout (16-byte aligned: the twiddle and guard slot
+  // counts are even)
+  const float4* P4 = reinterpret_cast<const float4*>(buf);
   stage_twiddles<N, NT>(twl, A.tw, G.tw_t_off, G.twp_t_off, ntp);
   for (int i = threadIdx.x; i < 2 * nband; i += NT) acc[i] = make_float2(0.f, 0.f);
+  if constexpr (N > 0) {
+    if ((int)threadIdx.x < kMapGuardSlots) buf[(int)threadIdx.x - kMapGuardSlots] = make_float2(0.f, 0.f);
+  }
   const int lu = (r == 0) ? 0 : r;
   const int ll = (r == 0) ? nrows : r;
   const double lup2 = (double)lu * (double)lu;
@@ -1020,6 +1103,53 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
     // rows >= 1 map only bins inside the cone (the rest add zero); row 0's
     // l = 0 half covers the whole band
     const int jstart = (r != 0) ? max(jlo, cone_first_bin(PD.c2 * lup2)) : jlo;
+    if constexpr (RC > 0) {
+      static_assert(RC == 4, "compile-time row kernels use the half-width-4 weight polynomials");
+      const RowA2 aup = split_a2(PD.c2 * lup2);
+      const RowA2 alo = split_a2(PD.c2 * llo2);
+      const int jcone_lo = (r == 0) ? cone_first_bin(PD.c2 * llo2) : 0;
+#pragma unroll 1
+      for (int j = jstart + (int)threadIdx.x; j <= jhi; j += NT) {
+        float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
+        const Taps4 tu = taps4(j, aup);
+        const float4* qu = P4 + (tu.k0 - 3);
+        if (r != 0) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const float4 q = qu[t];
+            au = cfma(tu.w[t], make_float2(q.x, q.y), au);
+            al = cfma(tu.w[t], make_float2(q.z, -q.w), al);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const float4 q = qu[t];
+            au = cfma(tu.w[t], make_float2(q.x, q.y), au);
+          }
+          if (j >= jcone_lo) {
+            const Taps4 tl = taps4(j, alo);
+            const float4* ql = P4 + (tl.k0 - 3);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const float4 q = ql[t];
+              al = cfma(tl.w[t], make_float2(q.z, -q.w), al);
+            }
+          }
+        }
+        float2* du = acc + (j - jlo);
+        float2* dl = acc + nband + (j - jlo);
+        if (plain) {
+          *du = cfma(PD.scale, au, *du);
+          *dl = cfma(PD.scale, al, *dl);
+        } else {
+          const float2 cj = bin_factor(G, PD, A.tw, A.wav, j);
+          *du = cadd(*du, cmul(cj, au));
+          *dl = cadd(*dl, cmul(cj, al));
+        }
+      }
+      __syncthreads();
+      continue;
+    }
 #pragma unroll 1
     for (int j = jstart + (int)threadIdx.x; j <= jhi; j += NT) {
       const Taps tu = taps_of<RC>(j, PD.c2 * lup2, R);
@@ -1081,7 +1211,8 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
 
 template <int N, int RC>
 __global__ __launch_bounds__(row_threads(N)) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu(N)))) void k_rows_fwd(RowsArgs A) {
-  extern __shared__ float2 lds[];
+  extern __shared__ float4 lds_raw[];  // 16-byte aligned: the map reads 16-byte pairs
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
   __syncthreads();
@@ -1285,6 +1416,50 @@ __device__ __forceinline__ ScatterBin scatter_bin(const RowsArgs& A, const Gathe
   return b;
 }
 
+// Half-width-4 form: the eight weights instead of the trig terms.
+struct ScatterBin4 {
+  int k0;
+  float w[8];
+  float2 e1, e2;
+};
+
+__device__ __forceinline__ ScatterBin4 scatter_bin4(const RowsArgs& A, const GatherDev& G, const PanelDev& PD,
+                                                    bool plain, const float2* bufD, int r, int pass, RowA2 a, int j,
+                                                    int jmax) {
+  ScatterBin4 b;
+  b.k0 = kNoTap;
+  b.e1 = b.e2 = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) b.w[t] = 0.f;
+  if (j > jmax) return b;
+  const Taps4 T = taps4(j, a);
+  b.k0 = T.k0;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) b.w[t] = T.w[t];
+  const float4 dq = reinterpret_cast<const float4*>(bufD)[j];
+  float2 du = make_float2(dq.x, dq.y);
+  float2 dl = make_float2(dq.z, -dq.w);
+  if (plain) {
+    du = cscale(du, PD.scale);
+    dl = cscale(dl, PD.scale);
+  } else {
+    const float2 c = bin_factor(G, PD, A.tw, A.wav, j);
+    du = cmulconj(du, c);
+    dl = cmulconj(dl, c);
+  }
+  if (r != 0) {
+    b.e1 = du;
+    b.e2 = cconj(dl);
+  } else if (pass == 0) {
+    b.e1 = du;
+    b.e2 = cconj(du);
+  } else {
+    b.e1 = make_float2(-dl.y, dl.x);
+    b.e2 = make_float2(dl.y, dl.x);
+  }
+  return b;
+}
+
 template <int N, int RC, int NT>
 __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem& w, const GatherDev& G,
                                               float2* lds, const float* ctab, const float* stab) {
@@ -1330,6 +1505,35 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
       // segments start at the cone edge (bins below it have no taps)
       const int jb = max(jlo, cone_first_bin(a2));
       const int nseg = jb <= jhi ? (jhi - jb + 64) >> 6 : 0;
+      if constexpr (RC > 0) {
+        static_assert(RC == 4, "compile-time row kernels use the half-width-4 weight polynomials");
+        const RowA2 a = split_a2(a2);
+        for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll 1
+          for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
+            const ScatterBin4 sb = scatter_bin4(A, G, PD, plain, bufD, r, pass, a, jb + sg * 64 + lane, jhi);
+            if (sb.k0 != kNoTap) {
+              // taps below bin 1 land in the padding that ends bufD (never
+              // read after its transform), taps past N/2-1 in bufM's own
+              // padding (overwritten by its transform), and pair 0 is never
+              // read by the inverse transform
+              float4* q0 = reinterpret_cast<float4*>(bufM) + (sb.k0 - 3);
+#pragma unroll
+              for (int t = 0; t < 8; ++t) {
+                float4 v = q0[t];
+                v.x = fmaf(sb.w[t], sb.e1.x, v.x);
+                v.y = fmaf(sb.w[t], sb.e1.y, v.y);
+                v.z = fmaf(sb.w[t], sb.e2.x, v.z);
+                v.w = fmaf(sb.w[t], sb.e2.y, v.w);
+                q0[t] = v;
+                __builtin_amdgcn_wave_barrier();
+              }
+            }
+          }
+          __syncthreads();
+        }
+        continue;
+      }
       for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll 1
         for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
@@ -1386,7 +1590,8 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
 
 template <int N, int RC>
 __global__ __launch_bounds__(row_threads(N)) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu(N)))) void k_rows_adj(RowsArgs A) {
-  extern __shared__ float2 lds[];
+  extern __shared__ float4 lds_raw[];  // 16-byte aligned: the map reads 16-byte pairs
+  float2* lds = reinterpret_cast<float2*>(lds_raw);
   __shared__ float ctab[2 * kMaxHalfWidth], stab[2 * kMaxHalfWidth];
   init_tap_trig(ctab, stab, RC > 0 ? RC : A.R);
   __syncthreads();

@@ -167,8 +167,9 @@ def test_zero_data_is_finite(A):
 
 def test_production_solve_matches_stored_oracle(A):
     """Full 10 x 20 solve of the production gather (1024 x 256, 32 velocities)
-    against the FP64 oracle's per-iteration misfits and separated-signal SNR,
-    stored by tests/golden/make_oracle_values.py (which calls only the oracle)."""
+    against the FP64 oracle's solve stored by tests/golden/make_oracle_values.py
+    (which calls only the oracle): the separated gather element-wise, the
+    model, Q_R, and the per-iteration misfits and clips."""
     import torch
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_separation.json")))
     ref = gold["crg-1024x256-nv32"]
@@ -177,14 +178,44 @@ def test_production_solve_matches_stored_oracle(A):
     plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
     d = torch.tensor(gth.d_blend, dtype=torch.float32, device="cuda")
     print("[gpu] invert parity crg-1024x256-nv32 10x20 vs stored oracle", flush=True)
-    _, drec, rep = plan.robust_invert(d, A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner))
-    q_r = oracle.q_db(gth.d_clean, drec.cpu().numpy())
-    print(f"  Q_R gpu {q_r:.6f} dB oracle {ref['q_r_db']:.6f} dB", flush=True)
-    print(f"  misfit rel err {np.max(np.abs(np.array(rep['misfit']) / np.array(ref['misfit']) - 1)):.2e}", flush=True)
-    assert q_r >= ref["q_r_db"] - 0.05
-    assert abs(q_r - ref["q_r_db"]) < 0.01
+    m, drec, rep = plan.robust_invert(d, A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner))
+    _check_stored_solve(gth, ref, m, drec, rep)
+
+
+def _check_stored_solve(gth, ref, m, drec, rep):
+    """The separated gather against the stored oracle solve, element-wise:
+    4096 seeded sample values (their relative L2 error estimates the whole
+    gather's), the norm and the 256 per-trace norms, each <= 1e-4; Q_R within
+    1e-4 dB; misfits per outer iteration within 1e-4."""
+    out = drec.cpu().numpy().astype(np.float64)
+    mm = m.cpu().numpy().astype(np.float64)
+    q_r = oracle.q_db(gth.d_clean, out)
+    idx = np.asarray(ref["drec_index"])
+    e_s = rel_l2(out.ravel()[idx], np.asarray(ref["drec_value"]))
+    e_n = abs(np.linalg.norm(out) / ref["drec_norm"] - 1.0)
+    e_t = rel_l2(np.linalg.norm(out, axis=1), np.asarray(ref["drec_trace_norm"]))
+    e_m = rel_l2(mm.ravel()[np.asarray(ref["m_index"])], np.asarray(ref["m_value"]))
+    e_mn = abs(np.linalg.norm(mm) / ref["m_norm"] - 1.0)
+    e_mis = np.max(np.abs(np.array(rep["misfit"]) / np.array(ref["misfit"]) - 1))
+    print(f"  d_rec: sampled rel-L2 {e_s:.2e}, norm {e_n:.2e}, trace norms {e_t:.2e}", flush=True)
+    print(f"  m: sampled rel-L2 {e_m:.2e}, norm {e_mn:.2e}", flush=True)
+    print(f"  Q_R gpu {q_r:.7f} dB oracle {ref['q_r_db']:.7f} dB (diff {q_r - ref['q_r_db']:.1e}); "
+          f"misfit rel err {e_mis:.2e}", flush=True)
+    assert e_s <= 1e-4 and e_n <= 1e-4 and e_t <= 1e-4
+    assert abs(q_r - ref["q_r_db"]) < 1e-4
     np.testing.assert_allclose(rep["misfit"], ref["misfit"], rtol=1e-4)
-    np.testing.assert_allclose(rep["eps_r"], ref["eps_r"], rtol=1e-3)
+    # the clips are order statistics (eps_r, a median) and an extreme value
+    # (eps_m, a maximum) of FP32 vectors: each moves by at most a few times
+    # the largest single-sample error, which is set by the largest amplitudes
+    # rather than by the clip, so their bound is 1e-3
+    if ref["p"] == 1:
+        e_r = np.max(np.abs(np.array(rep["eps_r"]) / np.array(ref["eps_r"]) - 1))
+        print(f"  eps_r max rel err {e_r:.2e}", flush=True)
+        assert e_r <= 1e-3
+    if ref["q"] == 1:
+        e_q = np.max(np.abs(np.array(rep["eps_m"][1:]) / np.array(ref["eps_m"]) - 1))
+        print(f"  eps_m max rel err {e_q:.2e}", flush=True)
+        assert e_q <= 1e-3
 
 
 def test_aashrt_production_solve_matches_stored_oracle(A):
