@@ -28,7 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed FP32)
+# The kernels are built without packed FP32, so their ceiling is one FP32 FMA
+# per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 # HBM bytes per launch of the row kernels on the production gather, by the
@@ -67,33 +70,49 @@ def _measured_traffic(workload, kernel, nchunk):
     return t["bytes"].get(kernel, {}).get(nchunk)
 
 
-def _geometry_numbers(plan, nx, nt, P, R, cg_frac=0.0):
-    """Algorithmic bytes and flops per launch of each kernel family.  cg_frac:
-    the fraction of model-transform launches that also apply the previous CG
-    iteration's update (read m, g; write m, pdir: four more model streams)."""
+def fft_len(n):
+    """Smallest 2^a or 3 * 2^a >= 2 n (the library's default padding)."""
+    best, p = None, 1
+    while p < 4 * n + 8:
+        for c in (p, 3 * p):
+            if c >= 2 * n and (best is None or c < best):
+                best = c
+        p *= 2
+    return best
+
+
+def _geometry_numbers(info, vel, dt, dx, nx, nt, P, R, cg_frac=0.0):
+    """Per launch of each operator kernel family on one gather: (algorithmic
+    bytes, method flops).
+
+    Bytes are the kernel's compulsory traffic: what it must read and write
+    in this decomposition (x-spectra only for the wavenumber rows that can
+    reach the band; the forward's panel-sum partials once; the adjoint's data
+    spectrum once, although each panel chunk re-reads it).  Flops are the
+    method's: 5 N log2 N per complex FFT of length N (one time FFT per live
+    model row and per data row, one x FFT per pair of time columns) and one
+    complex-by-real multiply-add (4 flop) per tap of every in-cone map output.
+    cg_frac: the fraction of model-transform launches that also apply the
+    previous CG iteration's update (read m, g; write m, pdir: four more model
+    streams)."""
     import numpy as np
-    info = plan.info
-    ntp, nxp, jlo, jhi, nchunk = info["ntp"], info["nxp"], info["jlo"], info["jhi"], info["nchunk"]
+    ntp, nxp, jlo, jhi = info["ntp"], info["nxp"], info["jlo"], info["jhi"]
     nrows = nxp // 2
     nband = jhi - jlo + 1
     f4, c8 = 4, 8
     model_b = P * nx * nt * f4
     data_b = nx * nt * f4
-    # x-spectrum rows that can reach the band (c2 r^2 <= jhi^2, row 0 always):
-    # the only ones written and read
-    bin_ = ntp * plan.dt / (nxp * plan.dx)
+    bin_ = ntp * dt / (nxp * dx)
     live_rows = 0
-    for v in plan.vel:
+    for v in vel:
         c2 = (v * bin_) ** 2
         rl = nrows if c2 <= 0 else min(nrows, 1 + sum(1 for r in range(1, nrows) if c2 * r * r <= jhi * jhi * (1 + 1e-9)))
         live_rows += rl
     X_b = live_rows * nt * c8
     H_b = nrows * nt * c8
-    Dp_b = nchunk * nrows * 2 * nband * c8
-    fft_t = 5.0 * ntp * math.log2(ntp)          # one complex time FFT
-    fft_x = 5.0 * nxp * math.log2(nxp)          # one complex x FFT (two real columns)
-    # in-cone map outputs: for each panel, row and band bin with j >= a (up and lo rows)
-    vel = plan.vel
+    D_b = nrows * 2 * nband * c8
+    fft_t = 5.0 * ntp * math.log2(ntp)
+    fft_x = 5.0 * nxp * math.log2(nxp)
     j = np.arange(jlo, jhi + 1, dtype=np.float64)
     l = np.arange(nrows, dtype=np.float64)
     cone = 0
@@ -101,18 +120,52 @@ def _geometry_numbers(plan, nx, nt, P, R, cg_frac=0.0):
         a_up = v * bin_ * l
         a_lo = v * bin_ * np.where(l == 0, nrows, l)
         cone += int(np.sum(j[None, :] >= a_up[:, None])) + int(np.sum(j[None, :] >= a_lo[:, None]))
-    # per in-cone output: one complex x real multiply-add per tap, plus ~40
-    # flops to evaluate the bin's tap weights (the survey's per-unit figure)
-    map_flops = cone * (2 * R * 4 + 40)
+    map_flops = cone * 2 * R * 4
     return {
         "k_xfft_fwd(model)": (model_b + X_b + cg_frac * 4 * model_b, P * math.ceil(nt / 2) * fft_x),
         "k_xfft_fwd(data)": (data_b + H_b, math.ceil(nt / 2) * fft_x),
-        "k_rows_fwd": (X_b + Dp_b, live_rows * fft_t + map_flops),
-        "k_rows_fwd_fin": (Dp_b + H_b, nrows * fft_t),
+        "k_rows_fwd": (X_b + D_b, live_rows * fft_t + map_flops),
+        "k_rows_fwd_fin": (D_b + H_b, nrows * fft_t),
         "k_xfft_inv(data)": (H_b + data_b, math.ceil(nt / 2) * fft_x),
-        "k_rows_adj": (nchunk * H_b + X_b, (nchunk * nrows + live_rows) * fft_t + map_flops),
+        "k_rows_adj": (H_b + X_b, (nrows + live_rows) * fft_t + map_flops),
         "k_xfft_inv(model)": (X_b + model_b, P * math.ceil(nt / 2) * fft_x),
     }
+
+
+def _roofline(dom, bytes_, flops, avg_s, launches, traffic):
+    """Roofline entry of the dominant kernel: bound by HBM bandwidth (the
+    operator's roofline), with its FP32 issue rate beside it."""
+    ach = bytes_ / avg_s / 1e9
+    alu = flops / avg_s / 1e12
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": dom, "avg_launch_us": avg_s * 1e6, "launches_timed": launches,
+            "algorithmic_bytes_per_launch": bytes_, "method_flops_per_launch": flops,
+            "alu_achieved_tflops": alu, "alu_peak_tflops": FP32_UNPACKED_PEAK_TFLOPS,
+            "alu_frac": alu / FP32_UNPACKED_PEAK_TFLOPS}
+
+
+def _profile_solve(lib, L, solve, reps=1):
+    """Per-kernel time per solve from the library's HIP-event timing (events
+    recorded around every launch on its stream), over reps solves; returns
+    the per-kernel table and the wall time of the reps solves."""
+    import ctypes as C
+    import torch
+    torch.cuda.synchronize()
+    lib.ashrt_profile_enable((1 << L.K_COUNT) - 1)
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(reps):
+        last = solve()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.ashrt_profile_enable(0)
+    out = {}
+    for k in range(L.K_COUNT):
+        tot, n = C.c_double(), C.c_int64()
+        L.check(lib.ashrt_profile_read(k, C.byref(tot), C.byref(n), 1), "ashrt_profile_read")
+        out[lib.ashrt_kernel_name(k).decode()] = {"ms_total_per_solve": tot.value / reps,
+                                                  "launches": n.value // reps, "kid": k}
+    return out, wall, last
 
 
 def _q_db(clean, est):
@@ -124,17 +177,36 @@ def _q_db(clean, est):
     return float(10.0 * np.log10(np.sum(c * c) / np.sum((c - e) ** 2)))
 
 
-def cpu_baseline(w, gth, budget_s=25.0):
-    """The FP64 oracle on the host: a short solve of the same gather, scaled
-    to a full solve by counting operator applications."""
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def _oracle_sample(args):
+    """One bounded oracle sample on the host, in its own process with one
+    thread: the Stolt-map set-up plus a 1 x 3 solve of the gather, scaled to
+    the full solve by counting operator applications.  Returns seconds per
+    gather and the parts."""
+    name, n_outer_full, n_inner_full = args
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
     import numpy as np
     import oracle
     from oracle.irls import IrlsParams
-    try:
-        from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
-    except Exception:  # pragma: no cover
-        lim = None
+    from synth import make_gather, workload
+    w = workload(name)
+    gth = make_gather(w)
     g = oracle.geometry(gth.nt, gth.nx, w.dt, w.dx, w.vel, tau0=w.tau0, fmax=w.fmax, R=w.half_width)
     d = gth.d_blend.astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
@@ -146,16 +218,37 @@ def cpu_baseline(w, gth, budget_s=25.0):
     oracle.robust_invert(g, d, IrlsParams(p=w.p, q=w.q, n_outer=n_outer, n_inner=n_inner))
     t_sample = time.perf_counter() - t1
     apps_sample = 1 + n_outer * (2 * n_inner + 2)
-    apps_full = 1 + w.n_outer * (2 * w.n_inner + 2)
-    t_full = t_setup + t_sample * apps_full / apps_sample
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
+    apps_full = 1 + n_outer_full * (2 * n_inner_full + 2)
+    return t_setup + t_sample * apps_full / apps_sample, t_setup, t_sample, apps_sample, apps_full
+
+
+def cpu_baseline(w, gth):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    gather.  One thread; and every core of the host's share running
+    independent samples at once (gathers are independent, so that is the
+    oracle's whole-host throughput)."""
+    from concurrent.futures import ProcessPoolExecutor
+    job = (w.name, w.n_outer, w.n_inner)
+    with ProcessPoolExecutor(max_workers=1) as ex:
+        t_full, t_setup, t_sample, apps_sample, apps_full = ex.submit(_oracle_sample, job).result()
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(ncpu, 16))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(_oracle_sample, [job] * workers))
+    wall = time.perf_counter() - t0
+    all_rate = sum(1.0 / r[0] for r in res)
     return {
         "value": 1.0 / t_full, "unit": "gathers/s", "cores": 1, "kind": "oracle",
-        "sample": (f"FP64 numpy/scipy oracle, one thread: stolt-map setup {t_setup:.2f} s plus a "
-                   f"{n_outer}x{n_inner} IRLS-CG solve of the same gather ({apps_sample} operator "
-                   f"applications, {t_sample:.2f} s), scaled to the {w.n_outer}x{w.n_inner} solve "
-                   f"({apps_full} applications): {t_full:.1f} s per gather"),
+        "host_cpu": _host_cpu(), "host_cpu_count": ncpu,
+        "sample": (f"FP64 numpy/scipy oracle, one thread: stolt-map set-up {t_setup:.2f} s plus a 1x3 "
+                   f"IRLS-CG solve of the same gather ({apps_sample} operator applications, {t_sample:.2f} s), "
+                   f"scaled to the {w.n_outer}x{w.n_inner} solve ({apps_full} applications): "
+                   f"{t_full:.1f} s per gather"),
+        "all_cores": {"value": all_rate, "unit": "gathers/s", "cores": workers, "kind": "oracle",
+                      "sample": (f"{workers} independent one-thread samples as above run at once on "
+                                 f"{workers} of the host's {ncpu} cores ({wall:.1f} s wall); value = sum of "
+                                 f"their per-gather rates (the oracle itself is single-threaded)")},
     }
 
 
@@ -173,58 +266,161 @@ def _gen_batch_gather(args):
     return g.d_blend.astype("float32"), g.d_clean.astype("float32")
 
 
-def run_batch(args):
-    """The batched workload: 512 receiver gathers of uneven size (nx in
-    96..320, nt in {1024, 1536, 2048}, 24 velocities) solved together by
-    robust_invert_batched (every stage one launch per FFT size class)."""
-    import numpy as np
+def _draw_batch(n, name="batch512-crg-nv24"):
+    """The batched workload's gathers, drawn on host worker processes (call
+    before the GPU is touched)."""
     from concurrent.futures import ProcessPoolExecutor
     from synth import batch_shapes, workload
-    w = workload(args.workload)
-    n = args.batch_gathers
+    w = workload(name)
     shapes = batch_shapes(n, w.seed)
-    t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         gathers = list(ex.map(_gen_batch_gather, [(w.name, nt, nx, s) for nt, nx, s in shapes]))
-    t_gen = time.perf_counter() - t0
+    return w, shapes, gathers
+
+
+def _band(ntp, dt, fmax):
+    jhi = ntp // 2 - 1
+    if fmax > 0:
+        jhi = min(jhi, int(math.floor(fmax * ntp * dt)))
+    return 1, jhi
+
+
+def _workload_roofline(prof, per_gather_nums, classes):
+    """Dominant operator kernel of a workload over one solve: its algorithmic
+    bytes per solve (every gather passes through each launch family once per
+    operator application; a family launches once per FFT size class) over its
+    total time."""
+    ops = [k for k in prof if k.startswith(("k_xfft", "k_rows")) and prof[k]["launches"] > 0]
+    dom = max(ops, key=lambda k: prof[k]["ms_total_per_solve"])
+    n_cls = classes["rows" if dom.startswith("k_rows") else "x"]
+    passes = prof[dom]["launches"] / n_cls
+    bytes_ = sum(g[dom][0] for g in per_gather_nums) * passes
+    flops = sum(g[dom][1] for g in per_gather_nums) * passes
+    t = prof[dom]["ms_total_per_solve"] / 1e3
+    r = _roofline(dom, bytes_, flops, t, prof[dom]["launches"], None)
+    r["avg_launch_us"] = t / max(prof[dom]["launches"], 1) * 1e6
+    r["algorithmic_bytes_per_solve"] = r.pop("algorithmic_bytes_per_launch")
+    r["method_flops_per_solve"] = r.pop("method_flops_per_launch")
+    r["ms_per_solve"] = t * 1e3
+    return r
+
+
+def batch_leg(w, shapes, gathers, steps, warmup):
+    """The batched workload: every gather solved by robust_invert_batched
+    (10 x 20, l1 misfit), all stages one launch per FFT size class.  Fixed
+    SNR: gathers 0..15 must reach the FP64 oracle's Q_R (stored by
+    tests/golden/make_oracle_values.py --batch-subset) within 0.05 dB."""
+    import numpy as np
     import torch
     import paper_1711_10214_amd as A
-    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    from paper_1711_10214_amd import _lib as L
     descs = [dict(nt=nt, nx=nx, dt=w.dt, dx=w.dx, vel=list(w.vel), fmax=w.fmax, half_width=w.half_width)
              for nt, nx, _ in shapes]
     plan = A.BatchPlan(descs)
     d = plan.pack_data([g for g, _ in gathers])
     prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
-    print(f"[bench] batch of {n} gathers: model {plan.model_total * 4 / 2**30:.1f} GiB, "
+    print(f"[bench] batch of {len(shapes)} gathers: model {plan.model_total * 4 / 2**30:.1f} GiB, "
           f"data {plan.data_total * 4 / 2**30:.2f} GiB", file=sys.stderr, flush=True)
-    for _ in range(max(args.warmup, 0)):
+    for _ in range(max(warmup, 1)):
         plan.robust_invert(d, prm, want_report=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = None
-    for _ in range(args.steps):
-        out = plan.robust_invert(d, prm, want_report=False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # timed solves, with HIP events around every launch (a few per stage)
+    prof, wall, out = _profile_solve(L.lib(), L, lambda: plan.robust_invert(d, prm, want_report=False), steps)
     _, drec, _ = out
     q = []
     for gi, (g, clean) in enumerate(gathers):
         rec = plan.unpack_data(drec, gi).cpu().numpy()
         q.append((_q_db(clean, rec), _q_db(clean, g)))
     q = np.array(q)
-    rec = {
-        "metric": "robust ASHRT gathers solved/s (batched, IRLS-CG 10x20, l1 misfit)",
-        "value": n * args.steps / wall, "unit": "gathers/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "gathers": n, "npanel": w.npanel, "n_outer": w.n_outer,
-                   "n_inner": w.n_inner, "nt_set": sorted(set(s[0] for s in shapes)),
-                   "nx_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)],
-                   "model_gib": plan.model_total * 4 / 2**30, "reductions": "f64"},
+    fixed = {"checked": 0, "reached": 0, "worst_margin_db": None}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_separation.json")
+    if os.path.exists(gold):
+        ref = json.load(open(gold)).get(w.name, {}).get("gathers", {})
+        margins = []
+        for k, r in ref.items():
+            gi = int(k)
+            if gi < len(shapes) and (r["nt"], r["nx"]) == shapes[gi][:2] and (r["n_outer"], r["n_inner"]) == (
+                    w.n_outer, w.n_inner):
+                margins.append(q[gi, 0] - r["q_r_db"])
+        if margins:
+            fixed = {"checked": len(margins), "reached": int(sum(m >= -0.05 for m in margins)),
+                     "worst_margin_db": float(min(margins)), "max_abs_diff_db": float(max(abs(m) for m in margins))}
+    nums = []
+    for nt, nx, _ in shapes:
+        ntp, nxp = fft_len(nt), fft_len(nx)
+        jlo, jhi = _band(ntp, w.dt, w.fmax)
+        info = {"ntp": ntp, "nxp": nxp, "jlo": jlo, "jhi": jhi}
+        nums.append(_geometry_numbers(info, w.vel, w.dt, w.dx, nx, nt, w.npanel, w.half_width,
+                                      cg_frac=(w.n_inner - 1) / (w.n_inner + 1)))
+    classes = {"rows": len(set(fft_len(nt) for nt, _, _ in shapes)),
+               "x": len(set(fft_len(nx) for _, nx, _ in shapes))}
+    return {
+        "value": len(shapes) * steps / wall, "unit": "gathers/s", "ms_per_step": wall / steps * 1e3,
+        "steps": steps, "config": {"workload": w.name, "gathers": len(shapes), "npanel": w.npanel,
+                                   "n_outer": w.n_outer, "n_inner": w.n_inner,
+                                   "nt_set": sorted(set(s[0] for s in shapes)),
+                                   "nx_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)],
+                                   "model_gib": plan.model_total * 4 / 2**30},
         "snr": {"q_r_db_mean": float(q[:, 0].mean()), "q_pd_db_mean": float(q[:, 1].mean()),
-                "improved": int((q[:, 0] > q[:, 1]).sum())},
-        "seconds_generate": t_gen,
+                "improved": int((q[:, 0] > q[:, 1]).sum()), "fixed_snr_vs_oracle": fixed},
+        "kernels_ms_per_solve": {k: round(v["ms_total_per_solve"], 3) for k, v in prof.items() if v["launches"]},
+        "roofline": _workload_roofline(prof, nums, classes),
     }
+
+
+def aashrt_leg(steps, warmup, autotune=True):
+    """The asymptote-shifted diffraction gather (1024 x 256, 24 velocities x
+    16 asymptote shifts = 384 panels, half the traces decimated, p 2, q 1,
+    10 x 20): gathers/s, with Q (against the complete clean gather) checked
+    against the FP64 oracle's stored solve."""
+    import torch
+    import paper_1711_10214_amd as A
+    from paper_1711_10214_amd import _lib as L
+    from synth import make_gather, workload
+    w = workload("aashrt-1024x256-nv24x16")
+    gth = make_gather(w)
+    plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
+                  half_width=w.half_width, tuning="auto" if autotune else None)
+    d = torch.tensor(gth.d_blend, dtype=torch.float32, device="cuda")
+    mask = torch.tensor(gth.mask, device="cuda")
+    prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
+
+    def solve():
+        return plan.robust_invert(d, prm, mask=mask, want_report=False)
+
+    for _ in range(max(warmup, 1)):
+        solve()
+    prof, wall, out = _profile_solve(L.lib(), L, solve, steps)
+    q_r = _q_db(gth.d_clean, out[1].cpu().numpy())
+    snr = {"q_r_db": q_r, "q_pd_db": _q_db(gth.d_clean, gth.d_blend)}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_separation.json")
+    if os.path.exists(gold):
+        ref = json.load(open(gold)).get(w.name)
+        if ref and (ref["n_outer"], ref["n_inner"]) == (w.n_outer, w.n_inner):
+            snr["oracle_q_r_db"] = ref["q_r_db"]
+            snr["reached"] = bool(q_r >= ref["q_r_db"] - 0.05)
+    info = plan.info
+    nums = _geometry_numbers(info, plan.vel, w.dt, w.dx, gth.nx, gth.nt, w.npanel, w.half_width,
+                             cg_frac=(w.n_inner - 1) / (w.n_inner + 1))
+    r = _workload_roofline(prof, [nums], {"rows": 1, "x": 1})
+    return {"value": steps / wall, "unit": "gathers/s", "ms_per_step": wall / steps * 1e3, "steps": steps,
+            "config": {"workload": w.name, "nt": gth.nt, "nx": gth.nx, "npanel": w.npanel, "p": w.p, "q": w.q,
+                       "n_outer": w.n_outer, "n_inner": w.n_inner, "decimated_traces": int((gth.mask == 0).sum()),
+                       "tiling": {k: info[k] for k in ("tile_model", "tile_data", "nchunk")}},
+            "snr": snr,
+            "kernels_ms_per_solve": {k: round(v["ms_total_per_solve"], 3) for k, v in prof.items() if v["launches"]},
+            "roofline": r}
+
+
+def run_batch(args):
+    """The batched workload alone (--workload batch512-crg-nv24)."""
+    w, shapes, gathers = _draw_batch(args.batch_gathers, args.workload)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    leg = batch_leg(w, shapes, gathers, args.steps, args.warmup)
+    rec = {"metric": "robust ASHRT gathers solved/s (batched, IRLS-CG 10x20, l1 misfit)", "n_gpus": 1,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic"}
+    rec.update(leg)
     print(json.dumps(rec), flush=True)
 
 
@@ -472,6 +668,152 @@ def run_unet(args):
     print(json.dumps(rec), flush=True)
 
 
+def headline(args, w, gth):
+    """The production gather's 10 x 20 solve: K timed solves (plain
+    launches, HIP events around the dominant kernel's launches on its
+    stream), the same solves replayed through the CG hipGraph, and
+    forward + adjoint pairs."""
+    import numpy as np
+    import torch
+    import paper_1711_10214_amd as A
+    from paper_1711_10214_amd import _lib as L
+    import ctypes as C
+    dev = torch.device("cuda", 0)
+    print(f"[bench] workload {w.name}: nt={gth.nt} nx={gth.nx} P={w.npanel} "
+          f"{w.n_outer}x{w.n_inner} p={w.p} q={w.q}", file=sys.stderr, flush=True)
+    # tiling chosen by the library's autotuner (timed forward + adjoint pairs)
+    plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
+                  half_width=w.half_width, device=0, tuning=None if args.no_autotune else "auto")
+    print(f"[bench] tiling {plan.tuning}", file=sys.stderr, flush=True)
+    d = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
+    mask = None if w.decimate_frac == 0 else torch.tensor(gth.mask, device=dev)
+    prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
+    lib = L.lib()
+
+    def solve(graph=True):
+        prm.cg_graph = graph
+        return plan.robust_invert(d, prm, mask=mask, want_report=False)
+
+    for _ in range(max(args.warmup, 1)):
+        solve()
+    per_kernel, _, _ = _profile_solve(lib, L, solve)
+    op_kernels = [k for k in per_kernel if k.startswith(("k_xfft", "k_rows"))]
+    dom = max(op_kernels, key=lambda k: per_kernel[k]["ms_total_per_solve"])
+    dom_kid = per_kernel[dom]["kid"]
+    print("[bench] per-kernel ms per solve: " +
+          ", ".join(f"{k}={v['ms_total_per_solve']:.2f}" for k, v in per_kernel.items()),
+          file=sys.stderr, flush=True)
+
+    # timed region: K solves; events around the dominant kernel's launches only
+    lib.ashrt_profile_enable(1 << dom_kid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(args.steps):
+        out = solve(graph=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.ashrt_profile_enable(0)
+    tot, n = C.c_double(), C.c_int64()
+    L.check(lib.ashrt_profile_read(dom_kid, C.byref(tot), C.byref(n), 1), "ashrt_profile_read")
+    dom_avg_s = tot.value / max(n.value, 1) / 1e3
+
+    # fixed-SNR check against the oracle's stored separation of this gather,
+    # and the separated gather against the stored oracle values element-wise
+    m_out, drec, _ = out
+    drec_np = drec.cpu().numpy().astype(np.float64)
+    q_r = _q_db(gth.d_clean, drec_np)
+    snr = {"q_r_db": q_r, "q_pd_db": _q_db(gth.d_clean, gth.d_blend)}
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_separation.json")
+    if os.path.exists(gold):
+        ref = json.load(open(gold)).get(w.name)
+        if ref and ref["n_outer"] == w.n_outer and ref["n_inner"] == w.n_inner:
+            snr["oracle_q_r_db"] = ref["q_r_db"]
+            snr["reached"] = bool(q_r >= ref["q_r_db"] - 0.05)
+            if "drec_index" in ref:
+                idx = np.asarray(ref["drec_index"])
+                sv = np.asarray(ref["drec_value"])
+                mi = np.asarray(ref["m_index"])
+                mv = np.asarray(ref["m_value"])
+                mm = m_out.cpu().numpy().astype(np.float64).ravel()
+                err = {"d_rec_sampled_rel_l2": float(np.linalg.norm(drec_np.ravel()[idx] - sv) / np.linalg.norm(sv)),
+                       "d_rec_norm_rel": float(abs(np.linalg.norm(drec_np) / ref["drec_norm"] - 1)),
+                       "m_sampled_rel_l2": float(np.linalg.norm(mm[mi] - mv) / np.linalg.norm(mv)),
+                       "samples": int(idx.size), "against": "FP64 oracle solve, stored"}
+
+    # the same solves with the CG iterations replayed from a hipGraph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solve(graph=True)
+    torch.cuda.synchronize()
+    graph_wall = time.perf_counter() - t0
+
+    # operator pairs per second
+    rng = np.random.default_rng(0)
+    mm_ = torch.tensor(rng.standard_normal((w.npanel, gth.nx, gth.nt)), dtype=torch.float32, device=dev)
+    dd = torch.empty((gth.nx, gth.nt), dtype=torch.float32, device=dev)
+    m2 = torch.empty_like(mm_)
+    for _ in range(3):
+        plan.forward(mm_, out=dd)
+        plan.adjoint(dd, out=m2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.pairs):
+        plan.forward(mm_, out=dd)
+        plan.adjoint(dd, out=m2)
+    torch.cuda.synchronize()
+    pair_s = (time.perf_counter() - t0) / args.pairs
+
+    # roofline of the dominant kernel; in the solve, the model transforms of
+    # CG iterations 1 .. n_inner-1 carry the fused update
+    info = plan.info
+    nums = _geometry_numbers(info, plan.vel, w.dt, w.dx, gth.nx, gth.nt, w.npanel, w.half_width,
+                             cg_frac=(w.n_inner - 1) / (w.n_inner + 1) if w.n_inner > 0 else 0.0)
+    bytes_, flops = nums[dom]
+    roof = _roofline(dom, bytes_, flops, dom_avg_s, n.value, _measured_traffic(w.name, dom, info["nchunk"]))
+    op_nums = _geometry_numbers(info, plan.vel, w.dt, w.dx, gth.nx, gth.nt, w.npanel, w.half_width)
+    pair_bytes = sum(v[0] for v in op_nums.values())
+    compulsory = 2 * (w.npanel + 1) * gth.nx * gth.nt * 4   # model and data read and written once each
+    if args.copy_calibration:
+        x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        x.fill_(1.0)
+        y = x.clone()
+        torch.cuda.synchronize()
+        del x, y
+    rec = {
+        "metric": "robust ASHRT gathers solved/s to fixed SNR (IRLS-CG 10x20, l1 misfit); also fwd+adj pairs/s, HBM GB/s",
+        "value": args.steps / wall,
+        "unit": "gathers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nt": gth.nt, "nx": gth.nx, "ntp": info["ntp"],
+                   "tiling": {"tile_model": info["tile_model"], "tile_data": info["tile_data"],
+                              "nchunk": info["nchunk"]},
+                   "nxp": info["nxp"], "npanel": w.npanel, "p": w.p, "q": w.q,
+                   "n_outer": w.n_outer, "n_inner": w.n_inner, "fmax_hz": w.fmax,
+                   "reductions": "f64", "seed": w.seed},
+        "graph_gathers_per_s": args.steps / graph_wall,
+        "pairs_per_s": 1.0 / pair_s,
+        "pair_ms": pair_s * 1e3,
+        "pair_algorithmic_gbs": pair_bytes / pair_s / 1e9,
+        "pair_compulsory_gbs": compulsory / pair_s / 1e9,
+        "snr": snr,
+        "error_vs_oracle": err,
+        "kernels_ms_per_solve": {k: round(v["ms_total_per_solve"], 4) for k, v in per_kernel.items()},
+        "roofline": roof,
+    }
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -480,6 +822,8 @@ def main():
     ap.add_argument("--workload", default="crg-1024x256-nv32")
     ap.add_argument("--pairs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and asymptote-shifted workloads after the headline solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB device copy (for HBM counter calibration)")
     ap.add_argument("--train-gathers", type=int, default=1024, help="warm-start workload: training gathers")
@@ -508,171 +852,31 @@ def main():
     if args.workload == "unet":
         return run_unet(args)
 
-    import numpy as np
-    import torch
-
-    import paper_1711_10214_amd as A
-    from paper_1711_10214_amd import _lib as L
     from synth import make_gather, workload
-
-    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
-    dev = torch.device("cuda", 0)
     w = workload(args.workload)
     gth = make_gather(w)
-    print(f"[bench] workload {w.name}: nt={gth.nt} nx={gth.nx} P={w.npanel} "
-          f"{w.n_outer}x{w.n_inner} p={w.p} q={w.q}", file=sys.stderr, flush=True)
-    # tiling chosen by the library's autotuner (timed forward + adjoint pairs)
-    plan = A.Plan(gth.nt, gth.nx, w.dt, w.dx, list(w.vel), tau0=list(w.tau0), fmax=w.fmax,
-                  half_width=w.half_width, device=0, tuning=None if args.no_autotune else "auto")
-    print(f"[bench] tiling {plan.tuning}", file=sys.stderr, flush=True)
-    d = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
-    mask = None if w.decimate_frac == 0 else torch.tensor(gth.mask, device=dev)
-    prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
-    lib = L.lib()
-
-    def solve(graph=True):
-        prm.cg_graph = graph
-        return plan.robust_invert(d, prm, mask=mask, want_report=False)
-
-    # warm-up, plus one fully profiled solve to find the dominant kernel
-    for _ in range(max(args.warmup, 1)):
-        solve()
-    torch.cuda.synchronize()
-    lib.ashrt_profile_enable((1 << L.K_COUNT) - 1)
-    solve()
-    torch.cuda.synchronize()
-    lib.ashrt_profile_enable(0)
-    per_kernel = {}
-    import ctypes as C
-    for k in range(L.K_COUNT):
-        tot, n = C.c_double(), C.c_int64()
-        L.check(lib.ashrt_profile_read(k, C.byref(tot), C.byref(n), 1), "ashrt_profile_read")
-        per_kernel[lib.ashrt_kernel_name(k).decode()] = {"ms_total_per_solve": tot.value, "launches": n.value,
-                                                        "kid": k}
-    op_kernels = [k for k in per_kernel if k.startswith(("k_xfft", "k_rows"))]
-    dom = max(op_kernels, key=lambda k: per_kernel[k]["ms_total_per_solve"])
-    dom_kid = per_kernel[dom]["kid"]
-    print(f"[bench] per-kernel ms per solve: " +
-          ", ".join(f"{k}={v['ms_total_per_solve']:.2f}" for k, v in per_kernel.items()),
-          file=sys.stderr, flush=True)
-
-    # timed region: K solves; events around the dominant kernel's launches only
-    lib.ashrt_profile_enable(1 << dom_kid)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    out = None
-    for _ in range(args.steps):
-        out = solve(graph=False)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lib.ashrt_profile_enable(0)
-    tot, n = C.c_double(), C.c_int64()
-    L.check(lib.ashrt_profile_read(dom_kid, C.byref(tot), C.byref(n), 1), "ashrt_profile_read")
-    dom_avg_s = tot.value / max(n.value, 1) / 1e3
-    ms_per_step = wall / args.steps * 1e3
-    value = args.steps / wall
-
-    # fixed-SNR check against the oracle's stored separation of this gather
-    m_out, drec, _ = out
-    q_r = _q_db(gth.d_clean, drec.cpu().numpy())
-    q_pd = _q_db(gth.d_clean, gth.d_blend)
-    snr = {"q_r_db": q_r, "q_pd_db": q_pd}
-    gold = os.path.join(ROOT, "tests", "golden", "oracle_separation.json")
-    if os.path.exists(gold):
-        ref = json.load(open(gold)).get(w.name)
-        if ref and ref["n_outer"] == w.n_outer and ref["n_inner"] == w.n_inner:
-            snr["oracle_q_r_db"] = ref["q_r_db"]
-            snr["reached"] = bool(q_r >= ref["q_r_db"] - 0.05)
-
-    # the same solves with the CG iterations replayed from a hipGraph (no
-    # per-kernel events, which keep the timed region above on plain launches)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solve(graph=True)
-    torch.cuda.synchronize()
-    graph_wall = time.perf_counter() - t0
-
-    # operator pairs per second
-    rng = np.random.default_rng(0)
-    mm = torch.tensor(rng.standard_normal((w.npanel, gth.nx, gth.nt)), dtype=torch.float32, device=dev)
-    dd = torch.empty((gth.nx, gth.nt), dtype=torch.float32, device=dev)
-    m2 = torch.empty_like(mm)
-    for _ in range(3):
-        plan.forward(mm, out=dd)
-        plan.adjoint(dd, out=m2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.pairs):
-        plan.forward(mm, out=dd)
-        plan.adjoint(dd, out=m2)
-    torch.cuda.synchronize()
-    pair_s = (time.perf_counter() - t0) / args.pairs
-
-    # roofline of the dominant kernel
-    # in the solve, the model transforms of CG iterations 1 .. n_inner-1 carry
-    # the fused update; iteration 0 and the residual forward of each outer
-    # step do not
-    nums = _geometry_numbers(plan, gth.nx, gth.nt, w.npanel, w.half_width,
-                             cg_frac=(w.n_inner - 1) / (w.n_inner + 1) if w.n_inner > 0 else 0.0)
-    bytes_, flops = nums[dom]
-    hbm_frac = (bytes_ / dom_avg_s / 1e9) / HBM_PEAK_GBS
-    alu_frac = (flops / dom_avg_s / 1e12) / FP32_VECTOR_PEAK_TFLOPS
-    if hbm_frac >= alu_frac:
-        roof = {"bound": "hbm", "achieved": bytes_ / dom_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": flops / dom_avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = _measured_traffic(w.name, dom, plan.info["nchunk"])
-    roof["kernel"] = dom
-    roof["avg_launch_us"] = dom_avg_s * 1e6
-    roof["launches_timed"] = n.value
-    roof["algorithmic_bytes_per_launch"] = bytes_
-    roof["algorithmic_flops_per_launch"] = flops
-    roof["hbm_frac"] = hbm_frac
-    roof["alu_frac"] = alu_frac
-    pair_bytes = sum(v[0] for v in _geometry_numbers(plan, gth.nx, gth.nt, w.npanel, w.half_width).values())
-    if args.copy_calibration:
-        x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
-        x.fill_(1.0)
-        y = x.clone()
-        torch.cuda.synchronize()
-        del x, y
-
-    rec = {
-        "metric": "robust ASHRT gathers solved/s to fixed SNR (IRLS-CG 10x20, l1 misfit); also fwd+adj pairs/s, HBM GB/s",
-        "value": value,
-        "unit": "gathers/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "nt": gth.nt, "nx": gth.nx, "ntp": plan.info["ntp"],
-                   "tiling": {"tile_model": plan.info["tile_model"], "tile_data": plan.info["tile_data"],
-                              "nchunk": plan.info["nchunk"]},
-                   "nxp": plan.info["nxp"], "npanel": w.npanel, "p": w.p, "q": w.q,
-                   "n_outer": w.n_outer, "n_inner": w.n_inner, "fmax_hz": w.fmax,
-                   "reductions": "f64", "seed": w.seed},
-        "graph_gathers_per_s": args.steps / graph_wall,
-        "pairs_per_s": 1.0 / pair_s,
-        "pair_ms": pair_s * 1e3,
-        "pair_algorithmic_gbs": pair_bytes / pair_s / 1e9,
-        "snr": snr,
-        "kernels_ms_per_solve": {k: round(v["ms_total_per_solve"], 4) for k, v in per_kernel.items()},
-        "roofline": roof,
-    }
+    # host work first: worker processes are started before the GPU is touched
+    cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on the host (bounded sample)", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(w, gth)
+        print("[bench] timing the FP64 oracle on the host (bounded samples)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, gth)
+    batch_in = None
+    if not args.no_extra:
+        print(f"[bench] drawing the {args.batch_gathers} batched gathers", file=sys.stderr, flush=True)
+        batch_in = _draw_batch(args.batch_gathers)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    rec = headline(args, w, gth)
+    if cpu is not None:
+        rec["cpu_baseline"] = cpu
+    if batch_in is not None:
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        rec["batch512"] = batch_leg(*batch_in, steps=1, warmup=1)
+        del batch_in
+        torch.cuda.empty_cache()
+        print("[bench] asymptote-shifted workload", file=sys.stderr, flush=True)
+        rec["aashrt"] = aashrt_leg(steps=3, warmup=1, autotune=not args.no_autotune)
     print(json.dumps(rec), flush=True)
 
 

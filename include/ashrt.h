@@ -171,7 +171,12 @@ int ashrt_plan_create_tuned(const ashrt_desc *desc, const ashrt_tuning *tuning, 
  * inputs of the descriptor's geometry, and returns the fastest in *best
  * (and its time in *best_ms, may be NULL).  Allocates and frees its own
  * scratch device memory and synchronises `device`; results are cached per
- * geometry for the life of the process. */
+ * geometry for the life of the process.  The time includes the per-gather
+ * sums of the CG partials that a tiling with many model tiles moves into
+ * their own launches.  When the environment variable ASHRT_TUNE_CACHE names
+ * a file, results are also looked up in and appended to it, keyed by the
+ * device's architecture name (gcnArchName) and the geometry; an unreadable
+ * or unwritable file is ignored. */
 int ashrt_autotune(const ashrt_desc *desc, int device, int32_t repeats, ashrt_tuning *best, double *best_ms);
 
 void ashrt_plan_destroy(ashrt_plan *plan);

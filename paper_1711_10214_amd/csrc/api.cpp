@@ -15,6 +15,7 @@
 #include <mutex>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1572,6 +1573,45 @@ extern "C" int robust_invert_batched(const ashrt_batch_plan* plan, const irls_pa
 namespace {
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<ashrt_tuning, double>> g_tune_cache;
+
+// Optional on-disk cache of tuned tilings: when ASHRT_TUNE_CACHE names a
+// file, a result is looked up there (lines "<arch>|<geometry key> tm td
+// chunks ms") before timing, and new results are appended.  Keyed by the
+// device's architecture name, since tile timings do not carry across GPUs.
+static std::string tune_file() {
+  const char* p = std::getenv("ASHRT_TUNE_CACHE");
+  return (p && *p) ? std::string(p) : std::string();
+}
+
+static bool tune_file_lookup(const std::string& fkey, ashrt_tuning* t, double* ms) {
+  const std::string path = tune_file();
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char k[384];
+    int tm, td, ch;
+    double v;
+    if (std::sscanf(line, "%383s %d %d %d %lf", k, &tm, &td, &ch, &v) == 5 && fkey == k) {
+      *t = ashrt_tuning{tm, td, ch};
+      *ms = v;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_file_append(const std::string& fkey, const ashrt_tuning& t, double ms) {
+  const std::string path = tune_file();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %.6f\n", fkey.c_str(), t.tile_model, t.tile_data, t.nchunk, ms);
+  std::fclose(f);
+}
 }  // namespace
 
 extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeats, ashrt_tuning* best,
@@ -1597,8 +1637,28 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
   }
   DeviceGuard dg(device);
   if (!dg.ok) return fail(ASHRT_E_HIP, "cannot select the device");
+  std::string fkey;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(ASHRT_E_HIP, "cannot query the device");
+    std::string arch = prop.gcnArchName;
+    for (char& ch : arch)
+      if (ch == ' ' || ch == '|') ch = '_';
+    fkey = arch + "|" + std::string(std::strchr(key, ':') + 1);
+    ashrt_tuning ft;
+    double fms = 0.0;
+    if (tune_file_lookup(fkey, &ft, &fms)) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = {ft, fms};
+      *best = ft;
+      if (best_ms) *best_ms = fms;
+      return ASHRT_OK;
+    }
+  }
   const size_t nm = (size_t)z.P * z.nx * z.nt, nd = (size_t)z.nx * z.nt;
   float *m = nullptr, *d = nullptr, *m2 = nullptr;
+  double *part = nullptr, *scal = nullptr;  // CG partial sums and scalar block (see below)
+  size_t part_cap = 0;
   void* ws = nullptr;
   size_t ws_cap = 0;
   hipStream_t s = nullptr;
@@ -1608,13 +1668,15 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
     if (m) (void)hipFree(m);
     if (d) (void)hipFree(d);
     if (m2) (void)hipFree(m2);
+    if (part) (void)hipFree(part);
+    if (scal) (void)hipFree(scal);
     if (ws) (void)hipFree(ws);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
   };
   if (hipMalloc(&m, nm * 4) != hipSuccess || hipMalloc(&d, nd * 4) != hipSuccess ||
-      hipMalloc(&m2, nm * 4) != hipSuccess) {
+      hipMalloc(&m2, nm * 4) != hipSuccess || hipMalloc(&scal, kNScal * sizeof(double)) != hipSuccess) {
     cleanup();
     return fail(ASHRT_E_OOM, "autotune scratch allocation failed");
   }
@@ -1647,13 +1709,37 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
           }
           ws_cap = need;
         }
+        // A CG iteration also sums the per-tile partials of |q|^2 and |g|^2:
+        // inside the consuming transform for small plans, else by one
+        // k_sum_items launch each (sum_*_in_kernel).  Those launches are
+        // timed with the pair, on zeroed partials, so that a tiling whose
+        // tile count moves the sums out of the transforms pays for them.
+        const size_t npart = (size_t)std::max(P.n_xm, P.n_xd);
+        if (npart > part_cap) {
+          if (part) (void)hipFree(part);
+          part = nullptr;
+          part_cap = 0;
+          if (hipMalloc(&part, npart * sizeof(double)) != hipSuccess ||
+              hipMemsetAsync(part, 0, npart * sizeof(double), s) != hipSuccess) {
+            destroy_impl(P);
+            cleanup();
+            return fail(ASHRT_E_OOM, "autotune partial-sum allocation failed");
+          }
+          part_cap = npart;
+        }
+        auto sums = [&]() {
+          hipError_t e = hipSuccess;
+          if (!P.sum_data_in_kernel) e = launch_sum_items(P.d_gd, 1, part, 0, scal, SC_DELTA, s);
+          if (e == hipSuccess && !P.sum_model_in_kernel) e = launch_sum_items(P.d_gd, 1, part, 1, scal, SC_GNEW, s);
+          return e == hipSuccess;
+        };
         bool ok = forward_impl(P, m, d, nullptr, ws, ws_cap, s) == ASHRT_OK &&
-                  adjoint_impl(P, d, m2, nullptr, ws, ws_cap, s) == ASHRT_OK;
+                  adjoint_impl(P, d, m2, nullptr, ws, ws_cap, s) == ASHRT_OK && sums();
         std::vector<float> ts;
         for (int r = 0; ok && r < repeats; ++r) {
           ok = hipEventRecord(e0, s) == hipSuccess && forward_impl(P, m, d, nullptr, ws, ws_cap, s) == ASHRT_OK &&
-               adjoint_impl(P, d, m2, nullptr, ws, ws_cap, s) == ASHRT_OK && hipEventRecord(e1, s) == hipSuccess &&
-               hipEventSynchronize(e1) == hipSuccess;
+               adjoint_impl(P, d, m2, nullptr, ws, ws_cap, s) == ASHRT_OK && sums() &&
+               hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
           float ms = 0.f;
           if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
           ts.push_back(ms);
@@ -1673,6 +1759,7 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = {bt, best_t};
+    tune_file_append(fkey, bt, best_t);
   }
   *best = bt;
   if (best_ms) *best_ms = best_t;

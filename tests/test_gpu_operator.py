@@ -216,3 +216,30 @@ def test_autotune_is_cached_and_usable(A):
     assert t1["tile_model"] in (8, 16, 32) and t1["tile_data"] in (2, 4, 8) and 1 <= t1["nchunk"] <= 8
     plan = A.Plan(**kw, tuning="auto")
     assert plan.info["tile_model"] == t1["tile_model"] and plan.info["nchunk"] == t1["nchunk"]
+
+
+def test_autotune_file_cache(A, tmp_path, monkeypatch):
+    """With ASHRT_TUNE_CACHE set, a tuned tiling is appended to the file under
+    the device's architecture name, and an entry already in the file is
+    returned without timing (here one written by hand for a geometry this
+    process has not tuned)."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("ASHRT_TUNE_CACHE", str(path))
+    kw = geom_kwargs(192, 40, 0.004, 12.5, [1600.0, 2500.0, 3100.0], fmax=100.0)
+    t1 = A.autotune(**kw)
+    lines = path.read_text().splitlines()
+    print(f"[gpu] autotune file cache: {lines}", flush=True)
+    assert len(lines) == 1
+    key, tm, td, ch, ms = lines[0].split()
+    arch = key.split("|")[0]
+    assert arch.startswith("gfx")
+    assert (int(tm), int(td), int(ch)) == (t1["tile_model"], t1["tile_data"], t1["nchunk"])
+    # a geometry not tuned yet in this process, with a made-up entry
+    kw2 = geom_kwargs(176, 40, 0.004, 12.5, [1600.0, 2500.0, 3100.0], fmax=100.0)
+    g = oracle_geometry(kw2)
+    jlo, jhi = oracle.band(g)
+    fake = f"{arch}|{176},{40},{g.ntp},{g.nxp},{3},{4},{jlo},{jhi},0 32 8 2 9.5"
+    with open(path, "a") as f:
+        f.write(fake + "\n")
+    t2 = A.autotune(**kw2)
+    assert (t2["tile_model"], t2["tile_data"], t2["nchunk"]) == (32, 8, 2)
