@@ -192,6 +192,21 @@ int ashrt_workspace_bytes(const ashrt_plan *plan, int op, const irls_params *par
 int ashrt_forward(const ashrt_plan *plan, const float *m, float *d, const uint8_t *trace_mask,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operator as ashrt_forward, with the same kernels and results, but its
+ * workspace is a library-owned static device array of 96 MiB (one per GPU,
+ * held until the process ends; its address is resolved when a plan is
+ * created on that GPU).  Calls no hipMalloc/hipFree.  Returns
+ * ASHRT_E_WORKSPACE when the plan's forward workspace
+ * (ashrt_workspace_bytes(plan, ASHRT_OP_FORWARD, ...)) exceeds 96 MiB.
+ * Nothing in the array needs to start at zero.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must be serialised by the
+ * caller. */
+int ashrt_forward_noalloc(const ashrt_plan *plan, const float *m, float *d, const uint8_t *trace_mask,
+                          void *stream);
+
 /* m = L' S d  (Chapter 5 equation ch5_adj_operator; Chapter 6 equation
  * ch6_adj_operator), the exact transpose of ashrt_forward. */
 int ashrt_adjoint(const ashrt_plan *plan, const float *d, float *m, const uint8_t *trace_mask,

@@ -184,6 +184,17 @@ class Plan:
                                       _stream(self.device)), "ashrt_forward")
         return d
 
+    def forward_noalloc(self, m, out, mask=None):
+        """d = S L m through ashrt_forward_noalloc: the library's static
+        device scratch instead of a workspace (the caller passes the output;
+        nothing is allocated)."""
+        self._check_model(m)
+        self._check_data(out)
+        mk = self._mask(mask)
+        L.check(L.lib().ashrt_forward_noalloc(self._h, _ptr(m), _ptr(out), _ptr(mk), _stream(self.device)),
+                "ashrt_forward_noalloc")
+        return out
+
     def adjoint(self, d, mask=None, out=None):
         """m = L' S d."""
         self._check_data(d)

@@ -346,6 +346,34 @@ static void destroy_impl(PlanImpl& P) {
   }
 }
 
+// ------------------------------------------------------------ static scratch
+// Workspace of the allocation-free forward (ashrt_forward_noalloc): a
+// file-scope device array, one copy per GPU the library runs on, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// a device address: kernels get the address from hipGetSymbolAddress,
+// resolved once per device (with that device current) when a plan is
+// created there, and kept in g_scratch.
+constexpr size_t kStaticScratchBytes = (size_t)96 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch;  // device -> that device's copy of scratch
+
+// The calling thread's current device must be `device`.
+static int static_scratch_setup(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ASHRT_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch.emplace(device, p).first;
+  }
+  if (out) *out = it->second;
+  return ASHRT_OK;
+}
+
 // Build work lists and device tables for a set of gathers.
 static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImpl& P,
                        const ashrt_tuning* tn = nullptr) {
@@ -636,6 +664,11 @@ static int create_impl(const ashrt_desc* descs, int ngather, int device, PlanImp
     static hipError_t init_err = hipSuccess;
     std::call_once(once, [] { init_err = op_kernels_init(kMaxDynLds); });
     e = init_err;
+  }
+  if (e == hipSuccess && static_scratch_setup(device, nullptr) != ASHRT_OK) {
+    (void)hipSetDevice(prev);
+    destroy_impl(P);
+    return ASHRT_E_HIP;  // the message is already set
   }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
@@ -1511,6 +1544,25 @@ extern "C" int ashrt_forward(const ashrt_plan* plan, const float* m, float* d, c
                              size_t wsb, void* stream) {
   if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
   return forward_impl(plan->impl, m, d, mask, ws, wsb, stream);
+}
+
+extern "C" int ashrt_forward_noalloc(const ashrt_plan* plan, const float* m, float* d, const uint8_t* mask,
+                                     void* stream) {
+  if (!plan) return fail(ASHRT_E_INVALID_ARG, "plan is NULL");
+  const PlanImpl& P = plan->impl;
+  const size_t need = P.layout(ASHRT_OP_FORWARD, 2).total;
+  if (need > kStaticScratchBytes)
+    return fail(ASHRT_E_WORKSPACE, "the plan's forward needs " + std::to_string(need) +
+                                       " bytes of scratch; the allocation-free entry point has " +
+                                       std::to_string(kStaticScratchBytes) + " (use ashrt_forward with a workspace)");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(P.device);
+    if (it != g_scratch.end()) ws = it->second;
+  }
+  if (!ws) return fail(ASHRT_E_HIP, "no static scratch address for the plan's device");
+  return forward_impl(P, m, d, mask, ws, kStaticScratchBytes, stream);
 }
 
 extern "C" int ashrt_adjoint(const ashrt_plan* plan, const float* d, float* m, const uint8_t* mask, void* ws,
