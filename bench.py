@@ -513,17 +513,20 @@ def run_warmstart(args):
     """Learned warm start against the plain zero start on the same GPU: CG
     iterations and wall time to reach the plain method's final separated-
     signal SNR (minus 0.05 dB) on held-out gathers drawn like the
-    production gather."""
+    production gather.  Training labels are streamed: host workers draw
+    gathers while the GPU labels them (plain 10 x 20 solves) into a rolling
+    buffer and trains on it."""
+    import multiprocessing as mp
     import numpy as np
-    from concurrent.futures import ProcessPoolExecutor
     base = "crg-1024x256-nv32"
     n_train, n_held = args.train_gathers, args.heldout_gathers
+    # host workers start before the GPU is touched; they keep drawing the
+    # training gathers while the GPU labels and trains
+    pool = mp.get_context("fork").Pool(processes=max(1, min(16, os.cpu_count() or 1) - 1))
     t0 = time.perf_counter()
-    # draw the gathers on host worker processes before the GPU is touched
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        train = [g for g, _ in ex.map(_gen_gather, [(base, 1_000_000 + i) for i in range(n_train)])]
-        held = list(ex.map(_gen_gather, [(base, 2_000_000 + i) for i in range(n_held)]))
+    held = pool.map(_gen_gather, [(base, 2_000_000 + i) for i in range(n_held)])
     t_gen = time.perf_counter() - t0
+    train_iter = (g for g, _ in pool.imap(_gen_gather, [(base, 1_000_000 + i) for i in range(n_train)], 8))
     import torch
     import paper_1711_10214_amd as A
     from paper_1711_10214_amd import warmstart as WS
@@ -532,32 +535,26 @@ def run_warmstart(args):
     w = workload(base)
     plan = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
     prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
-    print(f"[bench] warm start: labelling {n_train} gathers", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lab = WS.make_labels(plan, train, prm)
-    torch.cuda.synchronize()
-    t_lab = time.perf_counter() - t0
     net = A.UNet(w.npanel, base=16)
     net.init_params(seed=0)
-    print(f"[bench] warm start: training {args.epochs} epochs", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    losses = WS.train(net, lab, epochs=args.epochs, batch=args.batch, tp=A.TrainParams(lr=1e-3), seed=0,
-                      log_every=max(1, n_train // args.batch))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del lab
+    print(f"[bench] warm start: streaming {n_train} training gathers (buffer {args.ws_buffer})",
+          file=sys.stderr, flush=True)
+    ws = WS.train_streaming(plan, net, train_iter, n_train, prm, A.TrainParams(lr=1e-3), buffer=args.ws_buffer,
+                            chunk=128, passes=args.passes, batch=args.batch, seed=0, log_every=500)
+    pool.close()
+    pool.join()
+    torch.cuda.empty_cache()
     # one warm-up of each path
     d0 = torch.tensor(held[0][0], device="cuda")
     WS.outer_to_target(plan, d0, held[0][1], 1e9, prm, max_outer=1)
-    WS.outer_to_target(plan, d0, held[0][1], 1e9, prm, net=net, max_outer=1)
+    WS.outer_to_target(plan, d0, held[0][1], 1e9, prm, ws=ws, max_outer=1)
     rows = []
     for i, (g, clean) in enumerate(held):
         d = torch.tensor(g, device="cuda")
         _, d_rec, _ = plan.robust_invert(d, prm, want_report=False)
         target = WS.q_db(clean, d_rec.cpu().numpy())
         kp, qp, tp_, _ = WS.outer_to_target(plan, d, clean, target, prm)
-        kw, qw, tw, start = WS.outer_to_target(plan, d, clean, target, prm, net=net)
+        kw, qw, tw, start = WS.outer_to_target(plan, d, clean, target, prm, ws=ws)
         rows.append((target, kp, tp_, kw, tw, start, qw))
         if i % 16 == 0:
             print(f"[bench] held-out {i}: target {target:.2f} dB plain k={kp} warm k={kw} ({start})",
@@ -567,6 +564,8 @@ def run_warmstart(args):
     tp_ = np.array([r[2] for r in rows])
     tw = np.array([r[4] for r in rows])
     reached = sum(r[3] is not None for r in rows)
+    starts = [r[5] for r in rows]
+    losses = ws.stats.get("losses", [])
     rec = {
         "metric": "learned warm start: wall time to the plain IRLS-CG separated-signal SNR, plain / warm",
         "value": float(np.mean(tp_) / np.mean(tw)),
@@ -574,14 +573,17 @@ def run_warmstart(args):
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16 network, f32 solver",
         "data": "synthetic",
         "config": {"workload": "warmstart-crg-1024x256-nv32", "train_gathers": n_train,
-                   "heldout_gathers": n_held, "epochs": args.epochs, "batch": args.batch,
-                   "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner},
+                   "label_buffer": args.ws_buffer, "passes": args.passes, "heldout_gathers": n_held,
+                   "batch": args.batch, "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner,
+                   "model_label_scale": ws.m_scale},
         "plain": {"cg_iterations_mean": float(np.mean(kp) * w.n_inner), "outer_median": float(np.median(kp)),
                   "ms_mean": float(np.mean(tp_) * 1e3)},
         "warm": {"cg_iterations_mean": float(np.mean(kw) * w.n_inner), "outer_median": float(np.median(kw)),
                  "ms_mean": float(np.mean(tw) * 1e3), "reached_target": reached,
-                 "model_start_rate": float(np.mean([r[5] == "model+weights" for r in rows]))},
-        "seconds": {"generate": t_gen, "label": t_lab, "train": t_train},
+                 "model_start_rate": float(np.mean([s_ == "model+weights" for s_ in starts])),
+                 "fallback_rate": float(np.mean([s_ != "model+weights" for s_ in starts]))},
+        "seconds": {"generate_heldout": t_gen, "label": ws.stats.get("label_s"), "train": ws.stats.get("train_s")},
+        "train_steps": ws.stats.get("steps"),
         "train_loss": [losses[0], losses[-1]] if losses else None,
     }
     print(json.dumps(rec), flush=True)
@@ -826,9 +828,10 @@ def main():
                     help="skip the batched and asymptote-shifted workloads after the headline solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB device copy (for HBM counter calibration)")
-    ap.add_argument("--train-gathers", type=int, default=1024, help="warm-start workload: training gathers")
+    ap.add_argument("--train-gathers", type=int, default=4096, help="warm-start workload: training gathers (streamed)")
+    ap.add_argument("--ws-buffer", type=int, default=512, help="warm-start workload: resident label buffer")
+    ap.add_argument("--passes", type=float, default=4.0, help="warm-start workload: expected uses of each label")
     ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
-    ap.add_argument("--epochs", type=int, default=12, help="warm-start workload: training epochs")
     ap.add_argument("--batch", type=int, default=4, help="warm-start and unet workloads: batch size")
     ap.add_argument("--batch-gathers", type=int, default=512, help="batched workload: number of gathers")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling rule")

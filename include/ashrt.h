@@ -207,6 +207,29 @@ int ashrt_forward(const ashrt_plan *plan, const float *m, float *d, const uint8_
 int ashrt_forward_noalloc(const ashrt_plan *plan, const float *m, float *d, const uint8_t *trace_mask,
                           void *stream);
 
+/* Learned warm start support (an initial model m0 and initial residual
+ * weights w0 for robust_invert, predicted by the U-Net of unet.h).  All
+ * pointers are device pointers; calls are stream-ordered; nothing is
+ * allocated.
+ *
+ * ashrt_vec_stats: out[0] = sum_i |a_i - alpha b_i|^p (p = 1 or 2),
+ * out[1] = sum_i a_i b_i, out[2] = sum_i b_i^2, over n elements, summed in
+ * FP64 in a fixed order (deterministic); b may be NULL (a zero vector).
+ * out: 3 doubles.  Serves the gather's RMS scale (alpha = 0, p = 2), the
+ * least-squares step length of a predicted model along L m0 (out[1] /
+ * out[2] with b = L m0) and the l_p misfit that decides whether the
+ * prediction replaces the zero start (Chapter 4's misfit, equation
+ * ch4_cost_fn with mu = 0). */
+int ashrt_vec_stats(const float *a, const float *b, int64_t n, double alpha, int32_t p, double *out, void *stream);
+
+/* w_i = sqrt(eps / max(|d_i - d_rec_i|, eps)) over n elements, eps > 0: the
+ * final l1 IRLS residual weight of a solve (Chapter 4, W_r with p = 1),
+ * scaled into (0, 1] -- the training label of the predicted weights. */
+int ashrt_weight_target(const float *d, const float *d_rec, int64_t n, double eps, float *w, void *stream);
+
+/* y = s x over n elements (y may be x). */
+int ashrt_vec_scale(const float *x, int64_t n, double s, float *y, void *stream);
+
 /* m = L' S d  (Chapter 5 equation ch5_adj_operator; Chapter 6 equation
  * ch6_adj_operator), the exact transpose of ashrt_forward. */
 int ashrt_adjoint(const ashrt_plan *plan, const float *d, float *m, const uint8_t *trace_mask,

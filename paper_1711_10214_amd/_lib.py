@@ -132,6 +132,9 @@ def lib():
         "ashrt_workspace_bytes": (C.c_int, [vp, C.c_int, P_prm, C.POINTER(sz)]),
         "ashrt_forward": (C.c_int, [vp, vp, vp, vp, vp, sz, vp]),
         "ashrt_forward_noalloc": (C.c_int, [vp, vp, vp, vp, vp]),
+        "ashrt_vec_stats": (C.c_int, [vp, vp, C.c_int64, C.c_double, C.c_int32, vp, vp]),
+        "ashrt_weight_target": (C.c_int, [vp, vp, C.c_int64, C.c_double, vp, vp]),
+        "ashrt_vec_scale": (C.c_int, [vp, C.c_int64, C.c_double, vp, vp]),
         "ashrt_adjoint": (C.c_int, [vp, vp, vp, vp, vp, sz, vp]),
         "robust_invert": (C.c_int, [vp, P_prm, vp, vp, vp, vp, vp, P_rep, vp, sz, vp]),
         "ashrt_batch_plan_create": (C.c_int, [P_desc, i32, C.c_int, C.POINTER(vp)]),

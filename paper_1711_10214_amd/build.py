@@ -16,7 +16,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libashrt.so")
 ARCH = os.environ.get("ASHRT_ARCH", "gfx950")
 
-SOURCES = ["op_kernels.hip", "solver_kernels.hip", "td_kernels.hip", "survey_kernels.hip", "unet_kernels.hip", "api.cpp", "unet.cpp"]
+SOURCES = ["op_kernels.hip", "solver_kernels.hip", "td_kernels.hip", "survey_kernels.hip", "unet_kernels.hip",
+           "vec_kernels.hip", "api.cpp", "unet.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
@@ -43,7 +44,7 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -1818,6 +1818,36 @@ extern "C" int ashrt_autotune(const ashrt_desc* desc, int device, int32_t repeat
   return ASHRT_OK;
 }
 
+// ------------------------------------------------------------ warm-start support
+extern "C" int ashrt_vec_stats(const float* a, const float* b, int64_t n, double alpha, int32_t p, double* out,
+                               void* stream) {
+  if (!a || !out) return fail(ASHRT_E_INVALID_ARG, "a and out must be non-NULL");
+  if (n < 0) return fail(ASHRT_E_INVALID_ARG, "n must be >= 0");
+  if (p != 1 && p != 2) return fail(ASHRT_E_INVALID_ARG, "p must be 1 or 2");
+  if (!std::isfinite(alpha)) return fail(ASHRT_E_INVALID_ARG, "alpha must be finite");
+  HIP_TRY(launch_vec_stats(a, b, n, alpha, p, out, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_weight_target(const float* d, const float* d_rec, int64_t n, double eps, float* w,
+                                   void* stream) {
+  if (!d || !d_rec || !w) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  if (n < 0) return fail(ASHRT_E_INVALID_ARG, "n must be >= 0");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ASHRT_E_INVALID_ARG, "eps must be finite and > 0");
+  if (n == 0) return ASHRT_OK;
+  HIP_TRY(launch_weight_target(d, d_rec, n, (float)eps, w, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
+extern "C" int ashrt_vec_scale(const float* x, int64_t n, double s, float* y, void* stream) {
+  if (!x || !y) return fail(ASHRT_E_INVALID_ARG, "NULL argument");
+  if (n < 0) return fail(ASHRT_E_INVALID_ARG, "n must be >= 0");
+  if (!std::isfinite(s)) return fail(ASHRT_E_INVALID_ARG, "s must be finite");
+  if (n == 0) return ASHRT_OK;
+  HIP_TRY(launch_vec_scale(x, n, (float)s, y, (hipStream_t)stream));
+  return ASHRT_OK;
+}
+
 // ------------------------------------------------------------ survey cubes
 extern "C" int ashrt_blend(const float* D, int32_t ns, int32_t nr, int32_t nt, const int32_t* fire, float* b,
                            int32_t nrec, void* stream) {

@@ -196,6 +196,12 @@ struct TdArgs {
 };
 hipError_t launch_td(const TdArgs& a, bool forward, hipStream_t s);
 
+// vec_kernels.hip
+hipError_t launch_vec_stats(const float* a, const float* b, long long n, double alpha, int p, double* out,
+                            hipStream_t s);
+hipError_t launch_weight_target(const float* d, const float* drec, long long n, float eps, float* w, hipStream_t s);
+hipError_t launch_vec_scale(const float* x, long long n, float sc, float* y, hipStream_t s);
+
 // Blending / pseudo-deblending / re-sort of survey cubes (survey_kernels.hip).
 hipError_t launch_blend(const float* D, int ns, int nr, int nt, const int* fire, float* b, int nrec, hipStream_t s);
 hipError_t launch_deblend(const float* b, int ns, int nr, int nt, const int* fire, int nrec, float* out, int rmaj,
