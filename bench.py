@@ -593,14 +593,15 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
 
 
 def _unet_conv_flops(H, W, base=16, cin=1):
-    """Algorithmic FLOPs of the U-Net's fourteen 3x3 convolutions for one
+    """Algorithmic FLOPs of the U-Net's eighteen 3x3 convolutions for one
     sample at H x W (2 * 9 * ci * co per output pixel): forward, input
     gradient (every layer but the first, whose input is the data) and weight
-    gradient.  Same layer list as the library's graph (four levels, two
+    gradient.  Same layer list as the library's graph (five levels, two
     convolutions each, skip concatenations on the decoder side)."""
-    c1, c2, c3, c4 = base, 2 * base, 4 * base, 8 * base
-    spec = [(cin, c1, 0), (c1, c1, 0), (c1, c2, 1), (c2, c2, 1), (c2, c3, 2), (c3, c3, 2), (c3, c4, 3),
-            (c4, c4, 3), (c4 + c3, c3, 2), (c3, c3, 2), (c3 + c2, c2, 1), (c2, c2, 1), (c2 + c1, c1, 0),
+    c1, c2, c3, c4, c5 = base, 2 * base, 4 * base, 8 * base, 8 * base
+    spec = [(cin, c1, 0), (c1, c1, 0), (c1, c2, 1), (c2, c2, 1), (c2, c3, 2), (c3, c3, 2),
+            (c3, c4, 3), (c4, c4, 3), (c4, c5, 4), (c5, c5, 4), (c5 + c4, c4, 3), (c4, c4, 3),
+            (c4 + c3, c3, 2), (c3, c3, 2), (c3 + c2, c2, 1), (c2, c2, 1), (c2 + c1, c1, 0),
             (c1, c1, 0)]
     fwd = igrad = 0
     for i, (ci, co, lev) in enumerate(spec):

@@ -1,18 +1,21 @@
 /* libashrt: learned warm start for the robust inversion.
  *
- * A four-level 2-D U-Net maps a blended receiver gather to an initial Radon
- * model m0 (one channel per velocity panel) and initial residual weights w0,
- * which robust_invert (ashrt.h) takes as its warm start (thesis Chapter 4:
- * the IRLS outer loop starts from a model and a residual weighting; a good
- * start shortens it).  The network is not in the thesis.
+ * A 2-D U-Net with four 2x down-samplings maps a blended receiver gather to
+ * an initial Radon model m0 (one channel per velocity panel) and initial
+ * residual weights w0, which robust_invert (ashrt.h) takes as its warm start
+ * (thesis Chapter 4: the IRLS outer loop starts from a model and a residual
+ * weighting; a good start shortens it).  The network is not in the thesis.
  *
- * Architecture (c = base * (1, 2, 4, 8); every 3x3 convolution has zero
+ * Architecture (c = base * (1, 2, 4, 8, 8); every 3x3 convolution has zero
  * padding, a bias and a ReLU):
  *   enc1a Cin->c1, enc1b c1->c1 | 2x2 mean pool | enc2a c1->c2, enc2b |
- *   pool | enc3a c2->c3, enc3b | pool | bota c3->c4, botb |
- *   dec3a [nearest 2x upsample(botb), enc3b] -> c3, dec3b |
+ *   pool | enc3a c2->c3, enc3b | pool | enc4a c3->c4, enc4b |
+ *   pool | bota c4->c5, botb |
+ *   dec4a [nearest 2x upsample(botb), enc4b] -> c4, dec4b |
+ *   dec3a [up(dec4b), enc3b] -> c3, dec3b |
  *   dec2a [up(dec3b), enc2b] -> c2, dec2b | dec1a [up(dec2b), enc1b] -> c1,
  *   dec1b | head_m 1x1 c1 -> P (linear) | head_w 1x1 c1 -> 1, sigmoid.
+ * With base 16 and P = 32 that is 1,225,345 parameters.
  * Parameters: one flat FP32 vector, conv by conv in that order, weight
  * [co][ci][kh][kw] then bias [co].
  *
@@ -25,7 +28,7 @@
  *   x        [B][H][W]     FP32  network input (the caller scales the gather)
  *   y_model  [B][P][H][W]  FP32  predicted model / scale
  *   y_w      [B][H][W]     FP32  predicted weights in (0, 1)
- * H and W must be multiples of 8.  Every call is stream-ordered on `stream`;
+ * H and W must be multiples of 16.  Every call is stream-ordered on `stream`;
  * none allocates device memory after unet_create (the caller passes a
  * workspace of unet_workspace_bytes).  Return codes are the ASHRT_* status
  * codes of ashrt.h; ashrt_last_error() describes the last failure.

@@ -53,7 +53,7 @@ int fail(int code, const std::string& m) { return ashrt::set_error(code, m); }
       return fail(ASHRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kNConv = 14;
+constexpr int kNConv = 18;
 constexpr int kBiasBlocks = 1024;
 constexpr int kWgradTargetGroups = 1024;
 
@@ -99,25 +99,30 @@ struct unet_net {
 namespace {
 
 void build_graph(unet_net& n) {
-  const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
+  // four 2x down-samplings (levels 0..4), channels c1..c4 and a c4-wide bottleneck
+  const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base, c5 = 8 * n.base;
   struct Spec {
     int ci, co, level, srcA, modeA, srcB;
   };
   const Spec S[kNConv] = {
-      {n.cin, c1, 0, -1, 0, -1},  // enc1a
-      {c1, c1, 0, 0, 0, -1},      // enc1b
-      {c1, c2, 1, 1, 2, -1},      // enc2a (pool)
-      {c2, c2, 1, 2, 0, -1},      // enc2b
-      {c2, c3, 2, 3, 2, -1},      // enc3a
-      {c3, c3, 2, 4, 0, -1},      // enc3b
-      {c3, c4, 3, 5, 2, -1},      // bota
-      {c4, c4, 3, 6, 0, -1},      // botb
-      {c4 + c3, c3, 2, 7, 1, 5},  // dec3a [up(botb), enc3b]
-      {c3, c3, 2, 8, 0, -1},      // dec3b
-      {c3 + c2, c2, 1, 9, 1, 3},  // dec2a [up(dec3b), enc2b]
-      {c2, c2, 1, 10, 0, -1},     // dec2b
-      {c2 + c1, c1, 0, 11, 1, 1}, // dec1a [up(dec2b), enc1b]
-      {c1, c1, 0, 12, 0, -1},     // dec1b
+      {n.cin, c1, 0, -1, 0, -1},    // enc1a
+      {c1, c1, 0, 0, 0, -1},        // enc1b
+      {c1, c2, 1, 1, 2, -1},        // enc2a (pool)
+      {c2, c2, 1, 2, 0, -1},        // enc2b
+      {c2, c3, 2, 3, 2, -1},        // enc3a
+      {c3, c3, 2, 4, 0, -1},        // enc3b
+      {c3, c4, 3, 5, 2, -1},        // enc4a
+      {c4, c4, 3, 6, 0, -1},        // enc4b
+      {c4, c5, 4, 7, 2, -1},        // bota
+      {c5, c5, 4, 8, 0, -1},        // botb
+      {c5 + c4, c4, 3, 9, 1, 7},    // dec4a [up(botb), enc4b]
+      {c4, c4, 3, 10, 0, -1},       // dec4b
+      {c4 + c3, c3, 2, 11, 1, 5},   // dec3a [up(dec4b), enc3b]
+      {c3, c3, 2, 12, 0, -1},       // dec3b
+      {c3 + c2, c2, 1, 13, 1, 3},   // dec2a [up(dec3b), enc2b]
+      {c2, c2, 1, 14, 0, -1},       // dec2b
+      {c2 + c1, c1, 0, 15, 1, 1},   // dec1a [up(dec2b), enc1b]
+      {c1, c1, 0, 16, 0, -1},       // dec1b
   };
   long long off = 0, pk = 0;
   n.L.clear();
@@ -213,8 +218,8 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
 
 int check_shape(const unet_net* n, int B, int H, int W) {
   if (!n) return fail(ASHRT_E_INVALID_ARG, "net is NULL");
-  if (B < 1 || H < 8 || W < 8 || (H % 8) || (W % 8))
-    return fail(ASHRT_E_INVALID_ARG, "B >= 1 and H, W positive multiples of 8 required");
+  if (B < 1 || H < 16 || W < 16 || (H % 16) || (W % 16))
+    return fail(ASHRT_E_INVALID_ARG, "B >= 1 and H, W positive multiples of 16 required");
   return ASHRT_OK;
 }
 

@@ -34,7 +34,8 @@ class TrainParams:
 
 
 class UNet:
-    """Four-level U-Net: gather [H][W] -> model [P][H][W] and weights [H][W]."""
+    """U-Net with four 2x down-samplings: gather [H][W] -> model [P][H][W] and weights [H][W]
+    (H, W multiples of 16)."""
 
     def __init__(self, pout, base=16, cin=1, device=0):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
@@ -61,8 +62,10 @@ class UNet:
         """He-normal weights (fan-in), zero biases, drawn on the host."""
         rng = np.random.default_rng(seed)
         c1, c2, c3, c4 = (self.base * f for f in (1, 2, 4, 8))
+        c5 = c4
         convs = [(self.cin, c1, 3), (c1, c1, 3), (c1, c2, 3), (c2, c2, 3), (c2, c3, 3), (c3, c3, 3),
-                 (c3, c4, 3), (c4, c4, 3), (c4 + c3, c3, 3), (c3, c3, 3), (c3 + c2, c2, 3), (c2, c2, 3),
+                 (c3, c4, 3), (c4, c4, 3), (c4, c5, 3), (c5, c5, 3), (c5 + c4, c4, 3), (c4, c4, 3),
+                 (c4 + c3, c3, 3), (c3, c3, 3), (c3 + c2, c2, 3), (c2, c2, 3),
                  (c2 + c1, c1, 3), (c1, c1, 3), (c1, self.pout, 1), (c1, 1, 1)]
         parts = []
         for ci, co, k in convs:

@@ -51,9 +51,9 @@ def test_network_gradient_matches_finite_differences():
     spec = U.UNetSpec(cin=1, pout=3, base=2)
     rng = np.random.default_rng(3)
     theta = U.init_params(spec, rng) + 0.05 * rng.standard_normal(spec.n_params())
-    x = rng.standard_normal((2, 1, 8, 16))
-    t_m = rng.standard_normal((2, 3, 8, 16))
-    t_w = rng.uniform(0.1, 1.0, (2, 8, 16))
+    x = rng.standard_normal((2, 1, 16, 16))
+    t_m = rng.standard_normal((2, 3, 16, 16))
+    t_w = rng.uniform(0.1, 1.0, (2, 16, 16))
     L, g = U.loss_and_grad(spec, theta, x, t_m, t_w, lam_w=0.7)
     assert g.shape == theta.shape
     idx = rng.choice(theta.size, 60, replace=False)
@@ -81,6 +81,49 @@ def test_param_count_and_layout():
     assert np.array_equal(U.pack(spec, U.unpack(spec, theta)), theta)
     assert U.unpack(spec, theta)["enc1a"][0].shape == (16, 1, 3, 3)
     assert U.unpack(spec, theta)["dec3a"][0].shape == (64, 192, 3, 3)
+    assert U.unpack(spec, theta)["dec4a"][0].shape == (128, 256, 3, 3)
+    assert U.unpack(spec, theta)["botb"][0].shape == (128, 128, 3, 3)
+    assert n == 1_225_345
+
+
+def test_bf16_round_matches_torch_bfloat16():
+    """The precision model's rounding against torch's FP32 -> bfloat16
+    conversion (round to nearest, ties to even) on the CPU: random values
+    over many binades, exact ties, values already on the grid, subnormals."""
+    import torch
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(20000) * np.exp2(rng.integers(-40, 40, 20000))
+    grid = rng.integers(-2**15, 2**15, 4000).astype(np.int64)
+    on = np.ldexp(128.0 + (np.abs(grid) % 128), rng.integers(-20, 20, 4000)) * np.sign(grid + 0.5)
+    ties = on + np.ldexp(1.0, np.frexp(on)[1] - 9) * np.sign(on)      # half an ulp above a grid value
+    sub = rng.standard_normal(2000) * 2.0 ** -130
+    for a in (v, on, ties, sub):
+        a32 = a.astype(np.float32)
+        ref = torch.from_numpy(a32).to(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(U.bf16_round(a32.astype(np.float64)), ref)
+    assert np.array_equal(U.bf16_round(on), on)
+    # a tie goes to the even neighbour: 1 + 2^-8 -> 1, 1 + 3 * 2^-8 -> 1 + 2^-6
+    assert U.bf16_round(np.array([1 + 2.0 ** -8]))[0] == 1.0
+    assert U.bf16_round(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6
+
+
+def test_bf16_precision_model_is_a_small_perturbation():
+    """Rounding the operands moves the outputs by a BF16-sized amount (a
+    few units of 2^-9 relative), never zero and never O(1)."""
+    spec = U.UNetSpec(cin=1, pout=3, base=4)
+    rng = np.random.default_rng(8)
+    theta = U.init_params(spec, rng) + 0.05 * rng.standard_normal(spec.n_params())
+    x = rng.standard_normal((1, 1, 32, 48))
+    y0, w0, _ = U.forward(spec, theta, x)
+    y1, w1, _ = U.forward(spec, theta, x, bf16=True)
+    e = np.linalg.norm(y1 - y0) / np.linalg.norm(y0)
+    assert 2.0 ** -12 < e < 2.0 ** -4
+    t_m = rng.standard_normal(y0.shape)
+    t_w = rng.uniform(0.1, 1.0, w0.shape)
+    L0, g0 = U.loss_and_grad(spec, theta, x, t_m, t_w)
+    L1, g1 = U.loss_and_grad(spec, theta, x, t_m, t_w, bf16=True)
+    eg = np.linalg.norm(g1 - g0) / np.linalg.norm(g0)
+    assert 2.0 ** -12 < eg < 2.0 ** -3
 
 
 def test_adamw_closed_form():
