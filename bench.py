@@ -559,6 +559,22 @@ def run_warmstart(args):
         if i % 16 == 0:
             print(f"[bench] held-out {i}: target {target:.2f} dB plain k={kp} warm k={kw} ({start})",
                   file=sys.stderr, flush=True)
+    # separated-signal SNR after each outer iteration, plain and warm
+    # started, with the weights-only start as the ablation of the model
+    curves = {"plain": [], "model+weights": [], "weights only": []}
+    for g, clean in held[:args.ws_curves]:
+        d = torch.tensor(g, device="cuda")
+        for kind in curves:
+            qs = []
+            for k in range(1, w.n_outer + 1):
+                pk = A.Params(p=w.p, q=w.q, n_outer=k, n_inner=w.n_inner)
+                if kind == "plain":
+                    _, d_rec, _ = plan.robust_invert(d, pk, want_report=False)
+                else:
+                    _, d_rec, _, _ = WS.warm_solve(plan, ws, d, pk, use_model=(kind == "model+weights"))
+                qs.append(WS.q_db(clean, d_rec.cpu().numpy()))
+            curves[kind].append(qs)
+    q_by_outer = {k: np.mean(np.array(v), axis=0).tolist() for k, v in curves.items() if v}
     kp = np.array([r[1] or 99 for r in rows], float)
     kw = np.array([r[3] or 99 for r in rows], float)
     tp_ = np.array([r[2] for r in rows])
@@ -583,8 +599,70 @@ def run_warmstart(args):
                  "model_start_rate": float(np.mean([s_ == "model+weights" for s_ in starts])),
                  "fallback_rate": float(np.mean([s_ != "model+weights" for s_ in starts]))},
         "seconds": {"generate_heldout": t_gen, "label": ws.stats.get("label_s"), "train": ws.stats.get("train_s")},
+        "q_r_by_outer_db": {"gathers": min(args.ws_curves, n_held), **q_by_outer},
         "train_steps": ws.stats.get("steps"),
         "train_loss": [losses[0], losses[-1]] if losses else None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def run_separation(args):
+    """What limits the separated-signal SNR of the production gather
+    (--workload separation): Q_R after each outer iteration of the plain
+    solve; Q_R on the interfered and on the clean traces separately; the same
+    solver fitting the clean gather alone (no interference: the operator's
+    own limit); the non-robust l2 solve; and the solves with the Ricker
+    wavelet's amplitude spectrum as Chapter 4's wavelet operator C."""
+    import numpy as np
+    import torch
+    import paper_1711_10214_amd as A
+    from synth import make_gather, workload
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    w = workload("crg-1024x256-nv32")
+    gth = make_gather(w)
+    dev = torch.device("cuda", 0)
+    plan = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
+    ntp = plan.info["ntp"]
+    f = np.arange(ntp // 2 + 1) / (ntp * w.dt)
+    ric = (f / w.ricker_hz) ** 2 * np.exp(-(f / w.ricker_hz) ** 2)   # Ricker amplitude spectrum
+    ric /= ric.max()
+    plan_c = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax, wavelet=ric)
+    d_blend = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
+    d_clean = torch.tensor(gth.d_clean, dtype=torch.float32, device=dev)
+    hit = np.zeros(gth.nx, bool)
+    hit[gth.interfered] = True
+
+    def solve(pl, d, k, p=w.p):
+        prm = A.Params(p=p, q=w.q, n_outer=k, n_inner=w.n_inner)
+        _, d_rec, _ = pl.robust_invert(d, prm, want_report=False)
+        return d_rec.cpu().numpy().astype(np.float64)
+
+    def q(est, rows=None):
+        c = gth.d_clean if rows is None else gth.d_clean[rows]
+        e = est if rows is None else est[rows]
+        return _q_db(c, e)
+
+    solve(plan, d_blend, 1)   # warm-up
+    by_outer = [q(solve(plan, d_blend, k)) for k in range(1, w.n_outer + 1)]
+    final = solve(plan, d_blend, w.n_outer)
+    final_c = solve(plan_c, d_blend, w.n_outer)
+    rec = {
+        "metric": "separated-signal SNR Q_R of the production gather under controlled changes (dB)",
+        "value": by_outer[-1], "unit": "dB", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "separation-crg-1024x256-nv32", "p": w.p, "q": w.q, "n_outer": w.n_outer,
+                   "n_inner": w.n_inner, "interfered_traces": int(hit.sum()), "nx": gth.nx},
+        "q_pd_db": q(gth.d_blend),
+        "q_r_by_outer_db": by_outer,
+        "q_r_interfered_traces_db": q(final, hit),
+        "q_r_clean_traces_db": q(final, ~hit),
+        "q_pd_interfered_traces_db": q(gth.d_blend, hit),
+        "clean_gather_fit_db": q(solve(plan, d_clean, w.n_outer)),
+        "clean_gather_fit_l2_db": q(solve(plan, d_clean, w.n_outer, p=2)),
+        "blended_l2_solve_db": q(solve(plan, d_blend, w.n_outer, p=2)),
+        "wavelet_c": {"q_r_db": q(final_c), "q_r_interfered_traces_db": q(final_c, hit),
+                      "q_r_clean_traces_db": q(final_c, ~hit),
+                      "clean_gather_fit_db": q(solve(plan_c, d_clean, w.n_outer))},
     }
     print(json.dumps(rec), flush=True)
 
@@ -833,6 +911,8 @@ def main():
     ap.add_argument("--ws-buffer", type=int, default=512, help="warm-start workload: resident label buffer")
     ap.add_argument("--passes", type=float, default=4.0, help="warm-start workload: expected uses of each label")
     ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
+    ap.add_argument("--ws-curves", type=int, default=16,
+                    help="warm-start workload: held-out gathers for the SNR-by-outer-iteration curves")
     ap.add_argument("--batch", type=int, default=4, help="warm-start and unet workloads: batch size")
     ap.add_argument("--batch-gathers", type=int, default=512, help="batched workload: number of gathers")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling rule")
@@ -855,6 +935,8 @@ def main():
         return run_survey(args)
     if args.workload == "unet":
         return run_unet(args)
+    if args.workload == "separation":
+        return run_separation(args)
 
     from synth import make_gather, workload
     w = workload(args.workload)

@@ -230,19 +230,23 @@ def lp_misfit(plan: Plan, d: torch.Tensor, m: torch.Tensor, p: int) -> float:
     return vec_stats(d, y, 1.0, p)[0]
 
 
-def warm_solve(plan: Plan, ws: WarmStart, d: torch.Tensor, params: Params, use_weights: bool = True):
+def warm_solve(plan: Plan, ws: WarmStart, d: torch.Tensor, params: Params, use_weights: bool = True,
+               use_model: bool = True):
     """Warm-started robust solve.  The predicted model, scaled by its
     least-squares step length, is kept only if it fits the data better than
     m = 0 in the l_p misfit; otherwise the solve starts from zero, with the
-    predicted weights if use_weights.  Returns (m, d_rec, report, start) with
+    predicted weights if use_weights.  use_model False skips the model
+    (weights only: an ablation).  Returns (m, d_rec, report, start) with
     start "model+weights" ("model"), "weights" or "plain"."""
     m0, w0 = predict(ws, d)
-    y = plan.forward(m0)
-    _, dy, yy = vec_stats(d, y, 1.0, params.p)
-    alpha = max(dy / yy, 0.0) if yy > 0 else 0.0
-    fit = vec_stats(d, y, alpha, params.p)[0]
-    zero = vec_stats(d, None, 0.0, params.p)[0]
     w = w0.contiguous() if use_weights else None
+    alpha, fit, zero = 0.0, 0.0, 0.0
+    if use_model:
+        y = plan.forward(m0)
+        _, dy, yy = vec_stats(d, y, 1.0, params.p)
+        alpha = max(dy / yy, 0.0) if yy > 0 else 0.0
+        fit = vec_stats(d, y, alpha, params.p)[0]
+        zero = vec_stats(d, None, 0.0, params.p)[0]
     if alpha > 0 and fit < zero:
         vec_scale(m0, alpha, m0)
         m, d_rec, rep = plan.robust_invert(d, params, m0=m0, w0=w)
