@@ -858,11 +858,18 @@ def headline(args, w, gth):
     pair_bytes = sum(v[0] for v in op_nums.values())
     compulsory = 2 * (w.npanel + 1) * gth.nx * gth.nt * 4   # model and data read and written once each
     if args.copy_calibration:
-        x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
-        x.fill_(1.0)
-        y = x.clone()
-        torch.cuda.synchronize()
-        del x, y
+        # plain device copies of known size for the HBM counters: 512 MiB
+        # and 4 GiB (16 times the 256 MB last-level cache, so that cache
+        # hits cannot hide a share of the reads), each source written first
+        # and then pushed out of the caches by a 1 GiB fill
+        for n in (128 * 1024 * 1024, 1024 * 1024 * 1024):
+            x = torch.empty(n, dtype=torch.float32, device=dev)
+            x.fill_(1.0)
+            z = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+            z.fill_(2.0)
+            y = x.clone()
+            torch.cuda.synchronize()
+            del x, y, z
     rec = {
         "metric": "robust ASHRT gathers solved/s to fixed SNR (IRLS-CG 10x20, l1 misfit); also fwd+adj pairs/s, HBM GB/s",
         "value": args.steps / wall,
@@ -906,7 +913,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and asymptote-shifted workloads after the headline solve")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 512 MiB device copy (for HBM counter calibration)")
+                    help="also run a 512 MiB and a 4 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--train-gathers", type=int, default=4096, help="warm-start workload: training gathers (streamed)")
     ap.add_argument("--ws-buffer", type=int, default=512, help="warm-start workload: resident label buffer")
     ap.add_argument("--passes", type=float, default=4.0, help="warm-start workload: expected uses of each label")

@@ -142,6 +142,19 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // packed weights of output channel co0 + mi 16 + n16, k-step s of the
+  // whole reduction (s = cc nkc + kc): consecutive k-steps are consecutive
+  // KKp-CC blocks, 32 BF16 apart
+  const uint16_t* wrow[4];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+    wrow[mi] = a.Wp + ((long long)min(co0 + mi * 16 + n16, P.Coutp - 1) * P.ncc * P.KKp + tap_l) * CC + coff;
+  // the A fragments of the next k-step are loaded while this one multiplies
+  uint4 wq[4];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi) wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi]) : make_uint4(0u, 0u, 0u, 0u);
+  const int nks = P.ncc * nkc;
+
   for (int cc = 0; cc < P.ncc; ++cc) {
     for (int task = threadIdx.x; task < (kConvTH + 2) * TW2 * ng; task += 256) {
       const int g = task % ng, pix = task / ng;
@@ -163,15 +176,20 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
         if (!valid) q = make_uint4(0u, 0u, 0u, 0u);
         bfrag[ni] = __builtin_bit_cast(bf16x8, q);
       }
+      bf16x8 afrag[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) afrag[mi] = __builtin_bit_cast(bf16x8, wq[mi]);
+      const int sn = cc * nkc + kc + 1;
+      if (sn < nks) {
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+          if (mi < MI) wq[mi] = *reinterpret_cast<const uint4*>(wrow[mi] + (long long)sn * P.TPK * CC);
+      }
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi) {
         if (mi < MI) {
-          const int co = co0 + mi * 16 + n16;
-          const uint4 wq =
-              *reinterpret_cast<const uint4*>(a.Wp + (((long long)co * P.ncc + cc) * P.KKp + kk) * CC + coff);
-          const bf16x8 afrag = __builtin_bit_cast(bf16x8, wq);
-          acc[mi][0] = mfma(afrag, bfrag[0], acc[mi][0]);
-          acc[mi][1] = mfma(afrag, bfrag[1], acc[mi][1]);
+          acc[mi][0] = mfma(afrag[mi], bfrag[0], acc[mi][0]);
+          acc[mi][1] = mfma(afrag[mi], bfrag[1], acc[mi][1]);
         }
       }
     }
