@@ -526,7 +526,12 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
 
 // Loss terms, gradient of the head input (FP32 NHWC) and per-block partial
 // sums of the head-parameter gradient and of the two squared errors.
-// Dynamic LDS: gy [256][P+1], h [256][C1+1], gz [256], Wm [P][C1], Ww [C1].
+// Dynamic LDS: gy [256][P+1], h [256][C1+1], gz [256], Wm [P][C1], Ww [C1];
+// the partials of the Wm gradient reuse it from the start once those are read.
+// The Wm gradient block sum_t gy[t][co] h[t][c] (P x C1 outputs over the
+// block's 256 pixels) is register-blocked: a thread takes a 4 x 4 tile of
+// outputs over one of G pixel ranges (8 LDS reads per 16 FMAs), and the G
+// range sums of an output are added in range order.
 __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
   extern __shared__ float sh[];
   __shared__ double sred[2][4];
@@ -568,13 +573,46 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
   }
   __syncthreads();
   if (p < npix) {
-    for (int c = 0; c < C1; ++c) {
-      float s = sWw[c] * sgz[tid];
-      for (int co = 0; co < P; ++co) s = fmaf(sWm[co * C1 + c], sgy[tid * (P + 1) + co], s);
-      a.g_h[p * C1 + c] = s;
+    // four channels per 16-byte store (C1 is a multiple of 8)
+    for (int c = 0; c < C1; c += 4) {
+      float s[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s[i] = sWw[c + i] * sgz[tid];
+      for (int co = 0; co < P; ++co) {
+        const float gy = sgy[tid * (P + 1) + co];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
+      }
+      *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
     }
   }
-  for (int e = tid; e < a.ne; e += 256) {
+  const int tP = (P + 3) >> 2, tC = (C1 + 3) >> 2, nT = tP * tC;
+  const bool blocked = nT <= 256;
+  const int G = blocked ? 256 / nT : 1;
+  const int tile = tid % nT, grp = tid / nT;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+  if (blocked && grp < G) {
+    const int co0 = (tile / tC) * 4, c0 = (tile % tC) * 4;
+    const int tlo = grp * 256 / G, thi = (grp + 1) * 256 / G;
+    for (int t = tlo; t < thi; ++t) {
+      float gy[4], hh[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        gy[i] = co0 + i < P ? sgy[t * (P + 1) + co0 + i] : 0.f;
+        hh[i] = c0 + i < C1 ? shh[t * (C1 + 1) + c0 + i] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gy[i], hh[j], acc[i][j]);
+    }
+  }
+  // the other entries (and all of them when the tiles do not fit)
+  for (int e = (blocked ? P * C1 : 0) + tid; e < a.ne; e += 256) {
     float s = 0.f;
     if (e < P * C1) {
       const int co = e / C1, c = e - co * C1;
@@ -589,6 +627,24 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
       for (int t = 0; t < 256; ++t) s += sgz[t];
     }
     a.hpart[(long long)blockIdx.x * a.ne + e] = s;
+  }
+  if (blocked) {
+    __syncthreads();  // gy and h are read: their space takes the partials
+    float* red = sh;
+    if (grp < G) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[(grp * nT + tile) * 16 + i * 4 + j] = acc[i][j];
+    }
+    __syncthreads();
+    for (int e = tid; e < P * C1; e += 256) {
+      const int co = e / C1, c = e - co * C1;
+      const int o = ((co >> 2) * tC + (c >> 2)) * 16 + (co & 3) * 4 + (c & 3);
+      float s = 0.f;
+      for (int g = 0; g < G; ++g) s += red[g * nT * 16 + o];
+      a.hpart[(long long)blockIdx.x * a.ne + e] = s;
+    }
   }
   // block sums of the squared errors (fixed order)
   for (int off = 32; off > 0; off >>= 1) {
@@ -725,7 +781,11 @@ hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
 }
 
 size_t head_fwd_lds(int P, int C1) { return (size_t)(P * C1 + P + C1 + 1) * 4; }
-size_t head_bwd_lds(int P, int C1) { return (size_t)(256 * (P + 1) + 256 * (C1 + 1) + 256 + P * C1 + C1) * 4; }
+size_t head_bwd_lds(int P, int C1) {
+  const int nT = ((P + 3) / 4) * ((C1 + 3) / 4);
+  const size_t red = nT <= 256 ? (size_t)(256 / nT) * nT * 16 : 0;  // partials of the Wm gradient
+  return std::max((size_t)(256 * (P + 1) + 256 * (C1 + 1) + 256 + P * C1 + C1), red) * 4;
+}
 
 hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
   const long long npix = (long long)a.B * a.H * a.W;
