@@ -221,9 +221,10 @@ def _check_stored_solve(gth, ref, m, drec, rep):
 def test_aashrt_production_solve_matches_stored_oracle(A):
     """Full 10 x 20 solve of the decimated diffraction gather (1024 x 256,
     24 velocities x 16 asymptote shifts = 384 panels, half the traces
-    missing, p = 2, q = 1) against the FP64 oracle's per-iteration misfits,
-    model clips and separated-signal SNR stored by
-    tests/golden/make_oracle_values.py (which calls only the oracle)."""
+    missing, p = 2, q = 1) against the FP64 oracle's solve stored by
+    tests/golden/make_oracle_values.py (which calls only the oracle):
+    the reconstructed gather and the model element-wise at seeded samples,
+    per-trace norms, SNR, per-iteration misfits and model clips."""
     import torch
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_separation.json")))
     ref = gold["aashrt-1024x256-nv24x16"]
@@ -234,14 +235,8 @@ def test_aashrt_production_solve_matches_stored_oracle(A):
     d = torch.tensor(gth.d_blend, dtype=torch.float32, device="cuda")
     mask = torch.tensor(gth.mask, device="cuda")
     print("[gpu] invert parity aashrt-1024x256-nv24x16 10x20 vs stored oracle", flush=True)
-    _, drec, rep = plan.robust_invert(d, A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner), mask=mask)
-    q_r = oracle.q_db(gth.d_clean, drec.cpu().numpy())
-    print(f"  Q_R gpu {q_r:.6f} dB oracle {ref['q_r_db']:.6f} dB", flush=True)
-    print(f"  misfit rel err {np.max(np.abs(np.array(rep['misfit']) / np.array(ref['misfit']) - 1)):.2e}", flush=True)
-    assert q_r >= ref["q_r_db"] - 0.05
-    assert abs(q_r - ref["q_r_db"]) < 0.01
-    np.testing.assert_allclose(rep["misfit"], ref["misfit"], rtol=1e-4)
-    np.testing.assert_allclose(rep["eps_m"][1:], ref["eps_m"], rtol=1e-3)
+    m, drec, rep = plan.robust_invert(d, A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner), mask=mask)
+    _check_stored_solve(gth, ref, m, drec, rep)
 
 
 @pytest.mark.parametrize("pq_inner", [(1, 2, 7), (1, 1, 6)])
