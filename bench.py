@@ -539,7 +539,11 @@ def run_warmstart(args):
     net.init_params(seed=0)
     print(f"[bench] warm start: streaming {n_train} training gathers (buffer {args.ws_buffer})",
           file=sys.stderr, flush=True)
-    ws = WS.train_streaming(plan, net, train_iter, n_train, prm, A.TrainParams(lr=1e-3), buffer=args.ws_buffer,
+    # labels: the plain solve, with the workload's outer-iteration count or
+    # the one given (--label-outer)
+    n_lab = args.label_outer or w.n_outer
+    prm_lab = A.Params(p=w.p, q=w.q, n_outer=n_lab, n_inner=w.n_inner)
+    ws = WS.train_streaming(plan, net, train_iter, n_train, prm_lab, A.TrainParams(lr=1e-3), buffer=args.ws_buffer,
                             chunk=128, passes=args.passes, batch=args.batch, seed=0, log_every=500)
     pool.close()
     pool.join()
@@ -591,6 +595,7 @@ def run_warmstart(args):
         "config": {"workload": "warmstart-crg-1024x256-nv32", "train_gathers": n_train,
                    "label_buffer": args.ws_buffer, "passes": args.passes, "heldout_gathers": n_held,
                    "batch": args.batch, "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner,
+                   "label_outer": n_lab,
                    "model_label_scale": ws.m_scale},
         "plain": {"cg_iterations_mean": float(np.mean(kp) * w.n_inner), "outer_median": float(np.median(kp)),
                   "ms_mean": float(np.mean(tp_) * 1e3)},
@@ -918,6 +923,8 @@ def main():
     ap.add_argument("--ws-buffer", type=int, default=512, help="warm-start workload: resident label buffer")
     ap.add_argument("--passes", type=float, default=4.0, help="warm-start workload: expected uses of each label")
     ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
+    ap.add_argument("--label-outer", type=int, default=0,
+                    help="warm-start workload: outer iterations of the labelling solves (default: the workload's)")
     ap.add_argument("--ws-curves", type=int, default=16,
                     help="warm-start workload: held-out gathers for the SNR-by-outer-iteration curves")
     ap.add_argument("--batch", type=int, default=4, help="warm-start and unet workloads: batch size")
