@@ -15,8 +15,6 @@
 namespace unet {
 
 constexpr int kConvTH = 4;    // output rows per conv workgroup (one per wave)
-constexpr int kConvTW = 32;   // output columns per conv workgroup
-constexpr int kConvCoT = 64;  // output channels per conv workgroup
 constexpr int kWgTH = 4;      // pixel tile of the weight-gradient kernel (rows)
 constexpr int kWgTW = 32;     //                                      (columns)
 constexpr int kWgCoT = 64;    // output channels per weight-gradient workgroup

@@ -116,43 +116,49 @@ __device__ __forceinline__ void load_in8(const ConvIn& I, int b, int y, int x, i
 }
 
 // ------------------------------------------------------------ 3x3 convolution
-// Grid: (row tiles x column tiles, output-channel tiles of 64, batch).
-// Wave w computes output row w of the tile: up to 4 x 2 MFMA tiles
-// (64 channels x 32 columns).
-template <bool AF32, bool OUTF32>
+// Grid: (row tiles x column tiles, output-channel tiles of 16 MT, batch).
+// Wave w computes output row w of the tile: up to MT x NTL MFMA tiles
+// (16 MT channels x 16 NTL columns).  MT = 4, NTL = 2 in general; layers
+// with at most 16 output channels take MT = 1, NTL = 8 (128 columns), so
+// that every wave still issues eight MFMAs per k-step.
+template <bool AF32, bool OUTF32, int MT = 4, int NTL = 2>
 __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
-  constexpr int TW2 = kConvTW + 2;
-  __shared__ __attribute__((aligned(16))) uint16_t sX[(kConvTH + 2) * TW2 * 40];
+  static_assert(MT * NTL == 8, "eight 16 x 16 accumulator tiles per wave");
+  constexpr int TW = 16 * NTL;
+  constexpr int TW2 = TW + 2;
+  // input tile [row][col][channel], (kConvTH + 2) x TW2 pixels of CC + 8
+  // channel slots (dynamic: conv3_lds)
+  extern __shared__ __attribute__((aligned(16))) uint16_t sX[];
   const int H = a.in.H, W = a.in.W;
-  const int tiles_x = (W + kConvTW - 1) / kConvTW;
+  const int tiles_x = (W + TW - 1) / TW;
   const int ty0 = ((int)blockIdx.x / tiles_x) * kConvTH;
-  const int tx0 = ((int)blockIdx.x % tiles_x) * kConvTW;
-  const int co0 = (int)blockIdx.y * kConvCoT, b = (int)blockIdx.z;
+  const int tx0 = ((int)blockIdx.x % tiles_x) * TW;
+  const int co0 = (int)blockIdx.y * 16 * MT, b = (int)blockIdx.z;
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int sub = lane >> 4, n16 = lane & 15;
   const ConvPack& P = a.pk;
-  const int MI = min(4, (P.Coutp - co0) >> 4);
+  const int MI = min(MT, (P.Coutp - co0) >> 4);
   const int CC = P.CC, PS = CC + 8, ng = CC >> 3;
   const int kl = sub * 8, tap_l = kl / CC, coff = kl - tap_l * CC;
   const int nkc = P.KKp / P.TPK;
 
-  f32x4 acc[4][2];
+  f32x4 acc[MT][NTL];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ni = 0; ni < NTL; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   // packed weights of output channel co0 + mi 16 + n16, k-step s of the
   // whole reduction (s = cc nkc + kc): consecutive k-steps are consecutive
   // KKp-CC blocks, 32 BF16 apart
-  const uint16_t* wrow[4];
+  const uint16_t* wrow[MT];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MT; ++mi)
     wrow[mi] = a.Wp + ((long long)min(co0 + mi * 16 + n16, P.Coutp - 1) * P.ncc * P.KKp + tap_l) * CC + coff;
   // the A fragments of the next k-step are loaded while this one multiplies
-  uint4 wq[4];
+  uint4 wq[MT];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi) wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi]) : make_uint4(0u, 0u, 0u, 0u);
+  for (int mi = 0; mi < MT; ++mi) wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi]) : make_uint4(0u, 0u, 0u, 0u);
   const int nks = P.ncc * nkc;
 
   for (int cc = 0; cc < P.ncc; ++cc) {
@@ -168,28 +174,28 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
       const int kk = kc * P.TPK + tap_l;
       const bool valid = kk < 9;
       const int dy = valid ? kk / 3 : 0, dx = valid ? kk - (kk / 3) * 3 : 0;
-      bf16x8 bfrag[2];
+      bf16x8 bfrag[NTL];
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) {
+      for (int ni = 0; ni < NTL; ++ni) {
         const int px = ni * 16 + n16;
         uint4 q = *reinterpret_cast<const uint4*>(sX + ((wave + dy) * TW2 + px + dx) * PS + coff);
         if (!valid) q = make_uint4(0u, 0u, 0u, 0u);
         bfrag[ni] = __builtin_bit_cast(bf16x8, q);
       }
-      bf16x8 afrag[4];
+      bf16x8 afrag[MT];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) afrag[mi] = __builtin_bit_cast(bf16x8, wq[mi]);
+      for (int mi = 0; mi < MT; ++mi) afrag[mi] = __builtin_bit_cast(bf16x8, wq[mi]);
       const int sn = cc * nkc + kc + 1;
       if (sn < nks) {
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < MT; ++mi)
           if (mi < MI) wq[mi] = *reinterpret_cast<const uint4*>(wrow[mi] + (long long)sn * P.TPK * CC);
       }
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
+      for (int mi = 0; mi < MT; ++mi) {
         if (mi < MI) {
-          acc[mi][0] = mfma(afrag[mi], bfrag[0], acc[mi][0]);
-          acc[mi][1] = mfma(afrag[mi], bfrag[1], acc[mi][1]);
+#pragma unroll
+          for (int ni = 0; ni < NTL; ++ni) acc[mi][ni] = mfma(afrag[mi], bfrag[ni], acc[mi][ni]);
         }
       }
     }
@@ -199,12 +205,12 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
   const int y = ty0 + wave;
   if (y >= H) return;
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi) {
+  for (int mi = 0; mi < MT; ++mi) {
     if (mi >= MI) continue;
     const int co = co0 + mi * 16 + sub * 4;
     if (co >= P.Cout) continue;
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
+    for (int ni = 0; ni < NTL; ++ni) {
       const int x = tx0 + ni * 16 + n16;
       if (x >= W) continue;
       float o[4];
@@ -735,13 +741,21 @@ static inline unsigned grid_for(long long n, int per = 256, int cap = 8192) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+template <int MT, int NTL>
+static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
+  const int tiles = ((a.in.H + kConvTH - 1) / kConvTH) * ((a.in.W + 16 * NTL - 1) / (16 * NTL));
+  const dim3 grid(tiles, (a.pk.Coutp + 16 * MT - 1) / (16 * MT), a.B);
+  const size_t lds = (size_t)(kConvTH + 2) * (16 * NTL + 2) * (a.pk.CC + 8) * sizeof(uint16_t);
+  if (af32 && outf32) hipLaunchKernelGGL((k_conv3<true, true, MT, NTL>), grid, dim3(256), lds, s, a);
+  else if (af32) hipLaunchKernelGGL((k_conv3<true, false, MT, NTL>), grid, dim3(256), lds, s, a);
+  else if (outf32) hipLaunchKernelGGL((k_conv3<false, true, MT, NTL>), grid, dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((k_conv3<false, false, MT, NTL>), grid, dim3(256), lds, s, a);
+}
+
 hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
-  const int tiles = ((a.in.H + kConvTH - 1) / kConvTH) * ((a.in.W + kConvTW - 1) / kConvTW);
-  const dim3 grid(tiles, (a.pk.Coutp + kConvCoT - 1) / kConvCoT, a.B);
-  if (af32 && outf32) hipLaunchKernelGGL((k_conv3<true, true>), grid, dim3(256), 0, s, a);
-  else if (af32) hipLaunchKernelGGL((k_conv3<true, false>), grid, dim3(256), 0, s, a);
-  else if (outf32) hipLaunchKernelGGL((k_conv3<false, true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_conv3<false, false>), grid, dim3(256), 0, s, a);
+  // one 16-channel tile of outputs: a wave takes 128 columns instead of 32
+  if (a.pk.Coutp <= 16) conv3_launch<1, 8>(a, af32, outf32, s);
+  else conv3_launch<4, 2>(a, af32, outf32, s);
   return hipGetLastError();
 }
 
