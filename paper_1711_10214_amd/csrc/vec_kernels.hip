@@ -3,8 +3,9 @@
 //
 // ashrt_vec_stats sums in one 1024-thread workgroup: each thread takes a
 // fixed stride of elements, the partial sums combine in a fixed tree, so the
-// result does not depend on timing.  The vectors here are one gather's
-// data (a few hundred thousand samples), for which one workgroup suffices.
+// result does not depend on timing.  Most calls are on one gather's data (a
+// few hundred thousand samples); the one call per training run on the
+// model-label buffer (up to ~10^9 elements) takes tens of milliseconds.
 #include "block_reduce.h"
 #include "kernels.h"
 
