@@ -220,9 +220,8 @@ int ashrt_forward_noalloc(const ashrt_plan *plan, const float *m, float *d, cons
  * out[2] with b = L m0) and the l_p misfit that decides whether the
  * prediction replaces the zero start (Chapter 4's misfit, equation
  * ch4_cost_fn with mu = 0).  One workgroup does the sums (that is what
- * makes the order fixed): a gather's data takes a few microseconds, a
- * buffer of model labels (hundreds of millions of elements) tens of
- * milliseconds. */
+ * makes the order fixed), which suits a gather's data; over a buffer of
+ * model labels (~10^9 elements, once per training run) it is slow. */
 int ashrt_vec_stats(const float *a, const float *b, int64_t n, double alpha, int32_t p, double *out, void *stream);
 
 /* w_i = sqrt(eps / max(|d_i - d_rec_i|, eps)) over n elements, eps > 0: the

@@ -5,7 +5,7 @@
 // fixed stride of elements, the partial sums combine in a fixed tree, so the
 // result does not depend on timing.  Most calls are on one gather's data (a
 // few hundred thousand samples); the one call per training run on the
-// model-label buffer (up to ~10^9 elements) takes tens of milliseconds.
+// model-label buffer (~10^9 elements) is slow at one workgroup but rare.
 #include "block_reduce.h"
 #include "kernels.h"
 
