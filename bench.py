@@ -509,44 +509,60 @@ def run_survey(args):
     print(json.dumps(rec), flush=True)
 
 
-def run_warmstart(args):
-    """Learned warm start against the plain zero start on the same GPU: CG
-    iterations and wall time to reach the plain method's final separated-
-    signal SNR (minus 0.05 dB) on held-out gathers drawn like the
-    production gather.  Training labels are streamed: host workers draw
-    gathers while the GPU labels them (plain 10 x 20 solves) into a rolling
-    buffer and trains on it."""
+# The warm-start leg of the default run: 4096 streamed training gathers
+# labelled by the plain solve stopped at outer iteration 3 (where its Q_R
+# peaks; a third of the cost of 10), 128 held-out gathers, Q_R curves on 16.
+WS_DEFAULT = {"train_gathers": 4096, "heldout_gathers": 128, "label_outer": 3, "passes": 4.0, "curves": 16}
+
+
+def _ws_prepare(n_train, n_held):
+    """Host side of the warm-start workload, started before the GPU is
+    touched: worker processes draw the held-out gathers now and keep
+    drawing the training gathers lazily while the GPU labels and trains."""
     import multiprocessing as mp
-    import numpy as np
     base = "crg-1024x256-nv32"
-    n_train, n_held = args.train_gathers, args.heldout_gathers
-    # host workers start before the GPU is touched; they keep drawing the
-    # training gathers while the GPU labels and trains
     pool = mp.get_context("fork").Pool(processes=max(1, min(16, os.cpu_count() or 1) - 1))
     t0 = time.perf_counter()
     held = pool.map(_gen_gather, [(base, 2_000_000 + i) for i in range(n_held)])
     t_gen = time.perf_counter() - t0
-    train_iter = (g for g, _ in pool.imap(_gen_gather, [(base, 1_000_000 + i) for i in range(n_train)], 8))
+    # the training gathers are drawn only once the leg starts (idle workers
+    # do not compete with the host side of other timed work)
+    def train_iter():
+        return (g for g, _ in pool.imap(_gen_gather, [(base, 1_000_000 + i) for i in range(n_train)], 8))
+    return {"base": base, "pool": pool, "held": held, "t_gen": t_gen, "train_iter": train_iter,
+            "n_train": n_train, "n_held": n_held}
+
+
+def warmstart_leg(prep, label_outer=0, ws_buffer=512, passes=4.0, batch=4, ws_curves=16):
+    """Learned warm start against the plain zero start on the same GPU: CG
+    iterations and wall time to reach the plain method's final separated-
+    signal SNR (minus 0.05 dB) on held-out gathers drawn like the
+    production gather.  Training labels are streamed: host workers draw
+    gathers while the GPU labels them (plain solves; label_outer outer
+    iterations, default the workload's) into a rolling buffer and trains on
+    it."""
+    import numpy as np
     import torch
     import paper_1711_10214_amd as A
     from paper_1711_10214_amd import warmstart as WS
     from synth import workload
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    base, held, n_train, n_held = prep["base"], prep["held"], prep["n_train"], prep["n_held"]
     w = workload(base)
     plan = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
     prm = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
     net = A.UNet(w.npanel, base=16)
     net.init_params(seed=0)
-    print(f"[bench] warm start: streaming {n_train} training gathers (buffer {args.ws_buffer})",
+    print(f"[bench] warm start: streaming {n_train} training gathers (buffer {ws_buffer})",
           file=sys.stderr, flush=True)
     # labels: the plain solve, with the workload's outer-iteration count or
-    # the one given (--label-outer)
-    n_lab = args.label_outer or w.n_outer
+    # the one given
+    n_lab = label_outer or w.n_outer
     prm_lab = A.Params(p=w.p, q=w.q, n_outer=n_lab, n_inner=w.n_inner)
-    ws = WS.train_streaming(plan, net, train_iter, n_train, prm_lab, A.TrainParams(lr=1e-3), buffer=args.ws_buffer,
-                            chunk=128, passes=args.passes, batch=args.batch, seed=0, log_every=500)
-    pool.close()
-    pool.join()
+    ws = WS.train_streaming(plan, net, prep["train_iter"](), n_train, prm_lab, A.TrainParams(lr=1e-3),
+                            buffer=ws_buffer, chunk=128, passes=passes, batch=batch, seed=0, log_every=500)
+    prep["pool"].close()
+    prep["pool"].join()
     torch.cuda.empty_cache()
     # one warm-up of each path
     d0 = torch.tensor(held[0][0], device="cuda")
@@ -566,7 +582,7 @@ def run_warmstart(args):
     # separated-signal SNR after each outer iteration, plain and warm
     # started, with the weights-only start as the ablation of the model
     curves = {"plain": [], "model+weights": [], "weights only": []}
-    for g, clean in held[:args.ws_curves]:
+    for g, clean in held[:ws_curves]:
         d = torch.tensor(g, device="cuda")
         for kind in curves:
             qs = []
@@ -586,89 +602,35 @@ def run_warmstart(args):
     reached = sum(r[3] is not None for r in rows)
     starts = [r[5] for r in rows]
     losses = ws.stats.get("losses", [])
-    rec = {
+    return {
         "metric": "learned warm start: wall time to the plain IRLS-CG separated-signal SNR, plain / warm",
         "value": float(np.mean(tp_) / np.mean(tw)),
         "unit": "x (speed-up of time-to-SNR)",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16 network, f32 solver",
         "data": "synthetic",
         "config": {"workload": "warmstart-crg-1024x256-nv32", "train_gathers": n_train,
-                   "label_buffer": args.ws_buffer, "passes": args.passes, "heldout_gathers": n_held,
-                   "batch": args.batch, "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner,
-                   "label_outer": n_lab,
-                   "model_label_scale": ws.m_scale},
+                   "label_buffer": ws_buffer, "passes": passes, "heldout_gathers": n_held,
+                   "batch": batch, "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner,
+                   "label_outer": n_lab, "model_label_scale": ws.m_scale},
         "plain": {"cg_iterations_mean": float(np.mean(kp) * w.n_inner), "outer_median": float(np.median(kp)),
                   "ms_mean": float(np.mean(tp_) * 1e3)},
         "warm": {"cg_iterations_mean": float(np.mean(kw) * w.n_inner), "outer_median": float(np.median(kw)),
                  "ms_mean": float(np.mean(tw) * 1e3), "reached_target": reached,
                  "model_start_rate": float(np.mean([s_ == "model+weights" for s_ in starts])),
                  "fallback_rate": float(np.mean([s_ != "model+weights" for s_ in starts]))},
-        "seconds": {"generate_heldout": t_gen, "label": ws.stats.get("label_s"), "train": ws.stats.get("train_s")},
-        "q_r_by_outer_db": {"gathers": min(args.ws_curves, n_held), **q_by_outer},
+        "seconds": {"generate_heldout": prep["t_gen"], "label": ws.stats.get("label_s"),
+                    "train": ws.stats.get("train_s")},
+        "q_r_by_outer_db": {"gathers": min(ws_curves, n_held), **q_by_outer},
         "train_steps": ws.stats.get("steps"),
         "train_loss": [losses[0], losses[-1]] if losses else None,
     }
-    print(json.dumps(rec), flush=True)
 
 
-def run_separation(args):
-    """What limits the separated-signal SNR of the production gather
-    (--workload separation): Q_R after each outer iteration of the plain
-    solve; Q_R on the interfered and on the clean traces separately; the same
-    solver fitting the clean gather alone (no interference: the operator's
-    own limit); the non-robust l2 solve; and the solves with the Ricker
-    wavelet's amplitude spectrum as Chapter 4's wavelet operator C."""
-    import numpy as np
-    import torch
-    import paper_1711_10214_amd as A
-    from synth import make_gather, workload
-    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
-    w = workload("crg-1024x256-nv32")
-    gth = make_gather(w)
-    dev = torch.device("cuda", 0)
-    plan = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
-    ntp = plan.info["ntp"]
-    f = np.arange(ntp // 2 + 1) / (ntp * w.dt)
-    ric = (f / w.ricker_hz) ** 2 * np.exp(-(f / w.ricker_hz) ** 2)   # Ricker amplitude spectrum
-    ric /= ric.max()
-    plan_c = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax, wavelet=ric)
-    d_blend = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
-    d_clean = torch.tensor(gth.d_clean, dtype=torch.float32, device=dev)
-    hit = np.zeros(gth.nx, bool)
-    hit[gth.interfered] = True
-
-    def solve(pl, d, k, p=w.p):
-        prm = A.Params(p=p, q=w.q, n_outer=k, n_inner=w.n_inner)
-        _, d_rec, _ = pl.robust_invert(d, prm, want_report=False)
-        return d_rec.cpu().numpy().astype(np.float64)
-
-    def q(est, rows=None):
-        c = gth.d_clean if rows is None else gth.d_clean[rows]
-        e = est if rows is None else est[rows]
-        return _q_db(c, e)
-
-    solve(plan, d_blend, 1)   # warm-up
-    by_outer = [q(solve(plan, d_blend, k)) for k in range(1, w.n_outer + 1)]
-    final = solve(plan, d_blend, w.n_outer)
-    final_c = solve(plan_c, d_blend, w.n_outer)
-    rec = {
-        "metric": "separated-signal SNR Q_R of the production gather under controlled changes (dB)",
-        "value": by_outer[-1], "unit": "dB", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "separation-crg-1024x256-nv32", "p": w.p, "q": w.q, "n_outer": w.n_outer,
-                   "n_inner": w.n_inner, "interfered_traces": int(hit.sum()), "nx": gth.nx},
-        "q_pd_db": q(gth.d_blend),
-        "q_r_by_outer_db": by_outer,
-        "q_r_interfered_traces_db": q(final, hit),
-        "q_r_clean_traces_db": q(final, ~hit),
-        "q_pd_interfered_traces_db": q(gth.d_blend, hit),
-        "clean_gather_fit_db": q(solve(plan, d_clean, w.n_outer)),
-        "clean_gather_fit_l2_db": q(solve(plan, d_clean, w.n_outer, p=2)),
-        "blended_l2_solve_db": q(solve(plan, d_blend, w.n_outer, p=2)),
-        "wavelet_c": {"q_r_db": q(final_c), "q_r_interfered_traces_db": q(final_c, hit),
-                      "q_r_clean_traces_db": q(final_c, ~hit),
-                      "clean_gather_fit_db": q(solve(plan_c, d_clean, w.n_outer))},
-    }
+def run_warmstart(args):
+    """The warm-start workload alone (--workload warmstart)."""
+    prep = _ws_prepare(args.train_gathers, args.heldout_gathers)
+    rec = warmstart_leg(prep, label_outer=args.label_outer, ws_buffer=args.ws_buffer, passes=args.passes,
+                        batch=args.batch, ws_curves=args.ws_curves)
     print(json.dumps(rec), flush=True)
 
 
@@ -916,7 +878,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched and asymptote-shifted workloads after the headline solve")
+                    help="skip the batched, asymptote-shifted and warm-start workloads after the headline solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB and a 4 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--train-gathers", type=int, default=4096, help="warm-start workload: training gathers (streamed)")
@@ -960,8 +922,11 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host (bounded samples)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, gth)
-    batch_in = None
+    batch_in = ws_prep = None
     if not args.no_extra:
+        # warm-start workers first (forked while the process is small and
+        # before the GPU is touched), then the batched gathers
+        ws_prep = _ws_prepare(WS_DEFAULT["train_gathers"], WS_DEFAULT["heldout_gathers"])
         print(f"[bench] drawing the {args.batch_gathers} batched gathers", file=sys.stderr, flush=True)
         batch_in = _draw_batch(args.batch_gathers)
 
@@ -977,6 +942,10 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] asymptote-shifted workload", file=sys.stderr, flush=True)
         rec["aashrt"] = aashrt_leg(steps=3, warmup=1, autotune=not args.no_autotune)
+        torch.cuda.empty_cache()
+        print("[bench] learned warm start", file=sys.stderr, flush=True)
+        rec["warmstart"] = warmstart_leg(ws_prep, label_outer=WS_DEFAULT["label_outer"],
+                                         passes=WS_DEFAULT["passes"], ws_curves=WS_DEFAULT["curves"])
     print(json.dumps(rec), flush=True)
 
 
