@@ -634,6 +634,86 @@ def run_warmstart(args):
     print(json.dumps(rec), flush=True)
 
 
+def run_separation(args):
+    """What limits the separated-signal SNR of the production gather
+    (--workload separation): Q_R after each outer iteration of the plain
+    solve; Q_R on the interfered and on the clean traces separately; the same
+    solver fitting the clean gather alone (no interference: the operator's
+    own limit); the non-robust l2 solve; and the solves with the Ricker
+    wavelet's amplitude spectrum as Chapter 4's wavelet operator C."""
+    import numpy as np
+    import torch
+    import paper_1711_10214_amd as A
+    from synth import make_gather, workload
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    w = workload("crg-1024x256-nv32")
+    gth = make_gather(w)
+    dev = torch.device("cuda", 0)
+    plan = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax)
+    ntp = plan.info["ntp"]
+    f = np.arange(ntp // 2 + 1) / (ntp * w.dt)
+    ric = (f / w.ricker_hz) ** 2 * np.exp(-(f / w.ricker_hz) ** 2)   # Ricker amplitude spectrum
+    ric /= ric.max()
+    plan_c = A.Plan(w.nt, w.nx, w.dt, w.dx, list(w.vel), fmax=w.fmax, wavelet=ric)
+    d_blend = torch.tensor(gth.d_blend, dtype=torch.float32, device=dev)
+    d_clean = torch.tensor(gth.d_clean, dtype=torch.float32, device=dev)
+    hit = np.zeros(gth.nx, bool)
+    hit[gth.interfered] = True
+
+    def solve(pl, d, k, p=w.p):
+        prm = A.Params(p=p, q=w.q, n_outer=k, n_inner=w.n_inner)
+        _, d_rec, _ = pl.robust_invert(d, prm, want_report=False)
+        return d_rec.cpu().numpy().astype(np.float64)
+
+    def q(est, rows=None):
+        c = gth.d_clean if rows is None else gth.d_clean[rows]
+        e = est if rows is None else est[rows]
+        return _q_db(c, e)
+
+    solve(plan, d_blend, 1)   # warm-up
+    by_outer = [q(solve(plan, d_blend, k)) for k in range(1, w.n_outer + 1)]
+    final = solve(plan, d_blend, w.n_outer)
+    final_c = solve(plan_c, d_blend, w.n_outer)
+
+    # the best a warm start could predict: the plain solve's own final model
+    # m* and final residual weights w* (made as the warm start's labels are)
+    from paper_1711_10214_amd import warmstart as WS
+    prm_f = A.Params(p=w.p, q=w.q, n_outer=w.n_outer, n_inner=w.n_inner)
+    m_star, drec_star, rep_star = plan.robust_invert(d_blend, prm_f)
+    w_star = WS.weight_target(d_blend, drec_star, rep_star["eps_r"][-1])
+
+    def started(k, m0=None, w0=None):
+        prm = A.Params(p=w.p, q=w.q, n_outer=k, n_inner=w.n_inner)
+        _, d_rec, _ = plan.robust_invert(d_blend, prm, m0=m0, w0=w0, want_report=False)
+        return q(d_rec.cpu().numpy().astype(np.float64))
+
+    own_start = {
+        "model+weights": [started(k, m_star, w_star) for k in (1, 2, 3)],
+        "model only": [started(k, m_star, None) for k in (1, 2, 3)],
+        "weights only": [started(k, None, w_star) for k in (1, 2, 3)],
+    }
+    rec = {
+        "metric": "separated-signal SNR Q_R of the production gather under controlled changes (dB)",
+        "value": by_outer[-1], "unit": "dB", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "separation-crg-1024x256-nv32", "p": w.p, "q": w.q, "n_outer": w.n_outer,
+                   "n_inner": w.n_inner, "interfered_traces": int(hit.sum()), "nx": gth.nx},
+        "q_pd_db": q(gth.d_blend),
+        "q_r_by_outer_db": by_outer,
+        "q_r_interfered_traces_db": q(final, hit),
+        "q_r_clean_traces_db": q(final, ~hit),
+        "q_pd_interfered_traces_db": q(gth.d_blend, hit),
+        "clean_gather_fit_db": q(solve(plan, d_clean, w.n_outer)),
+        "clean_gather_fit_l2_db": q(solve(plan, d_clean, w.n_outer, p=2)),
+        "blended_l2_solve_db": q(solve(plan, d_blend, w.n_outer, p=2)),
+        "start_from_own_solution_q_r_by_outer_db": own_start,
+        "wavelet_c": {"q_r_db": q(final_c), "q_r_interfered_traces_db": q(final_c, hit),
+                      "q_r_clean_traces_db": q(final_c, ~hit),
+                      "clean_gather_fit_db": q(solve(plan_c, d_clean, w.n_outer))},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
 
 
