@@ -533,7 +533,7 @@ def _ws_prepare(n_train, n_held):
             "n_train": n_train, "n_held": n_held}
 
 
-def warmstart_leg(prep, label_outer=0, ws_buffer=512, passes=4.0, batch=4, ws_curves=16):
+def warmstart_leg(prep, label_outer=0, ws_buffer=512, passes=4.0, batch=4, ws_curves=16, lam_w=1.0):
     """Learned warm start against the plain zero start on the same GPU: CG
     iterations and wall time to reach the plain method's final separated-
     signal SNR (minus 0.05 dB) on held-out gathers drawn like the
@@ -559,7 +559,7 @@ def warmstart_leg(prep, label_outer=0, ws_buffer=512, passes=4.0, batch=4, ws_cu
     # the one given
     n_lab = label_outer or w.n_outer
     prm_lab = A.Params(p=w.p, q=w.q, n_outer=n_lab, n_inner=w.n_inner)
-    ws = WS.train_streaming(plan, net, prep["train_iter"](), n_train, prm_lab, A.TrainParams(lr=1e-3),
+    ws = WS.train_streaming(plan, net, prep["train_iter"](), n_train, prm_lab, A.TrainParams(lr=1e-3, lam_w=lam_w),
                             buffer=ws_buffer, chunk=128, passes=passes, batch=batch, seed=0, log_every=500)
     prep["pool"].close()
     prep["pool"].join()
@@ -611,7 +611,7 @@ def warmstart_leg(prep, label_outer=0, ws_buffer=512, passes=4.0, batch=4, ws_cu
         "config": {"workload": "warmstart-crg-1024x256-nv32", "train_gathers": n_train,
                    "label_buffer": ws_buffer, "passes": passes, "heldout_gathers": n_held,
                    "batch": batch, "params": net.n_params, "n_outer": w.n_outer, "n_inner": w.n_inner,
-                   "label_outer": n_lab, "model_label_scale": ws.m_scale},
+                   "label_outer": n_lab, "lam_w": lam_w, "model_label_scale": ws.m_scale},
         "plain": {"cg_iterations_mean": float(np.mean(kp) * w.n_inner), "outer_median": float(np.median(kp)),
                   "ms_mean": float(np.mean(tp_) * 1e3)},
         "warm": {"cg_iterations_mean": float(np.mean(kw) * w.n_inner), "outer_median": float(np.median(kw)),
@@ -630,7 +630,7 @@ def run_warmstart(args):
     """The warm-start workload alone (--workload warmstart)."""
     prep = _ws_prepare(args.train_gathers, args.heldout_gathers)
     rec = warmstart_leg(prep, label_outer=args.label_outer, ws_buffer=args.ws_buffer, passes=args.passes,
-                        batch=args.batch, ws_curves=args.ws_curves)
+                        batch=args.batch, ws_curves=args.ws_curves, lam_w=args.lam_w)
     print(json.dumps(rec), flush=True)
 
 
@@ -965,6 +965,8 @@ def main():
     ap.add_argument("--ws-buffer", type=int, default=512, help="warm-start workload: resident label buffer")
     ap.add_argument("--passes", type=float, default=4.0, help="warm-start workload: expected uses of each label")
     ap.add_argument("--heldout-gathers", type=int, default=256, help="warm-start workload: held-out gathers")
+    ap.add_argument("--lam-w", type=float, default=1.0,
+                    help="warm-start workload: weight of the residual-weight term in the training loss")
     ap.add_argument("--label-outer", type=int, default=0,
                     help="warm-start workload: outer iterations of the labelling solves (default: the workload's)")
     ap.add_argument("--ws-curves", type=int, default=16,
