@@ -635,8 +635,13 @@ def run_warmstart(args):
 
 
 def run_separation(args):
-    """What limits the separated-signal SNR of the production gather
-    (--workload separation): Q_R after each outer iteration of the plain
+    """The separated-signal SNR study alone (--workload separation)."""
+    print(json.dumps(separation_leg()), flush=True)
+
+
+def separation_leg():
+    """What limits the separated-signal SNR of the production gather:
+    Q_R after each outer iteration of the plain
     solve; Q_R on the interfered and on the clean traces separately; the same
     solver fitting the clean gather alone (no interference: the operator's
     own limit); the non-robust l2 solve; and the solves with the Ricker
@@ -711,7 +716,7 @@ def run_separation(args):
                       "q_r_clean_traces_db": q(final_c, ~hit),
                       "clean_gather_fit_db": q(solve(plan_c, d_clean, w.n_outer))},
     }
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
@@ -1025,6 +1030,8 @@ def main():
         print("[bench] asymptote-shifted workload", file=sys.stderr, flush=True)
         rec["aashrt"] = aashrt_leg(steps=3, warmup=1, autotune=not args.no_autotune)
         torch.cuda.empty_cache()
+        print("[bench] separated-signal SNR study", file=sys.stderr, flush=True)
+        rec["separation"] = separation_leg()
         print("[bench] learned warm start", file=sys.stderr, flush=True)
         rec["warmstart"] = warmstart_leg(ws_prep, label_outer=WS_DEFAULT["label_outer"],
                                          passes=WS_DEFAULT["passes"], ws_curves=WS_DEFAULT["curves"])
