@@ -30,13 +30,11 @@ hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s);
 hipError_t launch_wgrad_reduce(const float* part, int nsplit, int Cout, int Cin, int Cipw, float* grad,
                                hipStream_t s);
 hipError_t launch_bias(const BiasArgs& a, int nblk, float* gb, hipStream_t s);
-hipError_t launch_route(const RouteArgs& a, hipStream_t s);
 hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s);
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_adamw(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
                         float eps, float wd, float bc1, float bc2, hipStream_t s);
-hipError_t launch_zero(float* p, long long n, hipStream_t s);
 hipError_t unet_kernels_init();
 }  // namespace unet
 
@@ -164,7 +162,7 @@ void build_graph(unet_net& n) {
 
 struct WsLayout {
   std::vector<size_t> act, gact;
-  size_t y_m = 0, y_w = 0, gX = 0, wpart = 0, bpart = 0, hpart = 0, lpart = 0, total = 0;
+  size_t y_m = 0, y_w = 0, wpart = 0, bpart = 0, hpart = 0, lpart = 0, total = 0;
   std::vector<int> nsplit;
   int nblk_h = 0;
 };
@@ -190,13 +188,12 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
   w.y_w = take(npix0 * 4);
   if (train) {
     w.gact.resize(kNConv);
-    long long gx = 0, wp = 0;
+    long long wp = 0;
     w.nsplit.resize(kNConv);
     for (int i = 0; i < kNConv; ++i) {
       const Layer& l = n.L[i];
       const int Hl = H >> l.level, Wl = W >> l.level;
       w.gact[i] = take((long long)B * Hl * Wl * l.co * 4);
-      if (i > 0) gx = std::max(gx, (long long)B * Hl * Wl * l.ci);
       const int cipw = wgrad_cipw(l), ccw = wgrad_ccw(l);
       const long long T = (long long)B * ((Hl + kWgTH - 1) / kWgTH) * ((Wl + kWgTW - 1) / kWgTW);
       const long long groups = (long long)(cipw / ccw) * ((l.co + kWgCoT - 1) / kWgCoT);
@@ -204,7 +201,6 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
       w.nsplit[i] = ns;
       wp = std::max(wp, (long long)ns * l.co * 9 * cipw);
     }
-    w.gX = take(gx * 4);
     w.wpart = take(wp * 4);
     w.bpart = take((long long)kBiasBlocks * 8 * n.base * 4);
     w.nblk_h = (int)((npix0 + 255) / 256);
@@ -281,10 +277,11 @@ int run_forward(const unet_net& n, const WsLayout& w, unsigned char* ws, const f
 // Loss and gradient into g (nparam floats) after run_forward.
 int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const float* x, const float* t_m,
                  const float* t_w, int B, int H, int W, double lam_w, double* loss, float* g, hipStream_t s) {
-  for (int i = 0; i < kNConv; ++i) {
-    const Layer& l = n.L[i];
-    U_TRY(launch_zero((float*)(ws + w.gact[i]), (long long)B * (H >> l.level) * (W >> l.level) * l.co, s));
-  }
+  // every activation gradient is written by its first contribution (the
+  // head, or the input gradient of the first consumer in backward order)
+  // and added to by the later ones
+  std::vector<char> written(kNConv, 0);
+  written[kNConv - 1] = 1;
   LossArgs la{};
   la.hd.h = (const uint16_t*)(ws + w.act[kNConv - 1]);
   la.hd.Wm = n.theta + n.L[kNConv].woff;
@@ -347,20 +344,18 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     da.Wp = n.wpk + l.wtp_off;
     da.bias = nullptr;
     da.relu = 0;
-    da.out = ws + w.gX;
+    da.out = nullptr;
     da.B = B;
+    da.rt.gA = (float*)(ws + w.gact[l.srcA]);
+    da.rt.gB = l.srcB >= 0 ? (float*)(ws + w.gact[l.srcB]) : nullptr;
+    da.rt.Ca = l.Ca;
+    da.rt.Cb = l.srcB >= 0 ? l.Cb : 0;
+    da.rt.modeA = l.modeA;
+    da.rt.accA = written[l.srcA];
+    da.rt.accB = l.srcB >= 0 ? written[l.srcB] : 0;
+    written[l.srcA] = 1;
+    if (l.srcB >= 0) written[l.srcB] = 1;
     U_TRY(launch_conv3(da, true, true, s));
-    RouteArgs ra{};
-    ra.gX = (const float*)(ws + w.gX);
-    ra.gA = (float*)(ws + w.gact[l.srcA]);
-    ra.gB = l.srcB >= 0 ? (float*)(ws + w.gact[l.srcB]) : nullptr;
-    ra.Ca = l.Ca;
-    ra.Cb = l.Cb;
-    ra.modeA = l.modeA;
-    ra.H = Hl;
-    ra.W = Wl;
-    ra.B = B;
-    U_TRY(launch_route(ra, s));
   }
   return ASHRT_OK;
 }

@@ -40,6 +40,18 @@ struct ConvPack {
   int Coutp;                // Cout rounded up to 16
 };
 
+// Where an input-gradient convolution stores its result: the gradient of a
+// forward convolution's input goes straight to the tensors that input was
+// built from.  Channels [0, Ca) belong to A (mode 0: same resolution; 1: A at
+// half resolution, so a 2 x 2 block of gradient pixels sums into one A pixel;
+// 2: A at double resolution, each gradient pixel gives a quarter to its four
+// A pixels), channels [Ca, Ca + Cb) to the skip B at the same resolution.  A
+// tensor's first contribution is written, later ones are added (accA, accB).
+struct ConvRoute {
+  float* gA;                // FP32 NHWC gradient of A, or null: plain output to ConvArgs::out
+  float* gB;                // FP32 NHWC gradient of the skip, or null
+  int Ca, Cb, modeA, accA, accB;
+};
 struct ConvArgs {
   ConvIn in;
   ConvPack pk;
@@ -48,6 +60,7 @@ struct ConvArgs {
   int relu;
   void* out;                // BF16 or FP32 NHWC [B][H][W][Cout]
   int B;
+  ConvRoute rt;             // FP32 outputs only
 };
 
 struct WgradArgs {
@@ -67,12 +80,6 @@ struct PackArgs {
   ConvPack f, t;
 };
 
-struct RouteArgs {
-  const float* gX;          // [B][H][W][Ca + Cb] FP32 gradient of the conv input
-  float* gA;                // gradient of A (at A's resolution), accumulated
-  float* gB;                // gradient of the skip, accumulated, or null
-  int Ca, Cb, modeA, H, W, B;
-};
 
 struct BiasArgs {
   const float* gY;

@@ -115,13 +115,111 @@ __device__ __forceinline__ void load_in8(const ConvIn& I, int b, int y, int x, i
   }
 }
 
+// ------------------------------------------------------------ routed epilogue
+// float4 store or accumulate of four consecutive channels.
+__device__ __forceinline__ void put4(float* p, float v0, float v1, float v2, float v3, bool add) {
+  float4 o = make_float4(v0, v1, v2, v3);
+  if (add) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    o.x += q.x;
+    o.y += q.y;
+    o.z += q.z;
+    o.w += q.w;
+  }
+  *reinterpret_cast<float4*>(p) = o;
+}
+
+// The value held by lane l ^ 1 (DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ float lane_pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Epilogue of an input-gradient convolution (see ConvRoute): lane (sub, n16)
+// of wave w holds channels co0 + 16 mi + 4 sub + [0, 4) of pixel (ty0 + w,
+// tx0 + 16 ni + n16).  An upsampled A (UP, mode 1) sums each 2 x 2 pixel
+// block: the two columns by a lane exchange, then the two rows (waves 2k and
+// 2k + 1) through LDS, (g00 + g01) + (g10 + g11); every wave reaches that
+// barrier.  UP is a template parameter so that the other input gradients do
+// not carry its registers.
+template <int MT, int NTL, bool UP>
+__device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][NTL], int b, int ty0, int tx0,
+                                            int co0, int MI, float* red) {
+  const ConvRoute& R = a.rt;
+  const int H = a.in.H, W = a.in.W;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int sub = lane >> 4, n16 = lane & 15;
+  const int y = ty0 + wave;
+  if constexpr (UP) {
+    // column-pair sums in place for the A tiles (16-channel tiles lie wholly
+    // in A or in B, Ca being a multiple of 16)
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+      if (mi >= MI || co0 + mi * 16 >= R.Ca) continue;
+#pragma unroll
+      for (int ni = 0; ni < NTL; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[mi][ni][i] += lane_pair_swap(acc[mi][ni][i]);
+      if (wave & 1) {
+#pragma unroll
+        for (int ni = 0; ni < NTL; ++ni)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) red[((((wave >> 1) * MT + mi) * NTL + ni) * 4 + i) * 64 + lane] = acc[mi][ni][i];
+      }
+    }
+    __syncthreads();
+    if (!(wave & 1) && y < H && !(n16 & 1)) {
+      const int Hh = H >> 1, Wh = W >> 1;
+#pragma unroll
+      for (int mi = 0; mi < MT; ++mi) {
+        const int co = co0 + mi * 16 + sub * 4;
+        if (mi >= MI || co0 + mi * 16 >= R.Ca) continue;
+#pragma unroll
+        for (int ni = 0; ni < NTL; ++ni) {
+          const int x = tx0 + ni * 16 + n16;
+          if (x >= W) continue;
+          float t[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) t[i] = acc[mi][ni][i] + red[((((wave >> 1) * MT + mi) * NTL + ni) * 4 + i) * 64 + lane];
+          put4(R.gA + (((long long)b * Hh + (y >> 1)) * Wh + (x >> 1)) * R.Ca + co, t[0], t[1], t[2], t[3],
+               R.accA != 0);
+        }
+      }
+    }
+  }
+  if (y >= H) return;
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi) {
+    const int co = co0 + mi * 16 + sub * 4;
+    if (mi >= MI || co >= R.Ca + R.Cb) continue;
+    if (UP && co < R.Ca) continue;  // stored above
+#pragma unroll
+    for (int ni = 0; ni < NTL; ++ni) {
+      const int x = tx0 + ni * 16 + n16;
+      if (x >= W) continue;
+      const f32x4 o = acc[mi][ni];
+      if (co >= R.Ca) {
+        put4(R.gB + (((long long)b * H + y) * W + x) * R.Cb + (co - R.Ca), o[0], o[1], o[2], o[3], R.accB != 0);
+      } else if (R.modeA == 0) {
+        put4(R.gA + (((long long)b * H + y) * W + x) * R.Ca + co, o[0], o[1], o[2], o[3], R.accA != 0);
+      } else {
+        const int H2 = 2 * H, W2 = 2 * W;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long long pa = ((long long)b * H2 + 2 * y + (q >> 1)) * W2 + 2 * x + (q & 1);
+          put4(R.gA + pa * R.Ca + co, 0.25f * o[0], 0.25f * o[1], 0.25f * o[2], 0.25f * o[3], R.accA != 0);
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ 3x3 convolution
 // Grid: (row tiles x column tiles, output-channel tiles of 16 MT, batch).
 // Wave w computes output row w of the tile: up to MT x NTL MFMA tiles
 // (16 MT channels x 16 NTL columns).  MT = 4, NTL = 2 in general; layers
 // with at most 16 output channels take MT = 1, NTL = 8 (128 columns), so
 // that every wave still issues eight MFMAs per k-step.
-template <bool AF32, bool OUTF32, int MT = 4, int NTL = 2>
+template <bool AF32, bool OUTF32, int MT = 4, int NTL = 2, bool UP = false>
 __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
   static_assert(MT * NTL == 8, "eight 16 x 16 accumulator tiles per wave");
   constexpr int TW = 16 * NTL;
@@ -202,6 +300,12 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
     __syncthreads();
   }
 
+  if constexpr (OUTF32) {
+    if (a.rt.gA) {
+      route_store<MT, NTL, UP>(a, acc, b, ty0, tx0, co0, MI, reinterpret_cast<float*>(sX));
+      return;
+    }
+  }
   const int y = ty0 + wave;
   if (y >= H) return;
 #pragma unroll
@@ -457,46 +561,6 @@ static void sum_parts(const float* part, int nblk, int ne, float* out, hipStream
   }
 }
 
-// ------------------------------------------------------------ gradient routing
-// Adds the gradient of a convolution's input to the tensors it was built
-// from: A (same resolution; or upsampled: sum of the 2x2 block; or pooled:
-// a quarter to each of the four pixels) and the concatenated skip.
-__global__ __launch_bounds__(256) void k_route(RouteArgs a) {
-  const int Ct = a.Ca + a.Cb;
-  const int Ha = a.modeA == 1 ? a.H / 2 : (a.modeA == 2 ? a.H * 2 : a.H);
-  const int Wa = a.modeA == 1 ? a.W / 2 : (a.modeA == 2 ? a.W * 2 : a.W);
-  const long long nA = (long long)a.B * Ha * Wa * a.Ca;
-  const long long nB = a.gB ? (long long)a.B * a.H * a.W * a.Cb : 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nA + nB;
-       i += (long long)gridDim.x * blockDim.x) {
-    if (i < nA) {
-      const int c = (int)(i % a.Ca);
-      const long long pa = i / a.Ca;
-      const int xa = (int)(pa % Wa);
-      const long long t = pa / Wa;
-      const int ya = (int)(t % Ha);
-      const int b = (int)(t / Ha);
-      float g;
-      if (a.modeA == 0) {
-        g = a.gX[(((long long)b * a.H + ya) * a.W + xa) * Ct + c];
-      } else if (a.modeA == 1) {
-        g = 0.f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          g += a.gX[(((long long)b * a.H + 2 * ya + (q >> 1)) * a.W + 2 * xa + (q & 1)) * Ct + c];
-      } else {
-        g = 0.25f * a.gX[(((long long)b * a.H + (ya >> 1)) * a.W + (xa >> 1)) * Ct + c];
-      }
-      a.gA[i] += g;
-    } else {
-      const long long j = i - nA;
-      const int c = (int)(j % a.Cb);
-      const long long p = j / a.Cb;
-      a.gB[j] += a.gX[p * Ct + a.Ca + c];
-    }
-  }
-}
-
 // ------------------------------------------------------------ heads
 // One pixel per thread: y_m = Wm h + bm (P channels, planar output), y_w =
 // sigmoid(Ww h + bw).  FP32 weights in LDS.
@@ -730,10 +794,6 @@ __global__ __launch_bounds__(256) void k_adamw(float* __restrict__ th, const flo
   }
 }
 
-__global__ __launch_bounds__(256) void k_zero_f32(float* p, long long n) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = 0.f;
-}
 
 // ------------------------------------------------------------ launchers
 static inline unsigned grid_for(long long n, int per = 256, int cap = 8192) {
@@ -745,7 +805,16 @@ template <int MT, int NTL>
 static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
   const int tiles = ((a.in.H + kConvTH - 1) / kConvTH) * ((a.in.W + 16 * NTL - 1) / (16 * NTL));
   const dim3 grid(tiles, (a.pk.Coutp + 16 * MT - 1) / (16 * MT), a.B);
-  const size_t lds = (size_t)(kConvTH + 2) * (16 * NTL + 2) * (a.pk.CC + 8) * sizeof(uint16_t);
+  size_t lds = (size_t)(kConvTH + 2) * (16 * NTL + 2) * (a.pk.CC + 8) * sizeof(uint16_t);
+  const bool up = outf32 && a.rt.gA && a.rt.modeA == 1;
+  // an upsampled route exchanges two waves' MT x NTL x 4 sums per lane
+  if (up) lds = std::max(lds, (size_t)2 * MT * NTL * 4 * 64 * sizeof(float));
+  if constexpr (MT == 4) {
+    if (up) {
+      hipLaunchKernelGGL((k_conv3<true, true, MT, NTL, true>), grid, dim3(256), lds, s, a);
+      return;
+    }
+  }
   if (af32 && outf32) hipLaunchKernelGGL((k_conv3<true, true, MT, NTL>), grid, dim3(256), lds, s, a);
   else if (af32) hipLaunchKernelGGL((k_conv3<true, false, MT, NTL>), grid, dim3(256), lds, s, a);
   else if (outf32) hipLaunchKernelGGL((k_conv3<false, true, MT, NTL>), grid, dim3(256), lds, s, a);
@@ -753,8 +822,11 @@ static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t 
 }
 
 hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
+  const bool up = outf32 && a.rt.gA && a.rt.modeA == 1;
+  if (up && !af32) return hipErrorInvalidValue;  // routes carry FP32 gradients
   // one 16-channel tile of outputs: a wave takes 128 columns instead of 32
-  if (a.pk.Coutp <= 16) conv3_launch<1, 8>(a, af32, outf32, s);
+  // (the upsampled route takes 4 x 2 tiles)
+  if (a.pk.Coutp <= 16 && !up) conv3_launch<1, 8>(a, af32, outf32, s);
   else conv3_launch<4, 2>(a, af32, outf32, s);
   return hipGetLastError();
 }
@@ -786,13 +858,6 @@ hipError_t launch_bias(const BiasArgs& a, int nblk, float* gb, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
-  const int Ha = a.modeA == 1 ? a.H / 2 : (a.modeA == 2 ? a.H * 2 : a.H);
-  const int Wa = a.modeA == 1 ? a.W / 2 : (a.modeA == 2 ? a.W * 2 : a.W);
-  const long long n = (long long)a.B * Ha * Wa * a.Ca + (a.gB ? (long long)a.B * a.H * a.W * a.Cb : 0);
-  hipLaunchKernelGGL(k_route, dim3(grid_for(n)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
 
 size_t head_fwd_lds(int P, int C1) { return (size_t)(P * C1 + P + C1 + 1) * 4; }
 size_t head_bwd_lds(int P, int C1) {
@@ -829,10 +894,6 @@ hipError_t launch_adamw(float* th, const float* g, float* m, float* v, long long
   return hipGetLastError();
 }
 
-hipError_t launch_zero(float* p, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
 
 hipError_t unet_kernels_init() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_head_bwd),
