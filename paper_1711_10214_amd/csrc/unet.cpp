@@ -27,12 +27,12 @@ int set_error(int code, const std::string& msg);
 namespace unet {
 hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s);
-hipError_t launch_wgrad_reduce(const float* part, int nsplit, int Cout, int Cin, int Cipw, float* grad,
-                               hipStream_t s);
-hipError_t launch_bias(const BiasArgs& a, int nblk, float* gb, hipStream_t s);
+hipError_t launch_wgrad_reduce(const float* part, const float* bpart, int nsplit, int Cout, int Cin, int Cipw,
+                               float* grad, float* gb, hipStream_t s);
+int wgrad_cot(int Cout);
 hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s);
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s);
-hipError_t launch_pack(const PackArgs& a, hipStream_t s);
+hipError_t launch_pack(const PackAll& a, hipStream_t s);
 hipError_t launch_adamw(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
                         float eps, float wd, float bc1, float bc2, hipStream_t s);
 hipError_t unet_kernels_init();
@@ -52,7 +52,6 @@ int fail(int code, const std::string& m) { return ashrt::set_error(code, m); }
   } while (0)
 
 constexpr int kNConv = 18;
-constexpr int kBiasBlocks = 1024;
 constexpr int kWgradTargetGroups = 1024;
 
 ConvPack make_pack(int Cin, int Cout) {
@@ -188,7 +187,7 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
   w.y_w = take(npix0 * 4);
   if (train) {
     w.gact.resize(kNConv);
-    long long wp = 0;
+    long long wp = 0, bp = 0;
     w.nsplit.resize(kNConv);
     for (int i = 0; i < kNConv; ++i) {
       const Layer& l = n.L[i];
@@ -196,13 +195,15 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
       w.gact[i] = take((long long)B * Hl * Wl * l.co * 4);
       const int cipw = wgrad_cipw(l), ccw = wgrad_ccw(l);
       const long long T = (long long)B * ((Hl + kWgTH - 1) / kWgTH) * ((Wl + kWgTW - 1) / kWgTW);
-      const long long groups = (long long)(cipw / ccw) * ((l.co + kWgCoT - 1) / kWgCoT);
+      const int cot = wgrad_cot(l.co);
+      const long long groups = (long long)(cipw / ccw) * ((l.co + cot - 1) / cot);
       const int ns = (int)std::max(1LL, std::min(T, (long long)kWgradTargetGroups / std::max(1LL, groups)));
       w.nsplit[i] = ns;
       wp = std::max(wp, (long long)ns * l.co * 9 * cipw);
+      bp = std::max(bp, (long long)ns * l.co);
     }
     w.wpart = take(wp * 4);
-    w.bpart = take((long long)kBiasBlocks * 8 * n.base * 4);
+    w.bpart = take(bp * 4);
     w.nblk_h = (int)((npix0 + 255) / 256);
     const int ne = n.pout * n.base + n.pout + n.base + 1;
     w.hpart = take((long long)w.nblk_h * ne * 4);
@@ -307,14 +308,6 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     const int Hl = H >> l.level, Wl = W >> l.level;
     const float* gY = (const float*)(ws + w.gact[i]);
     const uint16_t* Y = (const uint16_t*)(ws + w.act[i]);
-    BiasArgs ba{};
-    ba.gY = gY;
-    ba.Y = Y;
-    ba.C = l.co;
-    ba.npix = (long long)B * Hl * Wl;
-    ba.part = (float*)(ws + w.bpart);
-    U_TRY(launch_bias(ba, kBiasBlocks, g + l.boff, s));
-
     WgradArgs wa{};
     wa.in = conv_input(n, w, ws, x, i, H, W);
     wa.gY = gY;
@@ -325,10 +318,11 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     wa.CCw = wgrad_ccw(l);
     wa.nccw = wa.Cipw / wa.CCw;
     wa.part = (float*)(ws + w.wpart);
+    wa.bpart = (float*)(ws + w.bpart);
     wa.nsplit = w.nsplit[i];
     wa.B = B;
     U_TRY(launch_wgrad(wa, l.srcA < 0, s));
-    U_TRY(launch_wgrad_reduce(wa.part, wa.nsplit, l.co, l.ci, wa.Cipw, g + l.woff, s));
+    U_TRY(launch_wgrad_reduce(wa.part, wa.bpart, wa.nsplit, l.co, l.ci, wa.Cipw, g + l.woff, g + l.boff, s));
 
     if (i == 0) continue;
     ConvArgs da{};
@@ -361,16 +355,23 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
 }
 
 int refresh_packed(const unet_net& n, hipStream_t s) {
+  static_assert(kNConv <= kPackMax, "pack table too small");
+  PackAll p{};
+  p.n = kNConv;
+  p.start[0] = 0;
   for (int i = 0; i < kNConv; ++i) {
     const Layer& l = n.L[i];
-    PackArgs p{};
-    p.W = n.theta + l.woff;
-    p.Wp = n.wpk + l.wp_off;
-    p.Wtp = i > 0 ? n.wpk + l.wtp_off : nullptr;
-    p.f = l.f;
-    p.t = l.t;
-    U_TRY(launch_pack(p, s));
+    PackArgs& a = p.L[i];
+    a.W = n.theta + l.woff;
+    a.Wp = n.wpk + l.wp_off;
+    a.Wtp = i > 0 ? n.wpk + l.wtp_off : nullptr;
+    a.f = l.f;
+    a.t = l.t;
+    const long long ne = (long long)l.f.Coutp * l.f.ncc * l.f.KKp * l.f.CC +
+                         (a.Wtp ? (long long)l.t.Coutp * l.t.ncc * l.t.KKp * l.t.CC : 0);
+    p.start[i + 1] = p.start[i] + (int)ne;
   }
+  U_TRY(launch_pack(p, s));
   return ASHRT_OK;
 }
 

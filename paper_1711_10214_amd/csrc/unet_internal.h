@@ -17,7 +17,6 @@ namespace unet {
 constexpr int kConvTH = 4;    // output rows per conv workgroup (one per wave)
 constexpr int kWgTH = 4;      // pixel tile of the weight-gradient kernel (rows)
 constexpr int kWgTW = 32;     //                                      (columns)
-constexpr int kWgCoT = 64;    // output channels per weight-gradient workgroup
 
 // Input of a convolution as its loader sees it: channels [0, Ca) come from
 // tensor A (mode 0: same resolution; 1: A at half resolution, nearest 2x
@@ -70,24 +69,26 @@ struct WgradArgs {
   int Cout, Cin;            // real counts
   int CCw, nccw, Cipw;      // channel chunk of the reduction tile (16 or 32), chunks, padded count
   float* part;              // [nsplit][Cout][9][Cipw]
+  float* bpart;             // [nsplit][Cout] bias partials (from channel chunk 0)
   int nsplit, B;
 };
 
 struct PackArgs {
   const float* W;           // canonical [Cout][Cin][3][3]
   uint16_t* Wp;             // forward packing
-  uint16_t* Wtp;            // transposed packing (input = Cout channels, output = Cin)
+  uint16_t* Wtp;            // transposed packing (input = Cout channels, output = Cin), or null
   ConvPack f, t;
 };
-
-
-struct BiasArgs {
-  const float* gY;
-  const uint16_t* Y;
-  int C;
-  long long npix;
-  float* part;              // [nblk][C]
+// Every convolution's packings in one launch: packed element e belongs to
+// layer l with start[l] <= e < start[l + 1] (forward packing first).
+constexpr int kPackMax = 20;
+struct PackAll {
+  int n;
+  int start[kPackMax + 1];
+  PackArgs L[kPackMax];
 };
+
+
 
 struct HeadArgs {
   const uint16_t* h;        // BF16 NHWC [B][H][W][C1]

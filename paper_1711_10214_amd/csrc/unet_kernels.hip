@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
   constexpr int TW = 16 * NTL;
   constexpr int TW2 = TW + 2;
   // input tile [row][col][channel], (kConvTH + 2) x TW2 pixels of CC + 8
-  // channel slots (dynamic: conv3_lds)
+  // channel slots (dynamic: conv3_launch)
   extern __shared__ __attribute__((aligned(16))) uint16_t sX[];
   const int H = a.in.H, W = a.in.W;
   const int tiles_x = (W + TW - 1) / TW;
@@ -335,40 +335,64 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
 }
 
 // ------------------------------------------------------------ weight gradient
-// Grid: (input-channel chunks, output-channel tiles of 64, pixel splits).
-// Wave w accumulates the taps kk = w, w + 4, w + 8.
-template <bool AF32>
+// Grid: (input-channel chunks, output-channel tiles of COT, pixel splits).
+// Wave w accumulates the taps kk = w, w + 4, w + 8.  Both operands are
+// staged in LDS pixel-major with channels contiguous (one 16-byte store per
+// 8 channels of a pixel, the tap shift being a per-lane address offset) and
+// read as MFMA fragments with the gfx950 LDS transpose read: for each group
+// of 16 lanes, lane 4 r + q loads four consecutive channels 4 q + [0, 4) of
+// pixel r, and lane c receives channel c of pixels 0..3.  Two such reads
+// (pixels 8 s + [0, 4) and 8 s + [4, 8)) give lane (s, c) the eight
+// consecutive pixels of k-group s of channel c.
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef short v8i16 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+
+__device__ __forceinline__ bf16x8 tr_frag(const uint16_t* p, int step) {
+  const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16*)((__attribute__((address_space(3))) uint16_t*)p));
+  const v4i16 hi =
+      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16*)((__attribute__((address_space(3))) uint16_t*)(p + step)));
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+template <bool AF32, int COT>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
-  constexpr int ZS = kWgTH * kWgTW + 8;  // LDS stride between output channels
-  constexpr int XR = kWgTH + 2;
-  constexpr int XS = XR * kWgTW + 8;     // LDS stride between input channels
-  __shared__ __attribute__((aligned(16))) uint16_t sZ[kWgCoT * ZS];
-  __shared__ __attribute__((aligned(16))) uint16_t sX[3 * 32 * XS];
+  constexpr int MT = COT / 16;
+  constexpr int NG = COT / 8;            // 8-channel groups of the output gradient
+  constexpr int ZP = COT + 8;            // LDS pixel stride of the output gradient
+  constexpr int XW = kWgTW + 2, XR = kWgTH + 2;
+  constexpr int XP = 32 + 8;             // LDS pixel stride of the input (chunks of up to 32 channels)
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[kWgTH * kWgTW * ZP];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[XR * XW * XP];
   const int H = a.in.H, W = a.in.W;
-  const int cc = (int)blockIdx.x, co0 = (int)blockIdx.y * kWgCoT, split = (int)blockIdx.z;
+  const int cc = (int)blockIdx.x, co0 = (int)blockIdx.y * COT, split = (int)blockIdx.z;
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int sub = lane >> 4, n16 = lane & 15;
-  const int MI = min(4, (a.Cout - co0 + 15) >> 4);
+  const int MI = min(MT, (a.Cout - co0 + 15) >> 4);
   const int NI = a.CCw >> 4;
   const int ngx = a.CCw >> 3;
   const int tiles_x = (W + kWgTW - 1) / kWgTW, tiles_y = (H + kWgTH - 1) / kWgTH;
   const int T = a.B * tiles_x * tiles_y;
+  // this lane's transpose-read offsets: pixel n16 / 4 of its k-group, channel quad n16 % 4
+  const int kp = 8 * sub + (n16 >> 2), cq = 4 * (n16 & 3);
 
-  f32x4 acc[3][4][2];
+  f32x4 acc[3][MT][2];
 #pragma unroll
   for (int s = 0; s < 3; ++s)
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) acc[s][mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // bias partial: thread t always stages channel group t % NG
+  float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
   for (int t = split; t < T; t += a.nsplit) {
     const int b = t / (tiles_x * tiles_y);
     const int rem = t - b * tiles_x * tiles_y;
     const int ty0 = (rem / tiles_x) * kWgTH, tx0 = (rem % tiles_x) * kWgTW;
-    // output gradient, ReLU-masked, transposed to [co][row][col]
-    for (int task = threadIdx.x; task < kWgTH * kWgTW * (kWgCoT / 8); task += 256) {
-      const int g = task & 7, pix = task >> 3;
+    // output gradient, ReLU-masked, [pixel][co]
+    for (int task = threadIdx.x; task < kWgTH * kWgTW * NG; task += 256) {
+      const int g = task % NG, pix = task / NG;
       const int row = pix / kWgTW, px = pix - row * kWgTW;
       const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
       float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -389,30 +413,23 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         }
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) sZ[(g * 8 + i) * ZS + row * kWgTW + px] = (uint16_t)f2bf(v[i]);
+      for (int i = 0; i < 8; ++i) bsum[i] += v[i];
+      *reinterpret_cast<uint4*>(sZ + pix * ZP + g * 8) = pack8(v);
     }
-    // input tile with a one-pixel halo, as three column-shifted copies
-    for (int task = threadIdx.x; task < XR * (kWgTW + 2) * ngx; task += 256) {
+    // input tile with a one-pixel halo, [pixel][ci]
+    for (int task = threadIdx.x; task < XR * XW * ngx; task += 256) {
       const int g = task % ngx, pix = task / ngx;
-      const int row = pix / (kWgTW + 2), px = pix - row * (kWgTW + 2);
+      const int row = pix / XW, px = pix - row * XW;
       float v[8];
       load_in8<AF32>(a.in, b, ty0 + row - 1, tx0 + px - 1, cc * a.CCw + g * 8, v);
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int txp = px - dx;
-        if (txp >= 0 && txp < kWgTW) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) sX[(dx * 32 + g * 8 + i) * XS + row * kWgTW + txp] = (uint16_t)f2bf(v[i]);
-        }
-      }
+      *reinterpret_cast<uint4*>(sX + pix * XP + g * 8) = pack8(v);
     }
     __syncthreads();
     for (int row = 0; row < kWgTH; ++row) {
-      bf16x8 af[4];
+      bf16x8 af[MT];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
-        af[mi] = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const uint4*>(sZ + (mi * 16 + n16) * ZS + row * kWgTW + sub * 8));
+      for (int mi = 0; mi < MT; ++mi)
+        af[mi] = mi < MI ? tr_frag(sZ + (row * kWgTW + kp) * ZP + mi * 16 + cq, 4 * ZP) : bf16x8{};
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int kk = wave + 4 * s;
@@ -421,10 +438,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) {
           if (ni >= NI) continue;
-          const bf16x8 bf = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const uint4*>(sX + (dx * 32 + ni * 16 + n16) * XS + (row + dy) * kWgTW + sub * 8));
+          const bf16x8 bf = tr_frag(sX + ((row + dy) * XW + kp + dx) * XP + ni * 16 + cq, 4 * XP);
 #pragma unroll
-          for (int mi = 0; mi < 4; ++mi)
+          for (int mi = 0; mi < MT; ++mi)
             if (mi < MI) acc[s][mi][ni] = mfma(af[mi], bf, acc[s][mi][ni]);
         }
       }
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     const int kk = wave + 4 * s;
     if (kk >= 9) continue;
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi) {
+    for (int mi = 0; mi < MT; ++mi) {
       if (mi >= MI) continue;
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) {
@@ -452,28 +468,44 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       }
     }
   }
+  // bias partial of this split (channel chunk 0 only): the threads of one
+  // channel group are added in thread order
+  if (a.bpart && cc == 0) {
+    float* red = reinterpret_cast<float*>(sX);  // the loop ended with a barrier
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[threadIdx.x * 8 + i] = bsum[i];
+    __syncthreads();
+    const int c = (int)threadIdx.x;
+    if (c < COT && co0 + c < a.Cout) {
+      float sum = 0.f;
+      for (int k = c >> 3; k < 256; k += NG) sum += red[k * 8 + (c & 7)];
+      a.bpart[(long long)split * a.Cout + co0 + c] = sum;
+    }
+  }
 }
 
 // Sum the pixel-split partials into the canonical weight gradient
-// [Cout][Cin][3][3] (fixed order over the splits).
+// [Cout][Cin][3][3] and the bias gradient (fixed order over the splits).
 // grad[co][ci][kk] = sum over the pixel splits of the partials.  A
 // workgroup takes E gradient elements and 256 / E thread groups
 // over the splits (split sp -> group sp mod G); the G partial sums of an
 // element are added in group order, so the result does not depend on timing.
+// Elements past the Cout Cin 9 weights are the Cout biases.
 template <int E>
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nsplit, int Cout, int Cin,
-                                                     int Cipw, float* __restrict__ grad) {
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ bpart,
+                                                     int nsplit, int Cout, int Cin, int Cipw, float* __restrict__ grad,
+                                                     float* __restrict__ gb) {
   constexpr int G = 256 / E;
   __shared__ float s[G][E + 1];
   const int te = (int)threadIdx.x % E, g = (int)threadIdx.x / E;
-  const int n = Cout * Cin * 9;
+  const int nw = Cout * Cin * 9, n = nw + Cout;
   // elements enumerated in the partials' order (co, kk, ci), ci fastest, so
   // neighbouring threads read neighbouring floats
   for (int j0 = blockIdx.x * E; j0 < n; j0 += gridDim.x * E) {
     const int j = j0 + te;
     float acc = 0.f;
     int co = 0, kk = 0, ci = 0;
-    if (j < n) {
+    if (j < nw) {
       co = j / (9 * Cin);
       const int r = j - co * 9 * Cin;
       kk = r / Cin;
@@ -481,47 +513,18 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
       const long long stride = (long long)Cout * 9 * Cipw;
       const float* p = part + ((long long)co * 9 + kk) * Cipw + ci;
       for (int sp = g; sp < nsplit; sp += G) acc += p[sp * stride];
+    } else if (j < n) {
+      for (int sp = g; sp < nsplit; sp += G) acc += bpart[(long long)sp * Cout + (j - nw)];
     }
     s[g][te] = acc;
     __syncthreads();
     if (g == 0 && j < n) {
       float t = 0.f;
       for (int q = 0; q < G; ++q) t += s[q][te];
-      grad[((long long)co * Cin + ci) * 9 + kk] = t;
+      if (j < nw) grad[((long long)co * Cin + ci) * 9 + kk] = t;
+      else gb[j - nw] = t;
     }
     __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------ bias gradient
-// Per-block partial sums of the ReLU-masked output gradient per channel
-// (C divides 256), then a fixed-order sum over the blocks.
-__global__ __launch_bounds__(256) void k_bias_part(BiasArgs a) {
-  __shared__ float s[256];
-  const int C = a.C, tid = (int)threadIdx.x, c = tid % C, q = tid / C, Q = 256 / C;
-  float sum = 0.f;
-  // four pixels' loads in flight per thread (indices past the end clamped
-  // for the loads, skipped in the sum, which keeps the pixel order)
-  const long long stride = (long long)gridDim.x * Q;
-  for (long long p0 = (long long)blockIdx.x * Q + q; p0 < a.npix; p0 += 4 * stride) {
-    float g[4];
-    uint16_t y[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const long long o = min(p0 + u * stride, a.npix - 1) * C + c;
-      g[u] = a.gY[o];
-      y[u] = a.Y ? a.Y[o] : (uint16_t)0x3f80u;  // 1.0 when there is no ReLU mask
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (p0 + u * stride < a.npix) sum += relu_on(y[u]) ? g[u] : 0.f;
-  }
-  s[tid] = sum;
-  __syncthreads();
-  if (tid < C) {
-    float t = 0.f;
-    for (int k = 0; k < Q; ++k) t += s[k * C + tid];
-    a.part[(long long)blockIdx.x * C + tid] = t;
   }
 }
 
@@ -755,28 +758,30 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const double* __restrict__ 
 }
 
 // ------------------------------------------------------------ parameters
-__global__ __launch_bounds__(256) void k_pack(PackArgs a) {
-  const long long nf = (long long)a.f.Coutp * a.f.ncc * a.f.KKp * a.f.CC;
-  const long long nt = a.Wtp ? (long long)a.t.Coutp * a.t.ncc * a.t.KKp * a.t.CC : 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nf + nt;
-       i += (long long)gridDim.x * blockDim.x) {
-    const bool fw = i < nf;
-    const ConvPack& P = fw ? a.f : a.t;
-    long long r = fw ? i : i - nf;
-    const int c = (int)(r % P.CC);
+__global__ __launch_bounds__(256) void k_pack(PackAll a) {
+  for (int e = (int)(blockIdx.x * blockDim.x + threadIdx.x); e < a.start[a.n]; e += (int)(gridDim.x * blockDim.x)) {
+    int l = 0;
+    while (e >= a.start[l + 1]) ++l;
+    const PackArgs& L = a.L[l];
+    const int nf = L.f.Coutp * L.f.ncc * L.f.KKp * L.f.CC;
+    const bool fw = e - a.start[l] < nf;
+    const ConvPack& P = fw ? L.f : L.t;
+    const int i = fw ? e - a.start[l] : e - a.start[l] - nf;
+    int r = i;
+    const int c = r % P.CC;
     r /= P.CC;
-    const int kk = (int)(r % P.KKp);
+    const int kk = r % P.KKp;
     r /= P.KKp;
-    const int cc = (int)(r % P.ncc);
-    const int co = (int)(r / P.ncc);
+    const int cc = r % P.ncc;
+    const int co = r / P.ncc;
     const int ci = cc * P.CC + c;
     float v = 0.f;
     if (co < P.Cout && ci < P.Cin && kk < 9) {
       // forward: W[co][ci][kk]; transposed: output = forward input channel
       // co, input = forward output channel ci, taps flipped
-      v = fw ? a.W[((long long)co * P.Cin + ci) * 9 + kk] : a.W[((long long)ci * P.Cout + co) * 9 + (8 - kk)];
+      v = fw ? L.W[((long long)co * P.Cin + ci) * 9 + kk] : L.W[((long long)ci * P.Cout + co) * 9 + (8 - kk)];
     }
-    (fw ? a.Wp : a.Wtp)[fw ? i : i - nf] = (uint16_t)f2bf(v);
+    (fw ? L.Wp : L.Wtp)[i] = (uint16_t)f2bf(v);
   }
 }
 
@@ -806,24 +811,23 @@ static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t 
   const int tiles = ((a.in.H + kConvTH - 1) / kConvTH) * ((a.in.W + 16 * NTL - 1) / (16 * NTL));
   const dim3 grid(tiles, (a.pk.Coutp + 16 * MT - 1) / (16 * MT), a.B);
   size_t lds = (size_t)(kConvTH + 2) * (16 * NTL + 2) * (a.pk.CC + 8) * sizeof(uint16_t);
-  const bool up = outf32 && a.rt.gA && a.rt.modeA == 1;
-  // an upsampled route exchanges two waves' MT x NTL x 4 sums per lane
-  if (up) lds = std::max(lds, (size_t)2 * MT * NTL * 4 * 64 * sizeof(float));
   if constexpr (MT == 4) {
-    if (up) {
+    if (outf32 && a.rt.gA && a.rt.modeA == 1) {
+      // an upsampled route exchanges two waves' MT x NTL x 4 sums per lane
+      lds = std::max(lds, (size_t)2 * MT * NTL * 4 * 64 * sizeof(float));
       hipLaunchKernelGGL((k_conv3<true, true, MT, NTL, true>), grid, dim3(256), lds, s, a);
       return;
     }
   }
   if (af32 && outf32) hipLaunchKernelGGL((k_conv3<true, true, MT, NTL>), grid, dim3(256), lds, s, a);
   else if (af32) hipLaunchKernelGGL((k_conv3<true, false, MT, NTL>), grid, dim3(256), lds, s, a);
-  else if (outf32) hipLaunchKernelGGL((k_conv3<false, true, MT, NTL>), grid, dim3(256), lds, s, a);
   else hipLaunchKernelGGL((k_conv3<false, false, MT, NTL>), grid, dim3(256), lds, s, a);
 }
 
 hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
   const bool up = outf32 && a.rt.gA && a.rt.modeA == 1;
-  if (up && !af32) return hipErrorInvalidValue;  // routes carry FP32 gradients
+  // FP32 outputs are input gradients: FP32 input, routed or not
+  if (outf32 && !af32) return hipErrorInvalidValue;
   // one 16-channel tile of outputs: a wave takes 128 columns instead of 32
   // (the upsampled route takes 4 x 2 tiles)
   if (a.pk.Coutp <= 16 && !up) conv3_launch<1, 8>(a, af32, outf32, s);
@@ -831,33 +835,34 @@ hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
-  const dim3 grid(a.nccw, (a.Cout + kWgCoT - 1) / kWgCoT, a.nsplit);
-  if (af32) hipLaunchKernelGGL((k_wgrad<true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_wgrad<false>), grid, dim3(256), 0, s, a);
-  return hipGetLastError();
-}
+int wgrad_cot(int Cout) { return Cout <= 16 ? 16 : 64; }
 
-hipError_t launch_wgrad_reduce(const float* part, int nsplit, int Cout, int Cin, int Cipw, float* grad,
-                               hipStream_t s) {
-  const long long n = (long long)Cout * Cin * 9;
-  if (n >= 16 * 256) {
-    const long long g = (n + 15) / 16;
-    hipLaunchKernelGGL(k_wgrad_reduce<16>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, part, nsplit,
-                       Cout, Cin, Cipw, grad);
+hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
+  const int cot = wgrad_cot(a.Cout);
+  const dim3 grid(a.nccw, (a.Cout + cot - 1) / cot, a.nsplit);
+  if (cot == 16) {
+    if (af32) hipLaunchKernelGGL((k_wgrad<true, 16>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_wgrad<false, 16>), grid, dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_wgrad_reduce<4>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, part, nsplit, Cout, Cin,
-                       Cipw, grad);
+    if (af32) hipLaunchKernelGGL((k_wgrad<true, 64>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_wgrad<false, 64>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_bias(const BiasArgs& a, int nblk, float* gb, hipStream_t s) {
-  hipLaunchKernelGGL(k_bias_part, dim3(nblk), dim3(256), 0, s, a);
-  sum_parts((const float*)a.part, nblk, a.C, gb, s);
+hipError_t launch_wgrad_reduce(const float* part, const float* bpart, int nsplit, int Cout, int Cin, int Cipw,
+                               float* grad, float* gb, hipStream_t s) {
+  const long long n = (long long)Cout * Cin * 9 + Cout;
+  if (n >= 16 * 256) {
+    const long long g = (n + 15) / 16;
+    hipLaunchKernelGGL(k_wgrad_reduce<16>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, part, bpart,
+                       nsplit, Cout, Cin, Cipw, grad, gb);
+  } else {
+    hipLaunchKernelGGL(k_wgrad_reduce<4>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, part, bpart, nsplit, Cout,
+                       Cin, Cipw, grad, gb);
+  }
   return hipGetLastError();
 }
-
 
 size_t head_fwd_lds(int P, int C1) { return (size_t)(P * C1 + P + C1 + 1) * 4; }
 size_t head_bwd_lds(int P, int C1) {
@@ -881,10 +886,8 @@ hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* lo
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
-  const long long n = (long long)a.f.Coutp * a.f.ncc * a.f.KKp * a.f.CC +
-                      (a.Wtp ? (long long)a.t.Coutp * a.t.ncc * a.t.KKp * a.t.CC : 0);
-  hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(256), 0, s, a);
+hipError_t launch_pack(const PackAll& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(a.start[a.n])), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
