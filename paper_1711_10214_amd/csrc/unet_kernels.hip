@@ -115,6 +115,102 @@ __device__ __forceinline__ void load_in8(const ConvIn& I, int b, int y, int x, i
   }
 }
 
+// Source of channels [c, c + 8) of conv-input pixel (b, y, x) for a BF16
+// loader without pooling (A at the same or at half resolution, and the
+// skip): one 16-byte load, or null where the channels are zero.
+__device__ __forceinline__ const uint4* in8_src(const ConvIn& I, int b, int y, int x, int c) {
+  if (y < 0 || y >= I.H || x < 0 || x >= I.W) return nullptr;
+  if (c < I.Ca) {
+    const uint16_t* A = static_cast<const uint16_t*>(I.A);
+    if (I.modeA == 0) return reinterpret_cast<const uint4*>(A + (((long long)b * I.H + y) * I.W + x) * I.Ca + c);
+    const int Ha = I.H >> 1, Wa = I.W >> 1;
+    return reinterpret_cast<const uint4*>(A + (((long long)b * Ha + (y >> 1)) * Wa + (x >> 1)) * I.Ca + c);
+  }
+  if (c < I.Ca + I.Cb)
+    return reinterpret_cast<const uint4*>(I.Bs + (((long long)b * I.H + y) * I.W + x) * I.Cb + (c - I.Ca));
+  return nullptr;
+}
+
+// Stage the (rows x cols) input tile of channel chunk [c0, c0 + 8 ng) into
+// LDS as [pixel][channel] with pixel stride PS, pixel (r, q) of the tile
+// being input pixel (y0 + r, x0 + q).  Loaders that need one load per 8
+// channels (BF16, no pooling) and the masked FP32 gradient issue the loads
+// of several tasks before storing any, so that a thread waits on one
+// memory latency per group of tasks rather than per task.
+template <bool AF32>
+__device__ __forceinline__ void stage_tile(const ConvIn& I, int b, int y0, int x0, int rows, int cols, int c0,
+                                           int ng, uint16_t* dst, int PS) {
+  const int ntask = rows * cols * ng;
+  if (!AF32 && I.modeA != 2) {
+    constexpr int U = 4;
+    for (int t0 = threadIdx.x; t0 < ntask; t0 += U * 256) {
+      uint4 q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int task = t0 + u * 256;
+        q[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (task < ntask) {
+          const int g = task % ng, pix = task / ng;
+          const int r = pix / cols, x = pix - r * cols;
+          const uint4* src = in8_src(I, b, y0 + r, x0 + x, c0 + g * 8);
+          if (src) q[u] = *src;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int task = t0 + u * 256;
+        if (task < ntask) *reinterpret_cast<uint4*>(dst + (task / ng) * PS + (task % ng) * 8) = q[u];
+      }
+    }
+  } else if (AF32 && I.Ca > 1 && I.Cb == 0 && I.modeA == 0) {
+    constexpr int U = 2;
+    const float* A = static_cast<const float*>(I.A);
+    for (int t0 = threadIdx.x; t0 < ntask; t0 += U * 256) {
+      float4 p[U], q[U];
+      uint4 m[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int task = t0 + u * 256;
+        p[u] = q[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        m[u] = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);  // 1.0: no mask
+        if (task < ntask) {
+          const int g = task % ng, pix = task / ng;
+          const int r = pix / cols, x = pix - r * cols;
+          const int y = y0 + r, xx = x0 + x, c = c0 + g * 8;
+          if (y >= 0 && y < I.H && xx >= 0 && xx < I.W && c < I.Ca) {
+            const long long o = (((long long)b * I.H + y) * I.W + xx) * I.Ca + c;
+            p[u] = *reinterpret_cast<const float4*>(A + o);
+            q[u] = *reinterpret_cast<const float4*>(A + o + 4);
+            if (I.Amask) m[u] = *reinterpret_cast<const uint4*>(I.Amask + o);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int task = t0 + u * 256;
+        if (task < ntask) {
+          float v[8] = {p[u].x, p[u].y, p[u].z, p[u].w, q[u].x, q[u].y, q[u].z, q[u].w};
+          const uint32_t mm[4] = {m[u].x, m[u].y, m[u].z, m[u].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (!relu_on(mm[i] & 0xFFFFu)) v[2 * i] = 0.f;
+            if (!relu_on(mm[i] >> 16)) v[2 * i + 1] = 0.f;
+          }
+          *reinterpret_cast<uint4*>(dst + (task / ng) * PS + (task % ng) * 8) = pack8(v);
+        }
+      }
+    }
+  } else {
+    for (int task = threadIdx.x; task < ntask; task += 256) {
+      const int g = task % ng, pix = task / ng;
+      const int r = pix / cols, x = pix - r * cols;
+      float v[8];
+      load_in8<AF32>(I, b, y0 + r, x0 + x, c0 + g * 8, v);
+      *reinterpret_cast<uint4*>(dst + pix * PS + g * 8) = pack8(v);
+    }
+  }
+}
+
 // ------------------------------------------------------------ routed epilogue
 // float4 store or accumulate of four consecutive channels.
 __device__ __forceinline__ void put4(float* p, float v0, float v1, float v2, float v3, bool add) {
@@ -260,13 +356,7 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
   const int nks = P.ncc * nkc;
 
   for (int cc = 0; cc < P.ncc; ++cc) {
-    for (int task = threadIdx.x; task < (kConvTH + 2) * TW2 * ng; task += 256) {
-      const int g = task % ng, pix = task / ng;
-      const int ty = pix / TW2, tx = pix - ty * TW2;
-      float v[8];
-      load_in8<AF32>(a.in, b, ty0 + ty - 1, tx0 + tx - 1, cc * CC + g * 8, v);
-      *reinterpret_cast<uint4*>(sX + pix * PS + g * 8) = pack8(v);
-    }
+    stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, kConvTH + 2, TW2, cc * CC, ng, sX, PS);
     __syncthreads();
     for (int kc = 0; kc < nkc; ++kc) {
       const int kk = kc * P.TPK + tap_l;
@@ -417,13 +507,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       *reinterpret_cast<uint4*>(sZ + pix * ZP + g * 8) = pack8(v);
     }
     // input tile with a one-pixel halo, [pixel][ci]
-    for (int task = threadIdx.x; task < XR * XW * ngx; task += 256) {
-      const int g = task % ngx, pix = task / ngx;
-      const int row = pix / XW, px = pix - row * XW;
-      float v[8];
-      load_in8<AF32>(a.in, b, ty0 + row - 1, tx0 + px - 1, cc * a.CCw + g * 8, v);
-      *reinterpret_cast<uint4*>(sX + pix * XP + g * 8) = pack8(v);
-    }
+    stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, XR, XW, cc * a.CCw, ngx, sX, XP);
     __syncthreads();
     for (int row = 0; row < kWgTH; ++row) {
       bf16x8 af[MT];
