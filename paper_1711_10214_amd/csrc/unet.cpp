@@ -52,7 +52,14 @@ int fail(int code, const std::string& m) { return ashrt::set_error(code, m); }
   } while (0)
 
 constexpr int kNConv = 18;
+// Pixel splits of a weight gradient: at most kWgradTargetGroups workgroups,
+// and no more splits than balance the FP32 partials each split writes (and
+// the reduction reads back) against the tiles each workgroup walks in
+// sequence: with P partial bytes per split and T pixel tiles, about
+// sqrt(T kWgradTileBytes / P) splits, kWgradTileBytes being the partial
+// traffic that costs about as long as one tile's load latency.
 constexpr int kWgradTargetGroups = 1024;
+constexpr double kWgradTileBytes = 6e6;
 
 ConvPack make_pack(int Cin, int Cout) {
   ConvPack p{};
@@ -197,7 +204,10 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
       const long long T = (long long)B * ((Hl + kWgTH - 1) / kWgTH) * ((Wl + kWgTW - 1) / kWgTW);
       const int cot = wgrad_cot(l.co);
       const long long groups = (long long)(cipw / ccw) * ((l.co + cot - 1) / cot);
-      const int ns = (int)std::max(1LL, std::min(T, (long long)kWgradTargetGroups / std::max(1LL, groups)));
+      const double pbytes = (double)l.co * 9 * cipw * 4;
+      const long long nbal = std::max(1LL, (long long)std::sqrt((double)T * kWgradTileBytes / pbytes));
+      const int ns = (int)std::max(
+          1LL, std::min({T, (long long)kWgradTargetGroups / std::max(1LL, groups), nbal}));
       w.nsplit[i] = ns;
       wp = std::max(wp, (long long)ns * l.co * 9 * cipw);
       bp = std::max(bp, (long long)ns * l.co);
@@ -236,7 +246,6 @@ ConvIn conv_input(const unet_net& n, const WsLayout& w, unsigned char* ws, const
   const Layer& l = n.L[i];
   ConvIn in{};
   in.A = l.srcA < 0 ? (const void*)x : (const void*)(ws + w.act[l.srcA]);
-  in.Amask = nullptr;
   in.Bs = l.srcB >= 0 ? (const uint16_t*)(ws + w.act[l.srcB]) : nullptr;
   in.Ca = l.Ca;
   in.Cb = l.Cb;
@@ -307,11 +316,9 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     const Layer& l = n.L[i];
     const int Hl = H >> l.level, Wl = W >> l.level;
     const float* gY = (const float*)(ws + w.gact[i]);
-    const uint16_t* Y = (const uint16_t*)(ws + w.act[i]);
     WgradArgs wa{};
     wa.in = conv_input(n, w, ws, x, i, H, W);
     wa.gY = gY;
-    wa.Y = Y;
     wa.Cout = l.co;
     wa.Cin = l.ci;
     wa.Cipw = wgrad_cipw(l);
@@ -327,7 +334,6 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     if (i == 0) continue;
     ConvArgs da{};
     da.in.A = gY;
-    da.in.Amask = Y;
     da.in.Bs = nullptr;
     da.in.Ca = l.co;
     da.in.Cb = 0;
@@ -342,6 +348,8 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     da.B = B;
     da.rt.gA = (float*)(ws + w.gact[l.srcA]);
     da.rt.gB = l.srcB >= 0 ? (float*)(ws + w.gact[l.srcB]) : nullptr;
+    da.rt.mA = (const uint16_t*)(ws + w.act[l.srcA]);
+    da.rt.mB = l.srcB >= 0 ? (const uint16_t*)(ws + w.act[l.srcB]) : nullptr;
     da.rt.Ca = l.Ca;
     da.rt.Cb = l.srcB >= 0 ? l.Cb : 0;
     da.rt.modeA = l.modeA;

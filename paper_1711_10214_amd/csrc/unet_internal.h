@@ -25,7 +25,6 @@ constexpr int kWgTW = 32;     //                                      (columns)
 // rest up to the padded count are zero.
 struct ConvIn {
   const void* A;            // BF16 NHWC, or FP32 NHWC when the kernel's AF32 is set
-  const uint16_t* Amask;    // FP32 A only: multiply by (Amask > 0) (ReLU derivative), or null
   const uint16_t* Bs;       // BF16 NHWC skip, or null
   int Ca, Cb, modeA;
   int H, W;                 // conv (output) resolution
@@ -46,9 +45,14 @@ struct ConvPack {
 // 2: A at double resolution, each gradient pixel gives a quarter to its four
 // A pixels), channels [Ca, Ca + Cb) to the skip B at the same resolution.  A
 // tensor's first contribution is written, later ones are added (accA, accB).
+// A and B are ReLU outputs: the stored gradient is that of their
+// pre-activations, each value zeroed where the activation (mA, mB) is not
+// positive, which is what every consumer of the gradient needs.
 struct ConvRoute {
   float* gA;                // FP32 NHWC gradient of A, or null: plain output to ConvArgs::out
   float* gB;                // FP32 NHWC gradient of the skip, or null
+  const uint16_t* mA;       // BF16 activation A (ReLU mask), or null
+  const uint16_t* mB;       // BF16 skip activation (ReLU mask), or null
   int Ca, Cb, modeA, accA, accB;
 };
 struct ConvArgs {
@@ -64,8 +68,7 @@ struct ConvArgs {
 
 struct WgradArgs {
   ConvIn in;                // the convolution's input (forward view)
-  const float* gY;          // FP32 NHWC [B][H][W][Cout]: gradient of the conv output
-  const uint16_t* Y;        // BF16 conv output (ReLU mask), or null
+  const float* gY;          // FP32 NHWC [B][H][W][Cout]: gradient of the conv output before its ReLU
   int Cout, Cin;            // real counts
   int CCw, nccw, Cipw;      // channel chunk of the reduction tile (16 or 32), chunks, padded count
   float* part;              // [nsplit][Cout][9][Cipw]
@@ -104,7 +107,7 @@ struct LossArgs {
   const float* t_m;
   const float* t_w;
   float lam_w;
-  float* g_h;               // FP32 NHWC [B][H][W][C1] gradient of the head input
+  float* g_h;               // FP32 NHWC [B][H][W][C1] gradient of the head input's pre-activation (ReLU)
   float* hpart;             // [nblk][17 * P + 17 ... ] head parameter-gradient partials
   double* lpart;            // [nblk][2]
   int ne;                   // entries per head partial: P*C1 + P + C1 + 1

@@ -78,15 +78,6 @@ __device__ __forceinline__ void load_in8(const ConvIn& I, int b, int y, int x, i
         const float4 q = *reinterpret_cast<const float4*>(A + o + 4);
         v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w;
         v[4] = q.x; v[5] = q.y; v[6] = q.z; v[7] = q.w;
-        if (I.Amask) {
-          const uint4 m = *reinterpret_cast<const uint4*>(I.Amask + o);
-          const uint32_t mm[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (!relu_on(mm[i] & 0xFFFFu)) v[2 * i] = 0.f;
-            if (!relu_on(mm[i] >> 16)) v[2 * i + 1] = 0.f;
-          }
-        }
       }
     } else {
       const uint16_t* A = static_cast<const uint16_t*>(I.A);
@@ -133,10 +124,10 @@ __device__ __forceinline__ const uint4* in8_src(const ConvIn& I, int b, int y, i
 
 // Stage the (rows x cols) input tile of channel chunk [c0, c0 + 8 ng) into
 // LDS as [pixel][channel] with pixel stride PS, pixel (r, q) of the tile
-// being input pixel (y0 + r, x0 + q).  Loaders that need one load per 8
-// channels (BF16, no pooling) and the masked FP32 gradient issue the loads
-// of several tasks before storing any, so that a thread waits on one
-// memory latency per group of tasks rather than per task.
+// being input pixel (y0 + r, x0 + q).  Loaders without pooling (BF16
+// activations, the FP32 gradient) issue the loads of several tasks before
+// storing any, so that a thread waits on one memory latency per group of
+// tasks rather than per task.
 template <bool AF32>
 __device__ __forceinline__ void stage_tile(const ConvIn& I, int b, int y0, int x0, int rows, int cols, int c0,
                                            int ng, uint16_t* dst, int PS) {
@@ -163,16 +154,14 @@ __device__ __forceinline__ void stage_tile(const ConvIn& I, int b, int y0, int x
       }
     }
   } else if (AF32 && I.Ca > 1 && I.Cb == 0 && I.modeA == 0) {
-    constexpr int U = 2;
+    constexpr int U = 4;
     const float* A = static_cast<const float*>(I.A);
     for (int t0 = threadIdx.x; t0 < ntask; t0 += U * 256) {
       float4 p[U], q[U];
-      uint4 m[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int task = t0 + u * 256;
         p[u] = q[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        m[u] = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);  // 1.0: no mask
         if (task < ntask) {
           const int g = task % ng, pix = task / ng;
           const int r = pix / cols, x = pix - r * cols;
@@ -181,7 +170,6 @@ __device__ __forceinline__ void stage_tile(const ConvIn& I, int b, int y0, int x
             const long long o = (((long long)b * I.H + y) * I.W + xx) * I.Ca + c;
             p[u] = *reinterpret_cast<const float4*>(A + o);
             q[u] = *reinterpret_cast<const float4*>(A + o + 4);
-            if (I.Amask) m[u] = *reinterpret_cast<const uint4*>(I.Amask + o);
           }
         }
       }
@@ -189,13 +177,7 @@ __device__ __forceinline__ void stage_tile(const ConvIn& I, int b, int y0, int x
       for (int u = 0; u < U; ++u) {
         const int task = t0 + u * 256;
         if (task < ntask) {
-          float v[8] = {p[u].x, p[u].y, p[u].z, p[u].w, q[u].x, q[u].y, q[u].z, q[u].w};
-          const uint32_t mm[4] = {m[u].x, m[u].y, m[u].z, m[u].w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (!relu_on(mm[i] & 0xFFFFu)) v[2 * i] = 0.f;
-            if (!relu_on(mm[i] >> 16)) v[2 * i + 1] = 0.f;
-          }
+          const float v[8] = {p[u].x, p[u].y, p[u].z, p[u].w, q[u].x, q[u].y, q[u].z, q[u].w};
           *reinterpret_cast<uint4*>(dst + (task / ng) * PS + (task % ng) * 8) = pack8(v);
         }
       }
@@ -212,8 +194,16 @@ __device__ __forceinline__ void stage_tile(const ConvIn& I, int b, int y0, int x
 }
 
 // ------------------------------------------------------------ routed epilogue
-// float4 store or accumulate of four consecutive channels.
-__device__ __forceinline__ void put4(float* p, float v0, float v1, float v2, float v3, bool add) {
+// float4 store or accumulate of four consecutive channels, each zeroed where
+// the activation m (four BF16 values, or null: none) is not positive.
+__device__ __forceinline__ void put4(float* p, const uint16_t* m, float v0, float v1, float v2, float v3, bool add) {
+  if (m) {
+    const uint2 h = *reinterpret_cast<const uint2*>(m);
+    if (!relu_on(h.x & 0xFFFFu)) v0 = 0.f;
+    if (!relu_on(h.x >> 16)) v1 = 0.f;
+    if (!relu_on(h.y & 0xFFFFu)) v2 = 0.f;
+    if (!relu_on(h.y >> 16)) v3 = 0.f;
+  }
   float4 o = make_float4(v0, v1, v2, v3);
   if (add) {
     const float4 q = *reinterpret_cast<const float4*>(p);
@@ -276,8 +266,8 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
           float t[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) t[i] = acc[mi][ni][i] + red[((((wave >> 1) * MT + mi) * NTL + ni) * 4 + i) * 64 + lane];
-          put4(R.gA + (((long long)b * Hh + (y >> 1)) * Wh + (x >> 1)) * R.Ca + co, t[0], t[1], t[2], t[3],
-               R.accA != 0);
+          const long long oa = (((long long)b * Hh + (y >> 1)) * Wh + (x >> 1)) * R.Ca + co;
+          put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, t[0], t[1], t[2], t[3], R.accA != 0);
         }
       }
     }
@@ -294,15 +284,18 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
       if (x >= W) continue;
       const f32x4 o = acc[mi][ni];
       if (co >= R.Ca) {
-        put4(R.gB + (((long long)b * H + y) * W + x) * R.Cb + (co - R.Ca), o[0], o[1], o[2], o[3], R.accB != 0);
+        const long long ob = (((long long)b * H + y) * W + x) * R.Cb + (co - R.Ca);
+        put4(R.gB + ob, R.mB ? R.mB + ob : nullptr, o[0], o[1], o[2], o[3], R.accB != 0);
       } else if (R.modeA == 0) {
-        put4(R.gA + (((long long)b * H + y) * W + x) * R.Ca + co, o[0], o[1], o[2], o[3], R.accA != 0);
+        const long long oa = (((long long)b * H + y) * W + x) * R.Ca + co;
+        put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, o[0], o[1], o[2], o[3], R.accA != 0);
       } else {
         const int H2 = 2 * H, W2 = 2 * W;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const long long pa = ((long long)b * H2 + 2 * y + (q >> 1)) * W2 + 2 * x + (q & 1);
-          put4(R.gA + pa * R.Ca + co, 0.25f * o[0], 0.25f * o[1], 0.25f * o[2], 0.25f * o[3], R.accA != 0);
+          const long long oa = (((long long)b * H2 + 2 * y + (q >> 1)) * W2 + 2 * x + (q & 1)) * R.Ca + co;
+          put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, 0.25f * o[0], 0.25f * o[1], 0.25f * o[2], 0.25f * o[3],
+               R.accA != 0);
         }
       }
     }
@@ -480,31 +473,37 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     const int b = t / (tiles_x * tiles_y);
     const int rem = t - b * tiles_x * tiles_y;
     const int ty0 = (rem / tiles_x) * kWgTH, tx0 = (rem % tiles_x) * kWgTW;
-    // output gradient, ReLU-masked, [pixel][co]
-    for (int task = threadIdx.x; task < kWgTH * kWgTW * NG; task += 256) {
-      const int g = task % NG, pix = task / NG;
-      const int row = pix / kWgTW, px = pix - row * kWgTW;
-      const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (y < H && x < W && co < a.Cout) {
-        const long long o = (((long long)b * H + y) * W + x) * a.Cout + co;
-        const float4 p = *reinterpret_cast<const float4*>(a.gY + o);
-        const float4 q = *reinterpret_cast<const float4*>(a.gY + o + 4);
-        v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w;
-        v[4] = q.x; v[5] = q.y; v[6] = q.z; v[7] = q.w;
-        if (a.Y) {
-          const uint4 m = *reinterpret_cast<const uint4*>(a.Y + o);
-          const uint32_t mm[4] = {m.x, m.y, m.z, m.w};
+    // output gradient (of the pre-activation), [pixel][co]; the loads of
+    // U tasks are issued before any is stored
+    {
+      constexpr int U = 4;
+      constexpr int NTASK = kWgTH * kWgTW * NG;
+      for (int t0 = threadIdx.x; t0 < NTASK; t0 += U * 256) {
+        float4 p[U], q[U];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (!relu_on(mm[i] & 0xFFFFu)) v[2 * i] = 0.f;
-            if (!relu_on(mm[i] >> 16)) v[2 * i + 1] = 0.f;
+        for (int u = 0; u < U; ++u) {
+          const int task = t0 + u * 256;
+          p[u] = q[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          const int g = task % NG, pix = task / NG;
+          const int row = pix / kWgTW, px = pix - row * kWgTW;
+          const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
+          if (task < NTASK && y < H && x < W && co < a.Cout) {
+            const long long o = (((long long)b * H + y) * W + x) * a.Cout + co;
+            p[u] = *reinterpret_cast<const float4*>(a.gY + o);
+            q[u] = *reinterpret_cast<const float4*>(a.gY + o + 4);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int task = t0 + u * 256;
+          if (task < NTASK) {
+            const float v[8] = {p[u].x, p[u].y, p[u].z, p[u].w, q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bsum[i] += v[i];
+            *reinterpret_cast<uint4*>(sZ + (task / NG) * ZP + (task % NG) * 8) = pack8(v);
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) bsum[i] += v[i];
-      *reinterpret_cast<uint4*>(sZ + pix * ZP + g * 8) = pack8(v);
     }
     // input tile with a one-pixel halo, [pixel][ci]
     stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, XR, XW, cc * a.CCw, ngx, sX, XP);
@@ -681,7 +680,8 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
   a.y_w[p] = 1.0f / (1.0f + __expf(-z));
 }
 
-// Loss terms, gradient of the head input (FP32 NHWC) and per-block partial
+// Loss terms, gradient of the head input's pre-activation (FP32 NHWC: the
+// head input is a ReLU output) and per-block partial
 // sums of the head-parameter gradient and of the two squared errors.
 // Dynamic LDS: gy [256][P+1], h [256][C1+1], gz [256], Wm [P][C1], Ww [C1];
 // the partials of the Wm gradient reuse it from the start once those are read.
@@ -740,6 +740,10 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
       }
+      // the head input is a ReLU output: store the gradient of its pre-activation
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (!(shh[tid * (C1 + 1) + c + i] > 0.f)) s[i] = 0.f;
       *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
     }
   }
