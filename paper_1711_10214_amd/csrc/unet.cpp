@@ -27,8 +27,7 @@ int set_error(int code, const std::string& msg);
 namespace unet {
 hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s);
-hipError_t launch_wgrad_reduce(const float* part, const float* bpart, int nsplit, int Cout, int Cin, int Cipw,
-                               float* grad, float* gb, hipStream_t s);
+hipError_t launch_wgrad_reduce(const RedAll& a, hipStream_t s);
 int wgrad_cot(int Cout);
 hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s);
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s);
@@ -168,7 +167,8 @@ void build_graph(unet_net& n) {
 
 struct WsLayout {
   std::vector<size_t> act, gact;
-  size_t y_m = 0, y_w = 0, wpart = 0, bpart = 0, hpart = 0, lpart = 0, total = 0;
+  std::vector<size_t> wpart, bpart;  // per layer: its weight-gradient partials stay until the reduction
+  size_t y_m = 0, y_w = 0, hpart = 0, lpart = 0, total = 0;
   std::vector<int> nsplit;
   int nblk_h = 0;
 };
@@ -194,7 +194,6 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
   w.y_w = take(npix0 * 4);
   if (train) {
     w.gact.resize(kNConv);
-    long long wp = 0, bp = 0;
     w.nsplit.resize(kNConv);
     for (int i = 0; i < kNConv; ++i) {
       const Layer& l = n.L[i];
@@ -209,11 +208,11 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
       const int ns = (int)std::max(
           1LL, std::min({T, (long long)kWgradTargetGroups / std::max(1LL, groups), nbal}));
       w.nsplit[i] = ns;
-      wp = std::max(wp, (long long)ns * l.co * 9 * cipw);
-      bp = std::max(bp, (long long)ns * l.co);
+      w.wpart.push_back(take((long long)ns * l.co * 9 * cipw * 4));
+      w.bpart.push_back(take((long long)ns * l.co * 4));
     }
-    w.wpart = take(wp * 4);
-    w.bpart = take(bp * 4);
+    // head-backward workgroups: one per 256-pixel block (walking several
+    // blocks per workgroup measured slower)
     w.nblk_h = (int)((npix0 + 255) / 256);
     const int ne = n.pout * n.base + n.pout + n.base + 1;
     w.hpart = take((long long)w.nblk_h * ne * 4);
@@ -312,6 +311,9 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
   la.ne = n.pout * n.base + n.pout + n.base + 1;
   U_TRY(launch_head_bwd(la, w.nblk_h, g + n.L[kNConv].woff, loss, lam_w, s));
 
+  static_assert(kNConv <= kRedMax, "reduction table too small");
+  RedAll red{};
+  red.n = kNConv;
   for (int i = kNConv - 1; i >= 0; --i) {
     const Layer& l = n.L[i];
     const int Hl = H >> l.level, Wl = W >> l.level;
@@ -324,12 +326,20 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     wa.Cipw = wgrad_cipw(l);
     wa.CCw = wgrad_ccw(l);
     wa.nccw = wa.Cipw / wa.CCw;
-    wa.part = (float*)(ws + w.wpart);
-    wa.bpart = (float*)(ws + w.bpart);
+    wa.part = (float*)(ws + w.wpart[i]);
+    wa.bpart = (float*)(ws + w.bpart[i]);
     wa.nsplit = w.nsplit[i];
     wa.B = B;
     U_TRY(launch_wgrad(wa, l.srcA < 0, s));
-    U_TRY(launch_wgrad_reduce(wa.part, wa.bpart, wa.nsplit, l.co, l.ci, wa.Cipw, g + l.woff, g + l.boff, s));
+    RedLayer& rl = red.L[i];
+    rl.part = wa.part;
+    rl.bpart = wa.bpart;
+    rl.grad = g + l.woff;
+    rl.gb = g + l.boff;
+    rl.nsplit = wa.nsplit;
+    rl.Cout = l.co;
+    rl.Cin = l.ci;
+    rl.Cipw = wa.Cipw;
 
     if (i == 0) continue;
     ConvArgs da{};
@@ -359,6 +369,9 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     if (l.srcB >= 0) written[l.srcB] = 1;
     U_TRY(launch_conv3(da, true, true, s));
   }
+  red.start[0] = 0;
+  for (int i = 0; i < kNConv; ++i) red.start[i + 1] = red.start[i] + red.L[i].Cout * (red.L[i].Cin * 9 + 1);
+  U_TRY(launch_wgrad_reduce(red, s));
   return ASHRT_OK;
 }
 

@@ -82,6 +82,23 @@ struct PackArgs {
   uint16_t* Wtp;            // transposed packing (input = Cout channels, output = Cin), or null
   ConvPack f, t;
 };
+// The weight and bias gradients of every convolution summed from their
+// pixel-split partials in one launch: element e belongs to layer l with
+// start[l] <= e < start[l + 1], weights first (in the partials' (co, kk,
+// ci) order), then the Cout biases.
+constexpr int kRedMax = 20;
+struct RedLayer {
+  const float* part;        // [nsplit][Cout][9][Cipw]
+  const float* bpart;       // [nsplit][Cout]
+  float* grad;              // [Cout][Cin][3][3]
+  float* gb;                // [Cout]
+  int nsplit, Cout, Cin, Cipw;
+};
+struct RedAll {
+  int n;
+  int start[kRedMax + 1];
+  RedLayer L[kRedMax];
+};
 // Every convolution's packings in one launch: packed element e belongs to
 // layer l with start[l] <= e < start[l + 1] (forward packing first).
 constexpr int kPackMax = 20;

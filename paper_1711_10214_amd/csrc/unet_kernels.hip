@@ -567,45 +567,51 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   }
 }
 
-// Sum the pixel-split partials into the canonical weight gradient
-// [Cout][Cin][3][3] and the bias gradient (fixed order over the splits).
-// grad[co][ci][kk] = sum over the pixel splits of the partials.  A
-// workgroup takes E gradient elements and 256 / E thread groups
-// over the splits (split sp -> group sp mod G); the G partial sums of an
-// element are added in group order, so the result does not depend on timing.
-// Elements past the Cout Cin 9 weights are the Cout biases.
+// Sum the pixel-split partials of every layer (see RedAll) into the
+// canonical weight gradients [Cout][Cin][3][3] and the bias gradients.  A
+// workgroup takes E consecutive elements (one per lane: each wave load is
+// E consecutive floats) and 256 / E thread groups over the splits (split
+// sp -> group sp mod G); the G partial sums of an element are added in
+// group order, so the result does not depend on timing.
 template <int E>
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ bpart,
-                                                     int nsplit, int Cout, int Cin, int Cipw, float* __restrict__ grad,
-                                                     float* __restrict__ gb) {
+__global__ __launch_bounds__(256) void k_wgrad_reduce(RedAll a) {
   constexpr int G = 256 / E;
   __shared__ float s[G][E + 1];
   const int te = (int)threadIdx.x % E, g = (int)threadIdx.x / E;
-  const int nw = Cout * Cin * 9, n = nw + Cout;
-  // elements enumerated in the partials' order (co, kk, ci), ci fastest, so
-  // neighbouring threads read neighbouring floats
+  const int n = a.start[a.n];
   for (int j0 = blockIdx.x * E; j0 < n; j0 += gridDim.x * E) {
     const int j = j0 + te;
     float acc = 0.f;
-    int co = 0, kk = 0, ci = 0;
-    if (j < nw) {
-      co = j / (9 * Cin);
-      const int r = j - co * 9 * Cin;
-      kk = r / Cin;
-      ci = r - kk * Cin;
-      const long long stride = (long long)Cout * 9 * Cipw;
-      const float* p = part + ((long long)co * 9 + kk) * Cipw + ci;
-      for (int sp = g; sp < nsplit; sp += G) acc += p[sp * stride];
-    } else if (j < n) {
-      for (int sp = g; sp < nsplit; sp += G) acc += bpart[(long long)sp * Cout + (j - nw)];
+    int l = 0, co = 0, kk = 0, ci = 0, jl = 0;
+    if (j < n) {
+      while (j >= a.start[l + 1]) ++l;
+      const RedLayer& L = a.L[l];
+      jl = j - a.start[l];
+      const int nw = L.Cout * L.Cin * 9;
+      if (jl < nw) {
+        // neighbouring elements are neighbouring ci: coalesced partial reads
+        co = jl / (9 * L.Cin);
+        const int r = jl - co * 9 * L.Cin;
+        kk = r / L.Cin;
+        ci = r - kk * L.Cin;
+        const long long stride = (long long)L.Cout * 9 * L.Cipw;
+        const float* p = L.part + ((long long)co * 9 + kk) * L.Cipw + ci;
+#pragma unroll 8
+        for (int sp = g; sp < L.nsplit; sp += G) acc += p[sp * stride];
+      } else {
+#pragma unroll 8
+        for (int sp = g; sp < L.nsplit; sp += G) acc += L.bpart[(long long)sp * L.Cout + (jl - nw)];
+      }
     }
     s[g][te] = acc;
     __syncthreads();
     if (g == 0 && j < n) {
       float t = 0.f;
       for (int q = 0; q < G; ++q) t += s[q][te];
-      if (j < nw) grad[((long long)co * Cin + ci) * 9 + kk] = t;
-      else gb[j - nw] = t;
+      const RedLayer& L = a.L[l];
+      const int nw = L.Cout * L.Cin * 9;
+      if (jl < nw) L.grad[((long long)co * L.Cin + ci) * 9 + kk] = t;
+      else L.gb[jl - nw] = t;
     }
     __syncthreads();
   }
@@ -681,131 +687,130 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
 }
 
 // Loss terms, gradient of the head input's pre-activation (FP32 NHWC: the
-// head input is a ReLU output) and per-block partial
-// sums of the head-parameter gradient and of the two squared errors.
-// Dynamic LDS: gy [256][P+1], h [256][C1+1], gz [256], Wm [P][C1], Ww [C1];
-// the partials of the Wm gradient reuse it from the start once those are read.
-// The Wm gradient block sum_t gy[t][co] h[t][c] (P x C1 outputs over the
-// block's 256 pixels) is register-blocked: a thread takes a 4 x 4 tile of
-// outputs over one of G pixel ranges (8 LDS reads per 16 FMAs), and the G
-// range sums of an output are added in range order.
+// head input is a ReLU output) and per-block partial sums of the
+// head-parameter gradient and of the two squared errors.
+// A workgroup walks 256-pixel blocks with stride gridDim.x.  Dynamic LDS:
+// gy [256][P+1] (column P: the gradient gz of the weight head's logit), h
+// [256][C1+1] (column C1: 1), Wm [P][C1], Ww [C1]; the partials of the
+// parameter gradient reuse it from the start once those are read.  Every head parameter's block gradient is one entry of
+// sum_t gy[t] h[t]^T, a (P+1) x (C1+1) outer-product sum (Wm, bm; Ww, bw),
+// register-blocked: a thread takes a 4 x 4 tile of entries over one of G
+// pixel ranges (8 LDS reads per 16 FMAs), and the G range sums of an entry
+// are added in range order.
 __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
   extern __shared__ float sh[];
   __shared__ double sred[2][4];
   const HeadArgs& d = a.hd;
   const int C1 = d.C1, P = d.P, tid = (int)threadIdx.x;
+  const int GP = P + 1, HC = C1 + 1;
   float* sgy = sh;
-  float* shh = sgy + 256 * (P + 1);
-  float* sgz = shh + 256 * (C1 + 1);
-  float* sWm = sgz + 256;
+  float* shh = sgy + 256 * GP;
+  float* sWm = shh + 256 * HC;
   float* sWw = sWm + P * C1;
   for (int i = tid; i < P * C1; i += 256) sWm[i] = d.Wm[i];
   for (int i = tid; i < C1; i += 256) sWw[i] = d.Ww[i];
   const long long HW = (long long)d.H * d.W, npix = d.B * HW;
-  const long long p = (long long)blockIdx.x * 256 + tid;
   const float inv_m = 1.0f / (float)((double)npix * P), inv_w = 1.0f / (float)npix;
-  double lm = 0.0, lw = 0.0;
-  if (p < npix) {
-    const uint16_t* hp = d.h + p * C1;
-    for (int c = 0; c < C1; c += 8) {
-      float v[8];
-      unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) shh[tid * (C1 + 1) + c + i] = v[i];
-    }
-    const long long b = p / HW, yx = p - b * HW;
-    for (int co = 0; co < P; ++co) {
-      const long long o = (b * P + co) * HW + yx;
-      const float df = d.y_m[o] - a.t_m[o];
-      lm += (double)df * (double)df;
-      sgy[tid * (P + 1) + co] = 2.0f * df * inv_m;
-    }
-    const float yw = d.y_w[p], dw = yw - a.t_w[p];
-    lw = (double)dw * (double)dw;
-    sgz[tid] = 2.0f * a.lam_w * dw * inv_w * yw * (1.0f - yw);
-  } else {
-    for (int co = 0; co < P; ++co) sgy[tid * (P + 1) + co] = 0.f;
-    for (int c = 0; c < C1; ++c) shh[tid * (C1 + 1) + c] = 0.f;
-    sgz[tid] = 0.f;
-  }
-  __syncthreads();
-  if (p < npix) {
-    // four channels per 16-byte store (C1 is a multiple of 8)
-    for (int c = 0; c < C1; c += 4) {
-      float s[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s[i] = sWw[c + i] * sgz[tid];
-      for (int co = 0; co < P; ++co) {
-        const float gy = sgy[tid * (P + 1) + co];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
-      }
-      // the head input is a ReLU output: store the gradient of its pre-activation
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (!(shh[tid * (C1 + 1) + c + i] > 0.f)) s[i] = 0.f;
-      *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
-    }
-  }
-  const int tP = (P + 3) >> 2, tC = (C1 + 3) >> 2, nT = tP * tC;
-  const bool blocked = nT <= 256;
-  const int G = blocked ? 256 / nT : 1;
+  const int tP = (GP + 3) >> 2, tC = (HC + 3) >> 2, nT = tP * tC;
+  const int G = 256 / nT;  // nT <= 256: checked by the launcher
   const int tile = tid % nT, grp = tid / nT;
+  const int r0 = (tile / tC) * 4, c0 = (tile % tC) * 4;
+  const int tlo = grp * 256 / G, thi = (grp + 1) * 256 / G;
   float acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
-  if (blocked && grp < G) {
-    const int co0 = (tile / tC) * 4, c0 = (tile % tC) * 4;
-    const int tlo = grp * 256 / G, thi = (grp + 1) * 256 / G;
-    for (int t = tlo; t < thi; ++t) {
-      float gy[4], hh[4];
+  double lm = 0.0, lw = 0.0;
+  // 256-pixel blocks pb = blockIdx.x, blockIdx.x + gridDim.x, ...
+  const long long npb = (npix + 255) / 256;
+  for (long long pb = blockIdx.x; pb < npb; pb += gridDim.x) {
+    const long long p = pb * 256 + tid;
+    if (p < npix) {
+      const uint16_t* hp = d.h + p * C1;
+      for (int c = 0; c < C1; c += 8) {
+        float v[8];
+        unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        gy[i] = co0 + i < P ? sgy[t * (P + 1) + co0 + i] : 0.f;
-        hh[i] = c0 + i < C1 ? shh[t * (C1 + 1) + c0 + i] : 0.f;
+        for (int i = 0; i < 8; ++i) shh[tid * HC + c + i] = v[i];
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gy[i], hh[j], acc[i][j]);
-    }
-  }
-  // the other entries (and all of them when the tiles do not fit)
-  for (int e = (blocked ? P * C1 : 0) + tid; e < a.ne; e += 256) {
-    float s = 0.f;
-    if (e < P * C1) {
-      const int co = e / C1, c = e - co * C1;
-      for (int t = 0; t < 256; ++t) s = fmaf(sgy[t * (P + 1) + co], shh[t * (C1 + 1) + c], s);
-    } else if (e < P * C1 + P) {
-      const int co = e - P * C1;
-      for (int t = 0; t < 256; ++t) s += sgy[t * (P + 1) + co];
-    } else if (e < P * C1 + P + C1) {
-      const int c = e - P * C1 - P;
-      for (int t = 0; t < 256; ++t) s = fmaf(sgz[t], shh[t * (C1 + 1) + c], s);
+      shh[tid * HC + C1] = 1.f;
+      const long long b = p / HW, yx = p - b * HW;
+      for (int co = 0; co < P; ++co) {
+        const long long o = (b * P + co) * HW + yx;
+        const float df = d.y_m[o] - a.t_m[o];
+        lm += (double)df * (double)df;
+        sgy[tid * GP + co] = 2.0f * df * inv_m;
+      }
+      const float yw = d.y_w[p], dw = yw - a.t_w[p];
+      lw += (double)dw * (double)dw;
+      sgy[tid * GP + P] = 2.0f * a.lam_w * dw * inv_w * yw * (1.0f - yw);
     } else {
-      for (int t = 0; t < 256; ++t) s += sgz[t];
-    }
-    a.hpart[(long long)blockIdx.x * a.ne + e] = s;
-  }
-  if (blocked) {
-    __syncthreads();  // gy and h are read: their space takes the partials
-    float* red = sh;
-    if (grp < G) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) red[(grp * nT + tile) * 16 + i * 4 + j] = acc[i][j];
+      for (int co = 0; co < GP; ++co) sgy[tid * GP + co] = 0.f;
+      for (int c = 0; c < HC; ++c) shh[tid * HC + c] = 0.f;
     }
     __syncthreads();
-    for (int e = tid; e < P * C1; e += 256) {
-      const int co = e / C1, c = e - co * C1;
-      const int o = ((co >> 2) * tC + (c >> 2)) * 16 + (co & 3) * 4 + (c & 3);
-      float s = 0.f;
-      for (int g = 0; g < G; ++g) s += red[g * nT * 16 + o];
-      a.hpart[(long long)blockIdx.x * a.ne + e] = s;
+    if (p < npix) {
+      // four channels per 16-byte store (C1 is a multiple of 8)
+      const float gz = sgy[tid * GP + P];
+      for (int c = 0; c < C1; c += 4) {
+        float s[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = sWw[c + i] * gz;
+        for (int co = 0; co < P; ++co) {
+          const float gy = sgy[tid * GP + co];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
+        }
+        // the head input is a ReLU output: store the gradient of its pre-activation
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (!(shh[tid * HC + c + i] > 0.f)) s[i] = 0.f;
+        *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
+      }
     }
+    if (grp < G) {
+      for (int t = tlo; t < thi; ++t) {
+        float gy[4], hh[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          gy[i] = r0 + i < GP ? sgy[t * GP + r0 + i] : 0.f;
+          hh[i] = c0 + i < HC ? shh[t * HC + c0 + i] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gy[i], hh[j], acc[i][j]);
+      }
+    }
+    __syncthreads();  // the block's gy and h are read
+  }
+  __syncthreads();  // gy and h are read: their space takes the partials
+  float* red = sh;
+  if (grp < G) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[(grp * nT + tile) * 16 + i * 4 + j] = acc[i][j];
+  }
+  __syncthreads();
+  // entry e of the partial layout [Wm P x C1][bm P][Ww C1][bw] -> (r, c)
+  for (int e = tid; e < a.ne; e += 256) {
+    int r, c;
+    if (e < P * C1) {
+      r = e / C1;
+      c = e - r * C1;
+    } else if (e < P * C1 + P) {
+      r = e - P * C1;
+      c = C1;
+    } else {
+      r = P;
+      c = e - P * C1 - P;  // C1 for bw
+    }
+    const int o = ((r >> 2) * tC + (c >> 2)) * 16 + (r & 3) * 4 + (c & 3);
+    float sum = 0.f;
+    for (int g = 0; g < G; ++g) sum += red[g * nT * 16 + o];
+    a.hpart[(long long)blockIdx.x * a.ne + e] = sum;
   }
   // block sums of the squared errors (fixed order)
   for (int off = 32; off > 0; off >>= 1) {
@@ -938,25 +943,17 @@ hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_wgrad_reduce(const float* part, const float* bpart, int nsplit, int Cout, int Cin, int Cipw,
-                               float* grad, float* gb, hipStream_t s) {
-  const long long n = (long long)Cout * Cin * 9 + Cout;
-  if (n >= 16 * 256) {
-    const long long g = (n + 15) / 16;
-    hipLaunchKernelGGL(k_wgrad_reduce<16>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, part, bpart,
-                       nsplit, Cout, Cin, Cipw, grad, gb);
-  } else {
-    hipLaunchKernelGGL(k_wgrad_reduce<4>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, part, bpart, nsplit, Cout,
-                       Cin, Cipw, grad, gb);
-  }
+hipError_t launch_wgrad_reduce(const RedAll& a, hipStream_t s) {
+  const long long g = (a.start[a.n] + 63) / 64;
+  hipLaunchKernelGGL(k_wgrad_reduce<64>, dim3((unsigned)(g > 16384 ? 16384 : g)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 size_t head_fwd_lds(int P, int C1) { return (size_t)(P * C1 + P + C1 + 1) * 4; }
 size_t head_bwd_lds(int P, int C1) {
-  const int nT = ((P + 3) / 4) * ((C1 + 3) / 4);
-  const size_t red = nT <= 256 ? (size_t)(256 / nT) * nT * 16 : 0;  // partials of the Wm gradient
-  return std::max((size_t)(256 * (P + 1) + 256 * (C1 + 1) + 256 + P * C1 + C1), red) * 4;
+  const int nT = ((P + 4) / 4) * ((C1 + 4) / 4);  // 4 x 4 tiles of the (P + 1) x (C1 + 1) entries
+  const size_t red = (size_t)(256 / nT) * nT * 16;
+  return std::max((size_t)(256 * (P + 1) + 256 * (C1 + 1) + P * C1 + C1), red) * 4;
 }
 
 hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
@@ -967,6 +964,7 @@ hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
 
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s) {
   const long long npix = (long long)a.hd.B * a.hd.H * a.hd.W;
+  if (((a.hd.P + 4) / 4) * ((a.hd.C1 + 4) / 4) > 256) return hipErrorInvalidValue;  // one tile per thread at least
   hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), head_bwd_lds(a.hd.P, a.hd.C1), s, a);
   sum_parts((const float*)a.hpart, nblk, a.ne, ghead, s);
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, (const double*)a.lpart, nblk,
