@@ -26,6 +26,7 @@ int set_error(int code, const std::string& msg);
 
 namespace unet {
 hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s);
+int conv_ksplit(const ConvPack& pk, int B, int H, int W, bool up);
 hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s);
 hipError_t launch_wgrad_reduce(const RedAll& a, hipStream_t s);
 int wgrad_cot(int Cout);
@@ -168,7 +169,8 @@ void build_graph(unet_net& n) {
 struct WsLayout {
   std::vector<size_t> act, gact;
   std::vector<size_t> wpart, bpart;  // per layer: its weight-gradient partials stay until the reduction
-  size_t y_m = 0, y_w = 0, hpart = 0, lpart = 0, total = 0;
+  size_t y_m = 0, y_w = 0, hpart = 0, lpart = 0, kpart = 0, total = 0;
+  std::vector<int> ks_f, ks_d;  // channel-chunk splits of the forward and input-gradient convolutions
   std::vector<int> nsplit;
   int nblk_h = 0;
 };
@@ -192,6 +194,19 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
   }
   w.y_m = take(npix0 * n.pout * 4);
   w.y_w = take(npix0 * 4);
+  // FP32 partials of the convolutions split over their channel chunks
+  long long kp = 0;
+  w.ks_f.resize(kNConv);
+  w.ks_d.resize(kNConv);
+  for (int i = 0; i < kNConv; ++i) {
+    const Layer& l = n.L[i];
+    const int Hl = H >> l.level, Wl = W >> l.level;
+    w.ks_f[i] = conv_ksplit(l.f, B, Hl, Wl, false);
+    kp = std::max(kp, (long long)w.ks_f[i] * B * Hl * Wl * l.f.Coutp);
+    w.ks_d[i] = train && i > 0 ? conv_ksplit(l.t, B, Hl, Wl, l.modeA == 1) : 1;
+    if (w.ks_d[i] > 1) kp = std::max(kp, (long long)w.ks_d[i] * B * Hl * Wl * l.t.Coutp);
+  }
+  w.kpart = take(kp * 4);
   if (train) {
     w.gact.resize(kNConv);
     w.nsplit.resize(kNConv);
@@ -266,6 +281,8 @@ int run_forward(const unet_net& n, const WsLayout& w, unsigned char* ws, const f
     a.relu = 1;
     a.out = ws + w.act[i];
     a.B = B;
+    a.ksplit = w.ks_f[i];
+    a.kpart = (float*)(ws + w.kpart);
     U_TRY(launch_conv3(a, l.srcA < 0, false, s));
   }
   HeadArgs h{};
@@ -367,6 +384,8 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     da.rt.accB = l.srcB >= 0 ? written[l.srcB] : 0;
     written[l.srcA] = 1;
     if (l.srcB >= 0) written[l.srcB] = 1;
+    da.ksplit = w.ks_d[i];
+    da.kpart = (float*)(ws + w.kpart);
     U_TRY(launch_conv3(da, true, true, s));
   }
   red.start[0] = 0;

@@ -64,6 +64,12 @@ struct ConvArgs {
   void* out;                // BF16 or FP32 NHWC [B][H][W][Cout]
   int B;
   ConvRoute rt;             // FP32 outputs only
+  // split over the channel chunks: with ksplit > 1, grid.z = ksplit B and
+  // split ks sums chunks [ks ncc / ksplit, (ks + 1) ncc / ksplit) into
+  // kpart [ksplit][B][H][W][Coutp] (FP32); k_conv_finish adds the splits in
+  // order and applies the epilogue (bias, ReLU and store, or the route)
+  int ksplit;
+  float* kpart;
 };
 
 struct WgradArgs {

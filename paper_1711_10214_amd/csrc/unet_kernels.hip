@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
   const int tiles_x = (W + TW - 1) / TW;
   const int ty0 = ((int)blockIdx.x / tiles_x) * kConvTH;
   const int tx0 = ((int)blockIdx.x % tiles_x) * TW;
-  const int co0 = (int)blockIdx.y * 16 * MT, b = (int)blockIdx.z;
+  const int co0 = (int)blockIdx.y * 16 * MT, b = (int)blockIdx.z % a.B, ks = (int)blockIdx.z / a.B;
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int sub = lane >> 4, n16 = lane & 15;
   const ConvPack& P = a.pk;
@@ -344,11 +344,15 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
     wrow[mi] = a.Wp + ((long long)min(co0 + mi * 16 + n16, P.Coutp - 1) * P.ncc * P.KKp + tap_l) * CC + coff;
   // the A fragments of the next k-step are loaded while this one multiplies
   uint4 wq[MT];
+  // this split's channel chunks (all of them without a split)
+  const int cc_lo = ks * P.ncc / a.ksplit, cc_hi = (ks + 1) * P.ncc / a.ksplit;
+  const long long s0 = (long long)cc_lo * nkc * P.TPK * CC;
 #pragma unroll
-  for (int mi = 0; mi < MT; ++mi) wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi]) : make_uint4(0u, 0u, 0u, 0u);
-  const int nks = P.ncc * nkc;
+  for (int mi = 0; mi < MT; ++mi)
+    wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi] + s0) : make_uint4(0u, 0u, 0u, 0u);
+  const int nks = cc_hi * nkc;
 
-  for (int cc = 0; cc < P.ncc; ++cc) {
+  for (int cc = cc_lo; cc < cc_hi; ++cc) {
     stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, kConvTH + 2, TW2, cc * CC, ng, sX, PS);
     __syncthreads();
     for (int kc = 0; kc < nkc; ++kc) {
@@ -383,13 +387,31 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
     __syncthreads();
   }
 
+  const int y = ty0 + wave;
+  if (!UP && a.ksplit > 1) {  // the upsampled route is launched unsplit
+    // raw partial sums of this split; the finishing kernel applies the epilogue
+    if (y >= H) return;
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+      if (mi >= MI) continue;
+      const int co = co0 + mi * 16 + sub * 4;
+#pragma unroll
+      for (int ni = 0; ni < NTL; ++ni) {
+        const int x = tx0 + ni * 16 + n16;
+        if (x >= W) continue;
+        const long long off = ((((long long)ks * a.B + b) * H + y) * W + x) * P.Coutp + co;
+        *reinterpret_cast<float4*>(a.kpart + off) =
+            make_float4(acc[mi][ni][0], acc[mi][ni][1], acc[mi][ni][2], acc[mi][ni][3]);
+      }
+    }
+    return;
+  }
   if constexpr (OUTF32) {
     if (a.rt.gA) {
       route_store<MT, NTL, UP>(a, acc, b, ty0, tx0, co0, MI, reinterpret_cast<float*>(sX));
       return;
     }
   }
-  const int y = ty0 + wave;
   if (y >= H) return;
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi) {
@@ -413,6 +435,91 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
         *reinterpret_cast<uint2*>(static_cast<uint16_t*>(a.out) + off) =
             make_uint2(f2bf(o[0]) | (f2bf(o[1]) << 16), f2bf(o[2]) | (f2bf(o[3]) << 16));
       }
+    }
+  }
+}
+
+// Finish a convolution split over its channel chunks: S(pixel, co) = the
+// ksplit partials added in split order, then the epilogue of k_conv3 for
+// that value: bias, ReLU and a BF16 (or FP32) store, or the route to A and
+// the skip (see ConvRoute).  Four channels a thread.  An upsampled A takes
+// its 2 x 2 block sums as (S00 + S01) + (S10 + S11) in a second index range
+// over A's pixels.
+__device__ __forceinline__ float4 ksum4(const ConvArgs& a, long long pix, int co) {
+  const long long stride = (long long)a.B * a.in.H * a.in.W * a.pk.Coutp;
+  float4 t = *reinterpret_cast<const float4*>(a.kpart + pix * a.pk.Coutp + co);
+  for (int k = 1; k < a.ksplit; ++k) {
+    const float4 q = *reinterpret_cast<const float4*>(a.kpart + k * stride + pix * a.pk.Coutp + co);
+    t.x += q.x;
+    t.y += q.y;
+    t.z += q.z;
+    t.w += q.w;
+  }
+  return t;
+}
+
+template <bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv_finish(ConvArgs a) {
+  const int H = a.in.H, W = a.in.W;
+  const long long npix = (long long)a.B * H * W;
+  const ConvRoute& R = a.rt;
+  const bool routed = OUTF32 && R.gA;
+  const bool up = routed && R.modeA == 1;
+  // range 1: every output pixel's channel groups (without the A channels of
+  // an upsampled route); range 2: the A pixels of an upsampled route
+  const int c_lo = up ? R.Ca : 0, ng1 = (a.pk.Cout - c_lo) >> 2;
+  const long long n1 = npix * ng1;
+  const long long n2 = up ? npix / 4 * (R.Ca >> 2) : 0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n1 + n2; i += (long long)gridDim.x * 256) {
+    if (i < n1) {
+      const long long pix = i / ng1;
+      const int co = c_lo + 4 * (int)(i - pix * ng1);
+      const float4 t = ksum4(a, pix, co);
+      if (!routed) {
+        float o[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (a.bias) o[k] += a.bias[co + k];
+          if (a.relu) o[k] = fmaxf(o[k], 0.f);
+        }
+        const long long off = pix * a.pk.Cout + co;
+        if constexpr (OUTF32) {
+          *reinterpret_cast<float4*>(static_cast<float*>(a.out) + off) = make_float4(o[0], o[1], o[2], o[3]);
+        } else {
+          *reinterpret_cast<uint2*>(static_cast<uint16_t*>(a.out) + off) =
+              make_uint2(f2bf(o[0]) | (f2bf(o[1]) << 16), f2bf(o[2]) | (f2bf(o[3]) << 16));
+        }
+      } else if (co >= R.Ca) {
+        const long long ob = pix * R.Cb + (co - R.Ca);
+        put4(R.gB + ob, R.mB ? R.mB + ob : nullptr, t.x, t.y, t.z, t.w, R.accB != 0);
+      } else if (R.modeA == 0) {
+        const long long oa = pix * R.Ca + co;
+        put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, t.x, t.y, t.z, t.w, R.accA != 0);
+      } else {
+        const long long b = pix / ((long long)H * W);
+        const int rem = (int)(pix - b * H * W), y = rem / W, x = rem - y * W;
+        const int H2 = 2 * H, W2 = 2 * W;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long long oa = ((b * H2 + 2 * y + (q >> 1)) * W2 + 2 * x + (q & 1)) * R.Ca + co;
+          put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, 0.25f * t.x, 0.25f * t.y, 0.25f * t.z, 0.25f * t.w,
+               R.accA != 0);
+        }
+      }
+    } else {
+      const long long j = i - n1;
+      const int ngA = R.Ca >> 2;
+      const long long ph = j / ngA;  // A pixel (b, yh, xh)
+      const int co = 4 * (int)(j - ph * ngA);
+      const int Hh = H >> 1, Wh = W >> 1;
+      const long long b = ph / ((long long)Hh * Wh);
+      const int rem = (int)(ph - b * Hh * Wh), yh = rem / Wh, xh = rem - yh * Wh;
+      const long long p00 = (b * H + 2 * yh) * W + 2 * xh;
+      const float4 s00 = ksum4(a, p00, co), s01 = ksum4(a, p00 + 1, co);
+      const float4 s10 = ksum4(a, p00 + W, co), s11 = ksum4(a, p00 + W + 1, co);
+      put4(R.gA + ph * R.Ca + co, R.mA ? R.mA + ph * R.Ca + co : nullptr, (s00.x + s01.x) + (s10.x + s11.x),
+           (s00.y + s01.y) + (s10.y + s11.y), (s00.z + s01.z) + (s10.z + s11.z), (s00.w + s01.w) + (s10.w + s11.w),
+           R.accA != 0);
     }
   }
 }
@@ -899,13 +1006,30 @@ static inline unsigned grid_for(long long n, int per = 256, int cap = 8192) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// Workgroups below which a convolution launch splits its channel chunks
+// (such launches leave CUs idle while each workgroup walks every chunk).
+constexpr long long kConvSplitGroups = 512;
+
+static bool conv_wide(const ConvPack& pk, bool up) { return pk.Coutp <= 16 && !up; }
+
+// Channel-chunk split of a launch (1: none); the host sizes the partial
+// buffer with this same function.
+int conv_ksplit(const ConvPack& pk, int B, int H, int W, bool up) {
+  const int NTL = conv_wide(pk, up) ? 8 : 2, MT = conv_wide(pk, up) ? 1 : 4;
+  const long long groups = (long long)((H + kConvTH - 1) / kConvTH) * ((W + 16 * NTL - 1) / (16 * NTL)) *
+                           ((pk.Coutp + 16 * MT - 1) / (16 * MT)) * B;
+  if (groups >= kConvSplitGroups) return 1;
+  return (int)std::min<long long>(pk.ncc, (kConvSplitGroups + groups - 1) / groups);
+}
+
 template <int MT, int NTL>
 static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
   const int tiles = ((a.in.H + kConvTH - 1) / kConvTH) * ((a.in.W + 16 * NTL - 1) / (16 * NTL));
-  const dim3 grid(tiles, (a.pk.Coutp + 16 * MT - 1) / (16 * MT), a.B);
+  const int ks = a.ksplit;
+  const dim3 grid(tiles, (a.pk.Coutp + 16 * MT - 1) / (16 * MT), a.B * ks);
   size_t lds = (size_t)(kConvTH + 2) * (16 * NTL + 2) * (a.pk.CC + 8) * sizeof(uint16_t);
   if constexpr (MT == 4) {
-    if (outf32 && a.rt.gA && a.rt.modeA == 1) {
+    if (ks == 1 && outf32 && a.rt.gA && a.rt.modeA == 1) {
       // an upsampled route exchanges two waves' MT x NTL x 4 sums per lane
       lds = std::max(lds, (size_t)2 * MT * NTL * 4 * 64 * sizeof(float));
       hipLaunchKernelGGL((k_conv3<true, true, MT, NTL, true>), grid, dim3(256), lds, s, a);
@@ -917,14 +1041,23 @@ static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t 
   else hipLaunchKernelGGL((k_conv3<false, false, MT, NTL>), grid, dim3(256), lds, s, a);
 }
 
-hipError_t launch_conv3(const ConvArgs& a, bool af32, bool outf32, hipStream_t s) {
+hipError_t launch_conv3(const ConvArgs& args, bool af32, bool outf32, hipStream_t s) {
+  ConvArgs a = args;
+  a.ksplit = std::max(1, a.ksplit);  // the kernel divides by it
   const bool up = outf32 && a.rt.gA && a.rt.modeA == 1;
   // FP32 outputs are input gradients: FP32 input, routed or not
   if (outf32 && !af32) return hipErrorInvalidValue;
+  if (a.ksplit > 1 && (!a.kpart || a.ksplit > a.pk.ncc)) return hipErrorInvalidValue;
   // one 16-channel tile of outputs: a wave takes 128 columns instead of 32
   // (the upsampled route takes 4 x 2 tiles)
-  if (a.pk.Coutp <= 16 && !up) conv3_launch<1, 8>(a, af32, outf32, s);
+  if (conv_wide(a.pk, up)) conv3_launch<1, 8>(a, af32, outf32, s);
   else conv3_launch<4, 2>(a, af32, outf32, s);
+  if (a.ksplit > 1) {
+    const long long npix = (long long)a.B * a.in.H * a.in.W;
+    const long long n = npix * (a.pk.Cout >> 2);  // an upper bound of both index ranges
+    if (outf32) hipLaunchKernelGGL(k_conv_finish<true>, dim3(grid_for(n)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_conv_finish<false>, dim3(grid_for(n)), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
