@@ -226,9 +226,7 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
       w.wpart.push_back(take((long long)ns * l.co * 9 * cipw * 4));
       w.bpart.push_back(take((long long)ns * l.co * 4));
     }
-    // head-backward workgroups: one per 256-pixel block (walking several
-    // blocks per workgroup measured slower)
-    w.nblk_h = (int)((npix0 + 255) / 256);
+    w.nblk_h = (int)((npix0 + 255) / 256);  // head-backward workgroups, one per 256 pixels
     const int ne = n.pout * n.base + n.pout + n.base + 1;
     w.hpart = take((long long)w.nblk_h * ne * 4);
     w.lpart = take((long long)w.nblk_h * 2 * 8);

@@ -796,10 +796,10 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
 // Loss terms, gradient of the head input's pre-activation (FP32 NHWC: the
 // head input is a ReLU output) and per-block partial sums of the
 // head-parameter gradient and of the two squared errors.
-// A workgroup walks 256-pixel blocks with stride gridDim.x.  Dynamic LDS:
-// gy [256][P+1] (column P: the gradient gz of the weight head's logit), h
-// [256][C1+1] (column C1: 1), Wm [P][C1], Ww [C1]; the partials of the
-// parameter gradient reuse it from the start once those are read.  Every head parameter's block gradient is one entry of
+// One 256-pixel block per workgroup.  Dynamic LDS: gy [256][P+1] (column
+// P: the gradient gz of the weight head's logit), h [256][C1+1] (column C1:
+// 1), Wm [P][C1], Ww [C1]; the partials of the parameter gradient reuse it
+// from the start once those are read.  Every head parameter's block gradient is one entry of
 // sum_t gy[t] h[t]^T, a (P+1) x (C1+1) outer-product sum (Wm, bm; Ww, bw),
 // register-blocked: a thread takes a 4 x 4 tile of entries over one of G
 // pixel ranges (8 LDS reads per 16 FMAs), and the G range sums of an entry
@@ -829,68 +829,63 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
   double lm = 0.0, lw = 0.0;
-  // 256-pixel blocks pb = blockIdx.x, blockIdx.x + gridDim.x, ...
-  const long long npb = (npix + 255) / 256;
-  for (long long pb = blockIdx.x; pb < npb; pb += gridDim.x) {
-    const long long p = pb * 256 + tid;
-    if (p < npix) {
-      const uint16_t* hp = d.h + p * C1;
-      for (int c = 0; c < C1; c += 8) {
-        float v[8];
-        unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
+  const long long p = (long long)blockIdx.x * 256 + tid;
+  if (p < npix) {
+    const uint16_t* hp = d.h + p * C1;
+    for (int c = 0; c < C1; c += 8) {
+      float v[8];
+      unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) shh[tid * HC + c + i] = v[i];
-      }
-      shh[tid * HC + C1] = 1.f;
-      const long long b = p / HW, yx = p - b * HW;
+      for (int i = 0; i < 8; ++i) shh[tid * HC + c + i] = v[i];
+    }
+    shh[tid * HC + C1] = 1.f;
+    const long long b = p / HW, yx = p - b * HW;
+    for (int co = 0; co < P; ++co) {
+      const long long o = (b * P + co) * HW + yx;
+      const float df = d.y_m[o] - a.t_m[o];
+      lm += (double)df * (double)df;
+      sgy[tid * GP + co] = 2.0f * df * inv_m;
+    }
+    const float yw = d.y_w[p], dw = yw - a.t_w[p];
+    lw = (double)dw * (double)dw;
+    sgy[tid * GP + P] = 2.0f * a.lam_w * dw * inv_w * yw * (1.0f - yw);
+  } else {
+    for (int co = 0; co < GP; ++co) sgy[tid * GP + co] = 0.f;
+    for (int c = 0; c < HC; ++c) shh[tid * HC + c] = 0.f;
+  }
+  __syncthreads();
+  if (p < npix) {
+    // four channels per 16-byte store (C1 is a multiple of 8)
+    const float gz = sgy[tid * GP + P];
+    for (int c = 0; c < C1; c += 4) {
+      float s[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s[i] = sWw[c + i] * gz;
       for (int co = 0; co < P; ++co) {
-        const long long o = (b * P + co) * HW + yx;
-        const float df = d.y_m[o] - a.t_m[o];
-        lm += (double)df * (double)df;
-        sgy[tid * GP + co] = 2.0f * df * inv_m;
+        const float gy = sgy[tid * GP + co];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
       }
-      const float yw = d.y_w[p], dw = yw - a.t_w[p];
-      lw += (double)dw * (double)dw;
-      sgy[tid * GP + P] = 2.0f * a.lam_w * dw * inv_w * yw * (1.0f - yw);
-    } else {
-      for (int co = 0; co < GP; ++co) sgy[tid * GP + co] = 0.f;
-      for (int c = 0; c < HC; ++c) shh[tid * HC + c] = 0.f;
+      // the head input is a ReLU output: store the gradient of its pre-activation
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (!(shh[tid * HC + c + i] > 0.f)) s[i] = 0.f;
+      *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
     }
-    __syncthreads();
-    if (p < npix) {
-      // four channels per 16-byte store (C1 is a multiple of 8)
-      const float gz = sgy[tid * GP + P];
-      for (int c = 0; c < C1; c += 4) {
-        float s[4];
+  }
+  if (grp < G) {
+    for (int t = tlo; t < thi; ++t) {
+      float gy[4], hh[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s[i] = sWw[c + i] * gz;
-        for (int co = 0; co < P; ++co) {
-          const float gy = sgy[tid * GP + co];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
-        }
-        // the head input is a ReLU output: store the gradient of its pre-activation
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (!(shh[tid * HC + c + i] > 0.f)) s[i] = 0.f;
-        *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
+      for (int i = 0; i < 4; ++i) {
+        gy[i] = r0 + i < GP ? sgy[t * GP + r0 + i] : 0.f;
+        hh[i] = c0 + i < HC ? shh[t * HC + c0 + i] : 0.f;
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gy[i], hh[j], acc[i][j]);
     }
-    if (grp < G) {
-      for (int t = tlo; t < thi; ++t) {
-        float gy[4], hh[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          gy[i] = r0 + i < GP ? sgy[t * GP + r0 + i] : 0.f;
-          hh[i] = c0 + i < HC ? shh[t * HC + c0 + i] : 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gy[i], hh[j], acc[i][j]);
-      }
-    }
-    __syncthreads();  // the block's gy and h are read
   }
   __syncthreads();  // gy and h are read: their space takes the partials
   float* red = sh;
