@@ -162,6 +162,43 @@ def test_forward_production_shape_matches_stored_reference(A):
     assert e_w <= _derived(ref["bf16_cost_y_w"], tw_bar)
 
 
+def test_batch_matches_single_samples(A):
+    """A batch and its samples one at a time take different launch shapes:
+    at 8 x 64 x 256 several convolutions split their channel chunks over
+    workgroups (fewer than 512 workgroups) in different ways for B = 8 and
+    B = 1, and the weight gradients split their pixels differently.  The
+    batch forward must equal the single-sample forwards, and the batch
+    gradient (the loss is a mean over samples) the mean of the single-sample
+    gradients, to the FP32-accumulation floor of the production-shape
+    reference: two FP32 summation orders of the same BF16-operand network
+    differ by up to that much, where a wrong split or route is O(1)."""
+    import json
+    import os
+    import torch
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_unet_samples.json")))
+    bar = ref["acc32_floor_y_m"]
+    B, H, W, P = 8, 64, 256, 8
+    spec, rng, theta, x, net, xt = _setup(A, B, H, W, P, 16, 14)
+    t_m = torch.tensor(0.3 * rng.standard_normal((B, P, H, W)), dtype=torch.float32, device="cuda")
+    t_w = torch.tensor(rng.uniform(0.1, 1, (B, H, W)), dtype=torch.float32, device="cuda")
+    y_m, y_w = net.forward(xt)
+    y_m, y_w = y_m.clone(), y_w.clone()
+    _, g = net.loss_grad(xt, t_m, t_w)
+    g = g.clone()
+    g_mean = torch.zeros_like(g)
+    e_m = e_w = 0.0
+    for i in range(B):
+        a, b = net.forward(xt[i:i + 1].contiguous())
+        e_m = max(e_m, rel_l2(a[0].cpu().numpy(), y_m[i].cpu().numpy()))
+        e_w = max(e_w, rel_l2(b[0].cpu().numpy(), y_w[i].cpu().numpy()))
+        _, gi = net.loss_grad(xt[i:i + 1].contiguous(), t_m[i:i + 1].contiguous(), t_w[i:i + 1].contiguous())
+        g_mean += gi
+    g_mean /= B
+    e_g = rel_l2(g_mean.cpu().numpy(), g.cpu().numpy())
+    print(f"[gpu] unet batch vs single: y_m {e_m:.2e} y_w {e_w:.2e} gradient {e_g:.2e} (bar {bar:.2e})", flush=True)
+    assert e_m <= bar and e_w <= bar and e_g <= bar
+
+
 def test_train_step_is_adamw_on_the_gradient(A):
     import torch
     B, H, W, P = 1, 16, 64, 4
