@@ -12,11 +12,14 @@
 // (so eight consecutive channels of one tap are one 16-byte read), D =
 // output channels x pixels, written as four consecutive channels of one
 // pixel (NHWC).  The input-gradient is the same kernel on the gradient of
-// the output (masked by the ReLU) with the transposed, tap-flipped weights.
-// Weight gradient: A = output gradient staged [co][pixel], B = input staged
-// [dx][ci][row][col] (three column-shifted copies keep every read aligned),
-// k = pixels; workgroups split the pixels and write FP32 partials that a
-// second kernel sums in a fixed order.
+// the output's pre-activation with the transposed, tap-flipped weights; its
+// epilogue routes the result to the tensors the forward input was built
+// from (ConvRoute).  Launches with few workgroups split the channel chunks
+// over workgroups and finish in k_conv_finish.
+// Weight gradient: A = output gradient, B = input, k = pixels, both staged
+// [pixel][channel] and read with the LDS transpose read; workgroups split
+// the pixels and write FP32 partials that one kernel for all layers sums in
+// a fixed order.
 #include "unet_internal.h"
 
 namespace unet {
@@ -303,8 +306,8 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
 }
 
 // ------------------------------------------------------------ 3x3 convolution
-// Grid: (row tiles x column tiles, output-channel tiles of 16 MT, batch).
-// Wave w computes output row w of the tile: up to MT x NTL MFMA tiles
+// Grid: (row tiles x column tiles, output-channel tiles of 16 MT, batch x
+// ksplit).  Wave w computes output row w of the tile: up to MT x NTL MFMA tiles
 // (16 MT channels x 16 NTL columns).  MT = 4, NTL = 2 in general; layers
 // with at most 16 output channels take MT = 1, NTL = 8 (128 columns), so
 // that every wave still issues eight MFMAs per k-step.
