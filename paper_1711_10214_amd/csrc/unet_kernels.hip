@@ -313,7 +313,7 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
 // that every wave still issues eight MFMAs per k-step.
 template <bool AF32, bool OUTF32, int MT = 4, int NTL = 2, bool UP = false>
 __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
-  static_assert(MT * NTL == 8, "eight 16 x 16 accumulator tiles per wave");
+  static_assert(MT * NTL == 8 || (MT == 1 && NTL == 4), "eight (or four) 16 x 16 accumulator tiles per wave");
   constexpr int TW = 16 * NTL;
   constexpr int TW2 = TW + 2;
   // input tile [row][col][channel], (kConvTH + 2) x TW2 pixels of CC + 8
@@ -1009,11 +1009,15 @@ static inline unsigned grid_for(long long n, int per = 256, int cap = 8192) {
 constexpr long long kConvSplitGroups = 512;
 
 static bool conv_wide(const ConvPack& pk, bool up) { return pk.Coutp <= 16 && !up; }
+// 16-channel outputs over 32-channel input chunks take 64-column tiles: the
+// 128-column tile's input staging (62 KB of LDS) would hold a CU to two
+// workgroups
+static bool conv_mid(const ConvPack& pk, bool up) { return conv_wide(pk, up) && pk.CC == 32; }
 
 // Channel-chunk split of a launch (1: none); the host sizes the partial
 // buffer with this same function.
 int conv_ksplit(const ConvPack& pk, int B, int H, int W, bool up) {
-  const int NTL = conv_wide(pk, up) ? 8 : 2, MT = conv_wide(pk, up) ? 1 : 4;
+  const int NTL = conv_mid(pk, up) ? 4 : (conv_wide(pk, up) ? 8 : 2), MT = conv_wide(pk, up) ? 1 : 4;
   const long long groups = (long long)((H + kConvTH - 1) / kConvTH) * ((W + 16 * NTL - 1) / (16 * NTL)) *
                            ((pk.Coutp + 16 * MT - 1) / (16 * MT)) * B;
   if (groups >= kConvSplitGroups) return 1;
@@ -1048,7 +1052,8 @@ hipError_t launch_conv3(const ConvArgs& args, bool af32, bool outf32, hipStream_
   if (a.ksplit > 1 && (!a.kpart || a.ksplit > a.pk.ncc)) return hipErrorInvalidValue;
   // one 16-channel tile of outputs: a wave takes 128 columns instead of 32
   // (the upsampled route takes 4 x 2 tiles)
-  if (conv_wide(a.pk, up)) conv3_launch<1, 8>(a, af32, outf32, s);
+  if (conv_mid(a.pk, up)) conv3_launch<1, 4>(a, af32, outf32, s);
+  else if (conv_wide(a.pk, up)) conv3_launch<1, 8>(a, af32, outf32, s);
   else conv3_launch<4, 2>(a, af32, outf32, s);
   if (a.ksplit > 1) {
     const long long npix = (long long)a.B * a.in.H * a.in.W;
