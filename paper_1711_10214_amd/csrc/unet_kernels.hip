@@ -309,11 +309,10 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
 // Grid: (row tiles x column tiles, output-channel tiles of 16 MT, batch x
 // ksplit).  Wave w computes output row w of the tile: up to MT x NTL MFMA tiles
 // (16 MT channels x 16 NTL columns).  MT = 4, NTL = 2 in general; layers
-// with at most 16 output channels take MT = 1, NTL = 8 (128 columns), so
-// that every wave still issues eight MFMAs per k-step.
+// with at most 16 output channels take MT = 1, NTL = 4 (64 columns).
 template <bool AF32, bool OUTF32, int MT = 4, int NTL = 2, bool UP = false>
 __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
-  static_assert(MT * NTL == 8 || (MT == 1 && NTL == 4), "eight (or four) 16 x 16 accumulator tiles per wave");
+  static_assert((MT == 4 && NTL == 2) || (MT == 1 && NTL == 4), "4 x 2 or 1 x 4 accumulator tiles per wave");
   constexpr int TW = 16 * NTL;
   constexpr int TW2 = TW + 2;
   // input tile [row][col][channel], (kConvTH + 2) x TW2 pixels of CC + 8
@@ -1008,16 +1007,24 @@ static inline unsigned grid_for(long long n, int per = 256, int cap = 8192) {
 // (such launches leave CUs idle while each workgroup walks every chunk).
 constexpr long long kConvSplitGroups = 512;
 
-static bool conv_wide(const ConvPack& pk, bool up) { return pk.Coutp <= 16 && !up; }
-// 16-channel outputs over 32-channel input chunks take 64-column tiles: the
-// 128-column tile's input staging (62 KB of LDS) would hold a CU to two
-// workgroups
-static bool conv_mid(const ConvPack& pk, bool up) { return conv_wide(pk, up) && pk.CC == 32; }
+// MFMA tile of a launch: MT 16-channel output tiles by NTL 16-column tiles
+// per wave.  4 x 2 in general and for the upsampled route; 16-channel
+// outputs take 1 x 4 (64 columns: wider tiles' input staging, 37-62 KB of
+// LDS, held a CU to two to four workgroups and measured slower).
+static void conv_tile(const ConvPack& pk, bool up, int& MT, int& NTL) {
+  MT = 4;
+  NTL = 2;
+  if (!up && pk.Coutp <= 16) {
+    MT = 1;
+    NTL = 4;
+  }
+}
 
 // Channel-chunk split of a launch (1: none); the host sizes the partial
 // buffer with this same function.
 int conv_ksplit(const ConvPack& pk, int B, int H, int W, bool up) {
-  const int NTL = conv_mid(pk, up) ? 4 : (conv_wide(pk, up) ? 8 : 2), MT = conv_wide(pk, up) ? 1 : 4;
+  int MT, NTL;
+  conv_tile(pk, up, MT, NTL);
   const long long groups = (long long)((H + kConvTH - 1) / kConvTH) * ((W + 16 * NTL - 1) / (16 * NTL)) *
                            ((pk.Coutp + 16 * MT - 1) / (16 * MT)) * B;
   if (groups >= kConvSplitGroups) return 1;
@@ -1050,10 +1057,9 @@ hipError_t launch_conv3(const ConvArgs& args, bool af32, bool outf32, hipStream_
   // FP32 outputs are input gradients: FP32 input, routed or not
   if (outf32 && !af32) return hipErrorInvalidValue;
   if (a.ksplit > 1 && (!a.kpart || a.ksplit > a.pk.ncc)) return hipErrorInvalidValue;
-  // one 16-channel tile of outputs: a wave takes 128 columns instead of 32
-  // (the upsampled route takes 4 x 2 tiles)
-  if (conv_mid(a.pk, up)) conv3_launch<1, 4>(a, af32, outf32, s);
-  else if (conv_wide(a.pk, up)) conv3_launch<1, 8>(a, af32, outf32, s);
+  int MT, NTL;
+  conv_tile(a.pk, up, MT, NTL);
+  if (MT == 1) conv3_launch<1, 4>(a, af32, outf32, s);
   else conv3_launch<4, 2>(a, af32, outf32, s);
   if (a.ksplit > 1) {
     const long long npix = (long long)a.B * a.in.H * a.in.W;
