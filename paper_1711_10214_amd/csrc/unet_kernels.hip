@@ -765,19 +765,23 @@ static void sum_parts(const float* part, int nblk, int ne, float* out, hipStream
 // ------------------------------------------------------------ heads
 // One pixel per thread: y_m = Wm h + bm (P channels, planar output), y_w =
 // sigmoid(Ww h + bw).  FP32 weights in LDS.
+// C1 (8, 16 or 32) at compile time: the head input stays in registers and
+// every weight row is read as C1 / 4 16-byte LDS broadcasts.
+template <int C1>
 __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
-  extern __shared__ float shw[];
-  const int C1 = a.C1, P = a.P;
-  float* sWm = shw;             // [P][C1], then bm [P]
-  float* sWw = shw + P * C1 + P;  // [C1], then bw
+  extern __shared__ __attribute__((aligned(16))) float shw[];
+  const int P = a.P;
+  float* sWm = shw;                 // [P][C1], then bm [P]
+  float* sWw = shw + P * C1 + P;    // [C1], then bw
   for (int i = threadIdx.x; i < P * C1 + P; i += blockDim.x) sWm[i] = a.Wm[i];
   for (int i = threadIdx.x; i < C1 + 1; i += blockDim.x) sWw[i] = a.Ww[i];
   __syncthreads();
   const long long HW = (long long)a.H * a.W, npix = a.B * HW;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  float h[32];
+  float h[C1];
   const uint16_t* hp = a.h + p * C1;
+#pragma unroll
   for (int c = 0; c < C1; c += 8) {
     float v[8];
     unpack8(*reinterpret_cast<const uint4*>(hp + c), v);
@@ -785,12 +789,23 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
     for (int i = 0; i < 8; ++i) h[c + i] = v[i];
   }
   const long long b = p / HW, yx = p - b * HW;
+  float* ym = a.y_m + b * P * HW + yx;
+#pragma unroll 2
   for (int co = 0; co < P; ++co) {
     float s = sWm[P * C1 + co];
-    for (int c = 0; c < C1; ++c) s = fmaf(sWm[co * C1 + c], h[c], s);
-    a.y_m[(b * P + co) * HW + yx] = s;
+    const float4* w = reinterpret_cast<const float4*>(sWm + co * C1);
+#pragma unroll
+    for (int c = 0; c < C1 / 4; ++c) {
+      const float4 q = w[c];
+      s = fmaf(q.x, h[4 * c], s);
+      s = fmaf(q.y, h[4 * c + 1], s);
+      s = fmaf(q.z, h[4 * c + 2], s);
+      s = fmaf(q.w, h[4 * c + 3], s);
+    }
+    ym[co * HW] = s;
   }
   float z = sWw[C1];
+#pragma unroll
   for (int c = 0; c < C1; ++c) z = fmaf(sWw[c], h[c], z);
   a.y_w[p] = 1.0f / (1.0f + __expf(-z));
 }
@@ -806,11 +821,12 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
 // register-blocked: a thread takes a 4 x 4 tile of entries over one of G
 // pixel ranges (8 LDS reads per 16 FMAs), and the G range sums of an entry
 // are added in range order.
+template <int C1>
 __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
-  extern __shared__ float sh[];
+  extern __shared__ __attribute__((aligned(16))) float sh[];
   __shared__ double sred[2][4];
   const HeadArgs& d = a.hd;
-  const int C1 = d.C1, P = d.P, tid = (int)threadIdx.x;
+  const int P = d.P, tid = (int)threadIdx.x;
   const int GP = P + 1, HC = C1 + 1;
   float* sgy = sh;
   float* shh = sgy + 256 * GP;
@@ -857,23 +873,32 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
   }
   __syncthreads();
   if (p < npix) {
-    // four channels per 16-byte store (C1 is a multiple of 8)
+    // g_h[c] = Ww[c] gz + sum over co of Wm[co][c] gy[co], co ascending; all
+    // C1 sums in registers, each gy read once, each Wm row as C1 / 4
+    // 16-byte LDS broadcasts
     const float gz = sgy[tid * GP + P];
-    for (int c = 0; c < C1; c += 4) {
-      float s[4];
+    float s[C1];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) s[i] = sWw[c + i] * gz;
-      for (int co = 0; co < P; ++co) {
-        const float gy = sgy[tid * GP + co];
+    for (int c = 0; c < C1; ++c) s[c] = sWw[c] * gz;
+    for (int co = 0; co < P; ++co) {
+      const float gy = sgy[tid * GP + co];
+      const float4* w = reinterpret_cast<const float4*>(sWm + co * C1);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s[i] = fmaf(sWm[co * C1 + c + i], gy, s[i]);
+      for (int c = 0; c < C1 / 4; ++c) {
+        const float4 q = w[c];
+        s[4 * c] = fmaf(q.x, gy, s[4 * c]);
+        s[4 * c + 1] = fmaf(q.y, gy, s[4 * c + 1]);
+        s[4 * c + 2] = fmaf(q.z, gy, s[4 * c + 2]);
+        s[4 * c + 3] = fmaf(q.w, gy, s[4 * c + 3]);
       }
-      // the head input is a ReLU output: store the gradient of its pre-activation
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (!(shh[tid * HC + c + i] > 0.f)) s[i] = 0.f;
-      *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[0], s[1], s[2], s[3]);
     }
+    // the head input is a ReLU output: store the gradient of its pre-activation
+#pragma unroll
+    for (int c = 0; c < C1; ++c)
+      if (!(shh[tid * HC + c] > 0.f)) s[c] = 0.f;
+#pragma unroll
+    for (int c = 0; c < C1; c += 4)
+      *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[c], s[c + 1], s[c + 2], s[c + 3]);
   }
   if (grp < G) {
     for (int t = tlo; t < thi; ++t) {
@@ -1100,14 +1125,23 @@ size_t head_bwd_lds(int P, int C1) {
 
 hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
   const long long npix = (long long)a.B * a.H * a.W;
-  hipLaunchKernelGGL(k_head_fwd, dim3((unsigned)((npix + 255) / 256)), dim3(256), head_fwd_lds(a.P, a.C1), s, a);
+  const dim3 grid((unsigned)((npix + 255) / 256));
+  const size_t lds = head_fwd_lds(a.P, a.C1);
+  if (a.C1 == 8) hipLaunchKernelGGL(k_head_fwd<8>, grid, dim3(256), lds, s, a);
+  else if (a.C1 == 16) hipLaunchKernelGGL(k_head_fwd<16>, grid, dim3(256), lds, s, a);
+  else if (a.C1 == 32) hipLaunchKernelGGL(k_head_fwd<32>, grid, dim3(256), lds, s, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s) {
   const long long npix = (long long)a.hd.B * a.hd.H * a.hd.W;
   if (((a.hd.P + 4) / 4) * ((a.hd.C1 + 4) / 4) > 256) return hipErrorInvalidValue;  // one tile per thread at least
-  hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), head_bwd_lds(a.hd.P, a.hd.C1), s, a);
+  const size_t lds = head_bwd_lds(a.hd.P, a.hd.C1);
+  if (a.hd.C1 == 8) hipLaunchKernelGGL(k_head_bwd<8>, dim3(nblk), dim3(256), lds, s, a);
+  else if (a.hd.C1 == 16) hipLaunchKernelGGL(k_head_bwd<16>, dim3(nblk), dim3(256), lds, s, a);
+  else if (a.hd.C1 == 32) hipLaunchKernelGGL(k_head_bwd<32>, dim3(nblk), dim3(256), lds, s, a);
+  else return hipErrorInvalidValue;
   sum_parts((const float*)a.hpart, nblk, a.ne, ghead, s);
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, (const double*)a.lpart, nblk,
                      (double)npix * a.hd.P, (double)npix, lam_w, loss);
@@ -1127,8 +1161,13 @@ hipError_t launch_adamw(float* th, const float* g, float* m, float* v, long long
 
 
 hipError_t unet_kernels_init() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_head_bwd),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  hipError_t e = hipSuccess;
+  const void* fns[3] = {reinterpret_cast<const void*>(&k_head_bwd<8>), reinterpret_cast<const void*>(&k_head_bwd<16>),
+                        reinterpret_cast<const void*>(&k_head_bwd<32>)};
+  for (const void* f : fns) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+  }
   return e;
 }
 
