@@ -386,8 +386,14 @@ int run_backward(const unet_net& n, const WsLayout& w, unsigned char* ws, const 
     da.kpart = (float*)(ws + w.kpart);
     U_TRY(launch_conv3(da, true, true, s));
   }
-  red.start[0] = 0;
-  for (int i = 0; i < kNConv; ++i) red.start[i + 1] = red.start[i] + red.L[i].Cout * (red.L[i].Cin * 9 + 1);
+  // 16 elements a workgroup (16 thread groups over the splits) where a
+  // layer has at least 256 splits, else 64 (4 groups)
+  red.wg[0] = 0;
+  for (int i = 0; i < kNConv; ++i) {
+    RedLayer& rl = red.L[i];
+    rl.e = rl.nsplit >= 256 ? 16 : 64;
+    red.wg[i + 1] = red.wg[i] + (rl.Cout * (rl.Cin * 9 + 1) + rl.e - 1) / rl.e;
+  }
   U_TRY(launch_wgrad_reduce(red, s));
   return ASHRT_OK;
 }

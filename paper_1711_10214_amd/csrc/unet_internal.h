@@ -89,9 +89,10 @@ struct PackArgs {
   ConvPack f, t;
 };
 // The weight and bias gradients of every convolution summed from their
-// pixel-split partials in one launch: element e belongs to layer l with
-// start[l] <= e < start[l + 1], weights first (in the partials' (co, kk,
-// ci) order), then the Cout biases.
+// pixel-split partials in one launch.  Layer l's elements (weights in the
+// partials' (co, kk, ci) order, then the Cout biases) go to workgroups
+// wg[l] <= b < wg[l + 1], e of them per workgroup (64, or 16 with more
+// thread groups over the splits where a layer has many splits).
 constexpr int kRedMax = 20;
 struct RedLayer {
   const float* part;        // [nsplit][Cout][9][Cipw]
@@ -99,10 +100,11 @@ struct RedLayer {
   float* grad;              // [Cout][Cin][3][3]
   float* gb;                // [Cout]
   int nsplit, Cout, Cin, Cipw;
+  int e;                    // elements per workgroup: 16 or 64
 };
 struct RedAll {
   int n;
-  int start[kRedMax + 1];
+  int wg[kRedMax + 1];
   RedLayer L[kRedMax];
 };
 // Every convolution's packings in one launch: packed element e belongs to

@@ -678,51 +678,44 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 
 // Sum the pixel-split partials of every layer (see RedAll) into the
 // canonical weight gradients [Cout][Cin][3][3] and the bias gradients.  A
-// workgroup takes E consecutive elements (one per lane: each wave load is
-// E consecutive floats) and 256 / E thread groups over the splits (split
-// sp -> group sp mod G); the G partial sums of an element are added in
-// group order, so the result does not depend on timing.
-template <int E>
+// workgroup takes E consecutive elements of one layer (E = 64: each wave
+// load is 64 consecutive floats; E = 16 for layers with many splits, so that
+// no thread walks a long chain of them) and 256 / E thread groups over the
+// splits (split sp -> group sp mod G); the G partial sums of an element are
+// added in group order, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(RedAll a) {
-  constexpr int G = 256 / E;
-  __shared__ float s[G][E + 1];
+  __shared__ float s[16 * 17 > 4 * 65 ? 16 * 17 : 4 * 65];
+  const int b = (int)blockIdx.x;
+  int l = 0;
+  while (b >= a.wg[l + 1]) ++l;
+  const RedLayer& L = a.L[l];
+  const int E = L.e, G = 256 / E;
   const int te = (int)threadIdx.x % E, g = (int)threadIdx.x / E;
-  const int n = a.start[a.n];
-  for (int j0 = blockIdx.x * E; j0 < n; j0 += gridDim.x * E) {
-    const int j = j0 + te;
-    float acc = 0.f;
-    int l = 0, co = 0, kk = 0, ci = 0, jl = 0;
-    if (j < n) {
-      while (j >= a.start[l + 1]) ++l;
-      const RedLayer& L = a.L[l];
-      jl = j - a.start[l];
-      const int nw = L.Cout * L.Cin * 9;
-      if (jl < nw) {
-        // neighbouring elements are neighbouring ci: coalesced partial reads
-        co = jl / (9 * L.Cin);
-        const int r = jl - co * 9 * L.Cin;
-        kk = r / L.Cin;
-        ci = r - kk * L.Cin;
-        const long long stride = (long long)L.Cout * 9 * L.Cipw;
-        const float* p = L.part + ((long long)co * 9 + kk) * L.Cipw + ci;
+  const int nw = L.Cout * L.Cin * 9, n = nw + L.Cout;
+  const int jl = (b - a.wg[l]) * E + te;
+  float acc = 0.f;
+  int co = 0, kk = 0, ci = 0;
+  if (jl < nw) {
+    // neighbouring elements are neighbouring ci: coalesced partial reads
+    co = jl / (9 * L.Cin);
+    const int r = jl - co * 9 * L.Cin;
+    kk = r / L.Cin;
+    ci = r - kk * L.Cin;
+    const long long stride = (long long)L.Cout * 9 * L.Cipw;
+    const float* p = L.part + ((long long)co * 9 + kk) * L.Cipw + ci;
 #pragma unroll 8
-        for (int sp = g; sp < L.nsplit; sp += G) acc += p[sp * stride];
-      } else {
+    for (int sp = g; sp < L.nsplit; sp += G) acc += p[sp * stride];
+  } else if (jl < n) {
 #pragma unroll 8
-        for (int sp = g; sp < L.nsplit; sp += G) acc += L.bpart[(long long)sp * L.Cout + (jl - nw)];
-      }
-    }
-    s[g][te] = acc;
-    __syncthreads();
-    if (g == 0 && j < n) {
-      float t = 0.f;
-      for (int q = 0; q < G; ++q) t += s[q][te];
-      const RedLayer& L = a.L[l];
-      const int nw = L.Cout * L.Cin * 9;
-      if (jl < nw) L.grad[((long long)co * L.Cin + ci) * 9 + kk] = t;
-      else L.gb[jl - nw] = t;
-    }
-    __syncthreads();
+    for (int sp = g; sp < L.nsplit; sp += G) acc += L.bpart[(long long)sp * L.Cout + (jl - nw)];
+  }
+  s[g * (E + 1) + te] = acc;
+  __syncthreads();
+  if (g == 0 && jl < n) {
+    float t = 0.f;
+    for (int q = 0; q < G; ++q) t += s[q * (E + 1) + te];
+    if (jl < nw) L.grad[((long long)co * L.Cin + ci) * 9 + kk] = t;
+    else L.gb[jl - nw] = t;
   }
 }
 
@@ -1111,8 +1104,8 @@ hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
 }
 
 hipError_t launch_wgrad_reduce(const RedAll& a, hipStream_t s) {
-  const long long g = (a.start[a.n] + 63) / 64;
-  hipLaunchKernelGGL(k_wgrad_reduce<64>, dim3((unsigned)(g > 16384 ? 16384 : g)), dim3(256), 0, s, a);
+  if (a.wg[a.n] < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)a.wg[a.n]), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
