@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void k_conv_finish(ConvArgs a) {
 }
 
 // ------------------------------------------------------------ weight gradient
-// Grid: (input-channel chunks, output-channel tiles of COT, pixel splits).
+// Grid: (input-channel chunks, output-channel tiles of COT (16, 32 or 64), pixel splits).
 // Wave w accumulates the taps kk = w, w + 4, w + 8.  Both operands are
 // staged in LDS pixel-major with channels contiguous (one 16-byte store per
 // 8 channels of a pixel, the tap shift being a per-lane address offset) and
@@ -1088,7 +1088,9 @@ hipError_t launch_conv3(const ConvArgs& args, bool af32, bool outf32, hipStream_
   return hipGetLastError();
 }
 
-int wgrad_cot(int Cout) { return Cout <= 16 ? 16 : 64; }
+// output-channel tile of the weight gradient: 16, 32 or 64 (no idle tiles
+// for 16- and 32-channel layers)
+int wgrad_cot(int Cout) { return Cout <= 16 ? 16 : (Cout <= 32 ? 32 : 64); }
 
 hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
   const int cot = wgrad_cot(a.Cout);
@@ -1096,6 +1098,9 @@ hipError_t launch_wgrad(const WgradArgs& a, bool af32, hipStream_t s) {
   if (cot == 16) {
     if (af32) hipLaunchKernelGGL((k_wgrad<true, 16>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_wgrad<false, 16>), grid, dim3(256), 0, s, a);
+  } else if (cot == 32) {
+    if (af32) hipLaunchKernelGGL((k_wgrad<true, 32>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_wgrad<false, 32>), grid, dim3(256), 0, s, a);
   } else {
     if (af32) hipLaunchKernelGGL((k_wgrad<true, 64>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_wgrad<false, 64>), grid, dim3(256), 0, s, a);
