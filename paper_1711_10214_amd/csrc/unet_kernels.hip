@@ -756,6 +756,8 @@ static void sum_parts(const float* part, int nblk, int ne, float* out, hipStream
 }
 
 // ------------------------------------------------------------ heads
+constexpr int kHeadRowTiles = 5;  // 16-row tiles of the P + 1 <= 65 head-gradient rows
+
 // One pixel per thread: y_m = Wm h + bm (P channels, planar output), y_w =
 // sigmoid(Ww h + bw).  FP32 weights in LDS.
 // C1 (8, 16 or 32) at compile time: the head input stays in registers and
@@ -808,12 +810,12 @@ __global__ __launch_bounds__(256) void k_head_fwd(HeadArgs a) {
 // head-parameter gradient and of the two squared errors.
 // One 256-pixel block per workgroup.  Dynamic LDS: gy [256][P+1] (column
 // P: the gradient gz of the weight head's logit), h [256][C1+1] (column C1:
-// 1), Wm [P][C1], Ww [C1]; the partials of the parameter gradient reuse it
-// from the start once those are read.  Every head parameter's block gradient is one entry of
-// sum_t gy[t] h[t]^T, a (P+1) x (C1+1) outer-product sum (Wm, bm; Ww, bw),
-// register-blocked: a thread takes a 4 x 4 tile of entries over one of G
-// pixel ranges (8 LDS reads per 16 FMAs), and the G range sums of an entry
-// are added in range order.
+// 1), Wm [P][C1], Ww [C1]; the waves' partials of the parameter gradient
+// reuse it from the start once those are read.  Every head parameter's
+// block gradient is one entry of sum_t gy[t] h[t]^T, a (P+1) x (C1+1)
+// outer-product sum (Wm, bm; Ww, bw), computed on the FP32 matrix cores,
+// each wave over a quarter of the block's pixels, and added over the waves
+// in wave order.
 template <int C1>
 __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
   extern __shared__ __attribute__((aligned(16))) float sh[];
@@ -829,16 +831,19 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
   for (int i = tid; i < C1; i += 256) sWw[i] = d.Ww[i];
   const long long HW = (long long)d.H * d.W, npix = d.B * HW;
   const float inv_m = 1.0f / (float)((double)npix * P), inv_w = 1.0f / (float)npix;
-  const int tP = (GP + 3) >> 2, tC = (HC + 3) >> 2, nT = tP * tC;
-  const int G = 256 / nT;  // nT <= 256: checked by the launcher
-  const int tile = tid % nT, grp = tid / nT;
-  const int r0 = (tile / tC) * 4, c0 = (tile % tC) * 4;
-  const int tlo = grp * 256 / G, thi = (grp + 1) * 256 / G;
-  float acc[4][4];
+  // parameter-gradient block sums on the FP32 matrix cores
+  // (v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16] and
+  // B[l / 16][l % 16] and receives D[4 (l / 16) + i][l % 16]):
+  // D[r][c] = sum_t gy[t][r] h[t][c], r < P + 1, c < C1 + 1, in 16 x 16
+  // tiles; wave w takes pixels 64 w .. 64 w + 63 (16 k-steps of 4)
+  constexpr int TC = (C1 + 1 + 15) / 16;
+  const int TR = (GP + 15) / 16;  // <= kHeadRowTiles: checked by the launcher
+  const int wave = tid >> 6, lane = tid & 63, kq = lane >> 4, l16 = lane & 15;
+  f32x4 acc[kHeadRowTiles][TC];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kHeadRowTiles; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int j = 0; j < TC; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   double lm = 0.0, lw = 0.0;
   const long long p = (long long)blockIdx.x * 256 + tid;
   if (p < npix) {
@@ -893,30 +898,33 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
     for (int c = 0; c < C1; c += 4)
       *reinterpret_cast<float4*>(a.g_h + p * C1 + c) = make_float4(s[c], s[c + 1], s[c + 2], s[c + 3]);
   }
-  if (grp < G) {
-    for (int t = tlo; t < thi; ++t) {
-      float gy[4], hh[4];
+  for (int ks = 0; ks < 16; ++ks) {
+    const int t = 64 * wave + 4 * ks + kq;
+    float hb[TC];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        gy[i] = r0 + i < GP ? sgy[t * GP + r0 + i] : 0.f;
-        hh[i] = c0 + i < HC ? shh[t * HC + c0 + i] : 0.f;
-      }
+    for (int ct = 0; ct < TC; ++ct) hb[ct] = 16 * ct + l16 < HC ? shh[t * HC + 16 * ct + l16] : 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int rt = 0; rt < kHeadRowTiles; ++rt) {
+      if (rt >= TR) continue;
+      const float ga = 16 * rt + l16 < GP ? sgy[t * GP + 16 * rt + l16] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gy[i], hh[j], acc[i][j]);
+      for (int ct = 0; ct < TC; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, hb[ct], acc[rt][ct], 0, 0, 0);
     }
   }
-  __syncthreads();  // gy and h are read: their space takes the partials
-  float* red = sh;
-  if (grp < G) {
+  __syncthreads();  // gy and h are read: their space takes the wave partials
+  float* red = sh;   // [wave][TR][TC][16 x 16]
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int rt = 0; rt < kHeadRowTiles; ++rt) {
+    if (rt >= TR) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) red[(grp * nT + tile) * 16 + i * 4 + j] = acc[i][j];
+    for (int ct = 0; ct < TC; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        red[((wave * TR + rt) * TC + ct) * 256 + (4 * kq + i) * 16 + l16] = acc[rt][ct][i];
   }
   __syncthreads();
-  // entry e of the partial layout [Wm P x C1][bm P][Ww C1][bw] -> (r, c)
+  // entry e of the partial layout [Wm P x C1][bm P][Ww C1][bw] -> (r, c),
+  // the four waves' sums added in wave order
   for (int e = tid; e < a.ne; e += 256) {
     int r, c;
     if (e < P * C1) {
@@ -929,9 +937,9 @@ __global__ __launch_bounds__(256) void k_head_bwd(LossArgs a) {
       r = P;
       c = e - P * C1 - P;  // C1 for bw
     }
-    const int o = ((r >> 2) * tC + (c >> 2)) * 16 + (r & 3) * 4 + (c & 3);
+    const int o = ((r >> 4) * TC + (c >> 4)) * 256 + (r & 15) * 16 + (c & 15);
     float sum = 0.f;
-    for (int g = 0; g < G; ++g) sum += red[g * nT * 16 + o];
+    for (int w = 0; w < 4; ++w) sum += red[w * TR * TC * 256 + o];
     a.hpart[(long long)blockIdx.x * a.ne + e] = sum;
   }
   // block sums of the squared errors (fixed order)
@@ -1116,8 +1124,8 @@ hipError_t launch_wgrad_reduce(const RedAll& a, hipStream_t s) {
 
 size_t head_fwd_lds(int P, int C1) { return (size_t)(P * C1 + P + C1 + 1) * 4; }
 size_t head_bwd_lds(int P, int C1) {
-  const int nT = ((P + 4) / 4) * ((C1 + 4) / 4);  // 4 x 4 tiles of the (P + 1) x (C1 + 1) entries
-  const size_t red = (size_t)(256 / nT) * nT * 16;
+  // the four waves' 16 x 16 tiles of the (P + 1) x (C1 + 1) entries
+  const size_t red = (size_t)4 * ((P + 16) / 16) * ((C1 + 16) / 16) * 256;
   return std::max((size_t)(256 * (P + 1) + 256 * (C1 + 1) + P * C1 + C1), red) * 4;
 }
 
@@ -1134,7 +1142,7 @@ hipError_t launch_head_fwd(const HeadArgs& a, hipStream_t s) {
 
 hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* loss, double lam_w, hipStream_t s) {
   const long long npix = (long long)a.hd.B * a.hd.H * a.hd.W;
-  if (((a.hd.P + 4) / 4) * ((a.hd.C1 + 4) / 4) > 256) return hipErrorInvalidValue;  // one tile per thread at least
+  if ((a.hd.P + 1 + 15) / 16 > kHeadRowTiles) return hipErrorInvalidValue;
   const size_t lds = head_bwd_lds(a.hd.P, a.hd.C1);
   if (a.hd.C1 == 8) hipLaunchKernelGGL(k_head_bwd<8>, dim3(nblk), dim3(256), lds, s, a);
   else if (a.hd.C1 == 16) hipLaunchKernelGGL(k_head_bwd<16>, dim3(nblk), dim3(256), lds, s, a);
