@@ -578,45 +578,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   // bias partial: thread t always stages channel group t % NG
   float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-  for (int t = split; t < T; t += a.nsplit) {
-    const int b = t / (tiles_x * tiles_y);
-    const int rem = t - b * tiles_x * tiles_y;
-    const int ty0 = (rem / tiles_x) * kWgTH, tx0 = (rem % tiles_x) * kWgTW;
-    // output gradient (of the pre-activation), [pixel][co]; the loads of
-    // U tasks are issued before any is stored
-    {
-      constexpr int U = 4;
-      constexpr int NTASK = kWgTH * kWgTW * NG;
-      for (int t0 = threadIdx.x; t0 < NTASK; t0 += U * 256) {
-        float4 p[U], q[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int task = t0 + u * 256;
-          p[u] = q[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-          const int g = task % NG, pix = task / NG;
-          const int row = pix / kWgTW, px = pix - row * kWgTW;
-          const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
-          if (task < NTASK && y < H && x < W && co < a.Cout) {
-            const long long o = (((long long)b * H + y) * W + x) * a.Cout + co;
-            p[u] = *reinterpret_cast<const float4*>(a.gY + o);
-            q[u] = *reinterpret_cast<const float4*>(a.gY + o + 4);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int task = t0 + u * 256;
-          if (task < NTASK) {
-            const float v[8] = {p[u].x, p[u].y, p[u].z, p[u].w, q[u].x, q[u].y, q[u].z, q[u].w};
-#pragma unroll
-            for (int i = 0; i < 8; ++i) bsum[i] += v[i];
-            *reinterpret_cast<uint4*>(sZ + (task / NG) * ZP + (task % NG) * 8) = pack8(v);
-          }
-        }
-      }
-    }
-    // input tile with a one-pixel halo, [pixel][ci]
-    stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, XR, XW, cc * a.CCw, ngx, sX, XP);
-    __syncthreads();
+  // the MFMA work of the tile staged in sZ and sX
+  auto tile_mfma = [&]() {
     for (int row = 0; row < kWgTH; ++row) {
       bf16x8 af[MT];
 #pragma unroll
@@ -637,7 +600,110 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         }
       }
     }
-    __syncthreads();
+  };
+
+  // Light loaders (BF16 without pooling) and 16-channel output tiles: the
+  // next tile's loads are issued before this tile's multiplies, so a
+  // workgroup walking many tiles waits on one memory latency per tile less
+  // (wider tiles measured slower with the extra registers).
+  constexpr int UZ = kWgTH * kWgTW * NG / 256;  // output-gradient tasks per thread
+  constexpr int UX = 4;                           // input tasks per thread (XR XW ngx <= 816)
+  if (COT == 16 && !AF32 && a.in.modeA != 2) {
+    const int ntx = XR * XW * ngx;
+    float4 zp[UZ], zq[UZ];
+    uint4 xq[UX];
+    auto fetch = [&](int t) {
+      const int b = t / (tiles_x * tiles_y);
+      const int rem = t - b * tiles_x * tiles_y;
+      const int ty0 = (rem / tiles_x) * kWgTH, tx0 = (rem % tiles_x) * kWgTW;
+#pragma unroll
+      for (int u = 0; u < UZ; ++u) {
+        const int task = (int)threadIdx.x + u * 256;
+        const int g = task % NG, pix = task / NG;
+        const int row = pix / kWgTW, px = pix - row * kWgTW;
+        const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
+        zp[u] = zq[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (y < H && x < W && co < a.Cout) {
+          const long long o = (((long long)b * H + y) * W + x) * a.Cout + co;
+          zp[u] = *reinterpret_cast<const float4*>(a.gY + o);
+          zq[u] = *reinterpret_cast<const float4*>(a.gY + o + 4);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UX; ++u) {
+        const int task = (int)threadIdx.x + u * 256;
+        xq[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (task < ntx) {
+          const int g = task % ngx, pix = task / ngx;
+          const int r = pix / XW, xx = pix - r * XW;
+          const uint4* src = in8_src(a.in, b, ty0 - 1 + r, tx0 - 1 + xx, cc * a.CCw + g * 8);
+          if (src) xq[u] = *src;
+        }
+      }
+    };
+    fetch(split);  // split < T: the host takes at most T splits
+    for (int t = split; t < T; t += a.nsplit) {
+#pragma unroll
+      for (int u = 0; u < UZ; ++u) {
+        const int task = (int)threadIdx.x + u * 256;
+        const float v[8] = {zp[u].x, zp[u].y, zp[u].z, zp[u].w, zq[u].x, zq[u].y, zq[u].z, zq[u].w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bsum[i] += v[i];
+        *reinterpret_cast<uint4*>(sZ + (task / NG) * ZP + (task % NG) * 8) = pack8(v);
+      }
+#pragma unroll
+      for (int u = 0; u < UX; ++u) {
+        const int task = (int)threadIdx.x + u * 256;
+        if (task < ntx) *reinterpret_cast<uint4*>(sX + (task / ngx) * XP + (task % ngx) * 8) = xq[u];
+      }
+      __syncthreads();
+      if (t + a.nsplit < T) fetch(t + a.nsplit);
+      tile_mfma();
+      __syncthreads();
+    }
+  } else {
+    for (int t = split; t < T; t += a.nsplit) {
+      const int b = t / (tiles_x * tiles_y);
+      const int rem = t - b * tiles_x * tiles_y;
+      const int ty0 = (rem / tiles_x) * kWgTH, tx0 = (rem % tiles_x) * kWgTW;
+      // output gradient (of the pre-activation), [pixel][co]; the loads of
+      // U tasks are issued before any is stored
+      {
+        constexpr int U = 4;
+        constexpr int NTASK = kWgTH * kWgTW * NG;
+        for (int t0 = threadIdx.x; t0 < NTASK; t0 += U * 256) {
+          float4 p[U], q[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int task = t0 + u * 256;
+            p[u] = q[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int g = task % NG, pix = task / NG;
+            const int row = pix / kWgTW, px = pix - row * kWgTW;
+            const int y = ty0 + row, x = tx0 + px, co = co0 + g * 8;
+            if (task < NTASK && y < H && x < W && co < a.Cout) {
+              const long long o = (((long long)b * H + y) * W + x) * a.Cout + co;
+              p[u] = *reinterpret_cast<const float4*>(a.gY + o);
+              q[u] = *reinterpret_cast<const float4*>(a.gY + o + 4);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int task = t0 + u * 256;
+            if (task < NTASK) {
+              const float v[8] = {p[u].x, p[u].y, p[u].z, p[u].w, q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+              for (int i = 0; i < 8; ++i) bsum[i] += v[i];
+              *reinterpret_cast<uint4*>(sZ + (task / NG) * ZP + (task % NG) * 8) = pack8(v);
+            }
+          }
+        }
+      }
+      // input tile with a one-pixel halo, [pixel][ci]
+      stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, XR, XW, cc * a.CCw, ngx, sX, XP);
+      __syncthreads();
+      tile_mfma();
+      __syncthreads();
+    }
   }
 
 #pragma unroll
