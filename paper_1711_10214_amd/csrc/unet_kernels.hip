@@ -344,15 +344,18 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
     wrow[mi] = a.Wp + ((long long)min(co0 + mi * 16 + n16, P.Coutp - 1) * P.ncc * P.KKp + tap_l) * CC + coff;
-  // the A fragments of the next k-step are loaded while this one multiplies
-  uint4 wq[MT];
+  // the A fragments of the next two k-steps are in flight while this one
+  // multiplies (wq: step s + 1, wq2: step s + 2)
+  uint4 wq[MT], wq2[MT];
   // this split's channel chunks (all of them without a split)
   const int cc_lo = ks * P.ncc / a.ksplit, cc_hi = (ks + 1) * P.ncc / a.ksplit;
-  const long long s0 = (long long)cc_lo * nkc * P.TPK * CC;
+  const int nks = cc_hi * nkc, sb = cc_lo * nkc;
 #pragma unroll
-  for (int mi = 0; mi < MT; ++mi)
-    wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi] + s0) : make_uint4(0u, 0u, 0u, 0u);
-  const int nks = cc_hi * nkc;
+  for (int mi = 0; mi < MT; ++mi) {
+    wq[mi] = mi < MI ? *reinterpret_cast<const uint4*>(wrow[mi] + (long long)sb * P.TPK * CC) : make_uint4(0u, 0u, 0u, 0u);
+    wq2[mi] = (mi < MI && sb + 1 < nks) ? *reinterpret_cast<const uint4*>(wrow[mi] + (long long)(sb + 1) * P.TPK * CC)
+                                          : make_uint4(0u, 0u, 0u, 0u);
+  }
 
   for (int cc = cc_lo; cc < cc_hi; ++cc) {
     stage_tile<AF32>(a.in, b, ty0 - 1, tx0 - 1, kConvTH + 2, TW2, cc * CC, ng, sX, PS);
@@ -371,12 +374,15 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
       }
       bf16x8 afrag[MT];
 #pragma unroll
-      for (int mi = 0; mi < MT; ++mi) afrag[mi] = __builtin_bit_cast(bf16x8, wq[mi]);
-      const int sn = cc * nkc + kc + 1;
+      for (int mi = 0; mi < MT; ++mi) {
+        afrag[mi] = __builtin_bit_cast(bf16x8, wq[mi]);
+        wq[mi] = wq2[mi];
+      }
+      const int sn = cc * nkc + kc + 2;
       if (sn < nks) {
 #pragma unroll
         for (int mi = 0; mi < MT; ++mi)
-          if (mi < MI) wq[mi] = *reinterpret_cast<const uint4*>(wrow[mi] + (long long)sn * P.TPK * CC);
+          if (mi < MI) wq2[mi] = *reinterpret_cast<const uint4*>(wrow[mi] + (long long)sn * P.TPK * CC);
       }
 #pragma unroll
       for (int mi = 0; mi < MT; ++mi) {
