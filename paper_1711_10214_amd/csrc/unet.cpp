@@ -228,7 +228,8 @@ WsLayout layout(const unet_net& n, int B, int H, int W, bool train) {
     }
     w.nblk_h = (int)((npix0 + 255) / 256);  // head-backward workgroups, one per 256 pixels
     const int ne = n.pout * n.base + n.pout + n.base + 1;
-    w.hpart = take((long long)w.nblk_h * ne * 4);
+    // the head partials, then the rows of their first summation stage
+    w.hpart = take(((long long)w.nblk_h + (w.nblk_h + 63) / 64) * ne * 4);
     w.lpart = take((long long)w.nblk_h * 2 * 8);
   }
   w.total = off;

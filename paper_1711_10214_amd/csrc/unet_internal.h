@@ -133,7 +133,7 @@ struct LossArgs {
   const float* t_w;
   float lam_w;
   float* g_h;               // FP32 NHWC [B][H][W][C1] gradient of the head input's pre-activation (ReLU)
-  float* hpart;             // [nblk][17 * P + 17 ... ] head parameter-gradient partials
+  float* hpart;             // [nblk][ne] head parameter-gradient partials, then [ceil(nblk / 64)][ne] scratch
   double* lpart;            // [nblk][2]
   int ne;                   // entries per head partial: P*C1 + P + C1 + 1
 };

@@ -791,40 +791,34 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(RedAll a) {
   }
 }
 
-// out[e] = sum over k of part[k ne + e]: E consecutive elements per
-// workgroup and 256 / E thread groups over k (k -> group k mod G), the
-// groups' sums added in group order (deterministic).
-template <int E>
-__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nblk, int ne,
-                                                  float* __restrict__ out) {
-  constexpr int G = 256 / E;
-  __shared__ float s[G][E + 1];
-  const int te = (int)threadIdx.x % E, g = (int)threadIdx.x / E;
-  for (int e0 = blockIdx.x * E; e0 < ne; e0 += gridDim.x * E) {
-    const int e = e0 + te;
-    float acc = 0.f;
-    if (e < ne)
-      for (int k = g; k < nblk; k += G) acc += part[(long long)k * ne + e];
-    s[g][te] = acc;
-    __syncthreads();
-    if (g == 0 && e < ne) {
-      float t = 0.f;
-      for (int q = 0; q < G; ++q) t += s[q][te];
-      out[e] = t;
-    }
-    __syncthreads();
-  }
+// out[seg ne + e] = sum over the rows k of segment seg (rows seg R ..
+// min(seg R + R, nblk) - 1) of part[k ne + e]: 64 consecutive elements per
+// workgroup (one per lane: each wave load is 64 consecutive floats) and
+// the four waves over the segment's rows (row k -> wave (k - seg R) mod 4),
+// the waves' sums added in wave order (deterministic).
+__global__ __launch_bounds__(256) void k_sum_rows(const float* __restrict__ part, int nblk, int ne, int R,
+                                                 float* __restrict__ out) {
+  __shared__ float s[4][65];
+  const int te = (int)threadIdx.x & 63, g = (int)threadIdx.x >> 6;
+  const int seg = (int)blockIdx.y, e = (int)blockIdx.x * 64 + te;
+  const int k0 = seg * R, k1 = min(k0 + R, nblk);
+  float acc = 0.f;
+  if (e < ne)
+    for (int k = k0 + g; k < k1; k += 4) acc += part[(long long)k * ne + e];
+  s[g][te] = acc;
+  __syncthreads();
+  if (g == 0 && e < ne) out[(long long)seg * ne + e] = ((s[0][te] + s[1][te]) + s[2][te]) + s[3][te];
 }
 
-// launch: wide element ranges take 16 elements per workgroup, narrow ones 4
-// (more thread groups over k)
-static void sum_parts(const float* part, int nblk, int ne, float* out, hipStream_t s) {
-  if (ne >= 16 * 256) {
-    const long long g = (ne + 15) / 16;
-    hipLaunchKernelGGL(k_sum_parts<16>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, part, nblk, ne, out);
-  } else {
-    hipLaunchKernelGGL(k_sum_parts<4>, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s, part, nblk, ne, out);
-  }
+// out[e] = sum over k < nblk of part[k ne + e], in two fixed-order stages:
+// segments of kSumRowsSeg rows into scratch (ceil(nblk / kSumRowsSeg) rows
+// of ne), then those rows.
+constexpr int kSumRowsSeg = 64;
+static void sum_parts(const float* part, int nblk, int ne, float* scratch, float* out, hipStream_t s) {
+  const unsigned gx = (unsigned)((ne + 63) / 64);
+  const int nseg = (nblk + kSumRowsSeg - 1) / kSumRowsSeg;
+  hipLaunchKernelGGL(k_sum_rows, dim3(gx, (unsigned)nseg), dim3(256), 0, s, part, nblk, ne, kSumRowsSeg, scratch);
+  hipLaunchKernelGGL(k_sum_rows, dim3(gx, 1), dim3(256), 0, s, (const float*)scratch, nseg, ne, nseg, out);
 }
 
 // ------------------------------------------------------------ heads
@@ -1220,7 +1214,7 @@ hipError_t launch_head_bwd(const LossArgs& a, int nblk, float* ghead, double* lo
   else if (a.hd.C1 == 16) hipLaunchKernelGGL(k_head_bwd<16>, dim3(nblk), dim3(256), lds, s, a);
   else if (a.hd.C1 == 32) hipLaunchKernelGGL(k_head_bwd<32>, dim3(nblk), dim3(256), lds, s, a);
   else return hipErrorInvalidValue;
-  sum_parts((const float*)a.hpart, nblk, a.ne, ghead, s);
+  sum_parts((const float*)a.hpart, nblk, a.ne, a.hpart + (long long)nblk * a.ne, ghead, s);
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, (const double*)a.lpart, nblk,
                      (double)npix * a.hd.P, (double)npix, lam_w, loss);
   return hipGetLastError();
