@@ -742,7 +742,7 @@ def _unet_conv_flops(H, W, base=16, cin=1):
     return fwd, igrad, fwd
 
 
-def run_unet(args):
+def unet_leg(batch=4, steps=20, warmup=3):
     """Training steps (forward, backward, AdamW) and inference of the
     warm-start U-Net at the production gather's shape, against the dense BF16
     matrix-core peak."""
@@ -750,7 +750,7 @@ def run_unet(args):
     import paper_1711_10214_amd as A
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     dev = torch.device("cuda", 0)
-    B, H, W, P = args.batch, 256, 1024, 32
+    B, H, W, P = batch, 256, 1024, 32
     net = A.UNet(P, base=16)
     net.init_params(seed=0)
     g = torch.Generator(device="cpu").manual_seed(0)
@@ -758,35 +758,35 @@ def run_unet(args):
     t_m = (0.1 * torch.randn((B, P, H, W), generator=g)).to(dev)
     t_w = torch.rand((B, H, W), generator=g).to(dev)
     tp = A.TrainParams(lr=1e-4)
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         net.train_step(x, t_m, t_w, tp, want_loss=False)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         net.train_step(x, t_m, t_w, tp, want_loss=False)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_s = e0.elapsed_time(e1) / 1e3 / args.steps
+    step_s = e0.elapsed_time(e1) / 1e3 / steps
     x1 = x[:1].contiguous()
     for _ in range(3):
         net.forward(x1)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         net.forward(x1)
     e1.record()
     torch.cuda.synchronize()
-    inf_s = e0.elapsed_time(e1) / 1e3 / args.steps
+    inf_s = e0.elapsed_time(e1) / 1e3 / steps
     fwd, igrad, wgrad = _unet_conv_flops(H, W)
     step_flops = B * (fwd + igrad + wgrad)
     achieved = step_flops / step_s / 1e12
     rec = {
         "metric": "warm-start U-Net training steps/s (batch 4, 256 x 1024 gathers, 32 output panels)",
-        "value": args.steps / wall, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "value": steps / wall, "unit": "steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
         "config": {"workload": "unet-train-b4-256x1024-p32", "batch": B, "height": H, "width": W,
                    "out_panels": P, "params": net.n_params},
@@ -798,7 +798,12 @@ def run_unet(args):
                                "(forward, input and weight gradients) / step time",
                      "algorithmic_flops_per_step": step_flops},
     }
-    print(json.dumps(rec), flush=True)
+    return rec
+
+
+def run_unet(args):
+    """The U-Net workload alone (one JSON line)."""
+    print(json.dumps(unet_leg(args.batch, args.steps, args.warmup)), flush=True)
 
 
 def headline(args, w, gth):
@@ -1035,6 +1040,8 @@ def main():
         print("[bench] learned warm start", file=sys.stderr, flush=True)
         rec["warmstart"] = warmstart_leg(ws_prep, label_outer=WS_DEFAULT["label_outer"],
                                          passes=WS_DEFAULT["passes"], ws_curves=WS_DEFAULT["curves"])
+        print("[bench] warm-start U-Net training and inference", file=sys.stderr, flush=True)
+        rec["unet"] = unet_leg(batch=4, steps=20, warmup=3)
     print(json.dumps(rec), flush=True)
 
 

@@ -28,7 +28,8 @@ def test_every_dispatched_workload_exists(bench):
     assert called >= {"run_warmstart", "run_batch", "run_speedratio", "run_survey", "run_unet", "run_separation"}
     for name in called:
         assert callable(getattr(bench, name)), name
-    for name in ("headline", "batch_leg", "aashrt_leg", "warmstart_leg", "separation_leg", "cpu_baseline"):
+    for name in ("headline", "batch_leg", "aashrt_leg", "warmstart_leg", "separation_leg", "unet_leg",
+                 "cpu_baseline"):
         assert callable(getattr(bench, name)), name
 
 
