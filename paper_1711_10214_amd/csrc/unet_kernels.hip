@@ -293,6 +293,8 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
         const long long oa = (((long long)b * H + y) * W + x) * R.Ca + co;
         put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, o[0], o[1], o[2], o[3], R.accA != 0);
       } else {
+        // mode 2 (pooled A): an upsampled A (mode 1) always launches with UP
+        // set, or split with the route left to k_conv_finish
         const int H2 = 2 * H, W2 = 2 * W;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
