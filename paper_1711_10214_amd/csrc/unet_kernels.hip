@@ -569,8 +569,10 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int sub = lane >> 4, n16 = lane & 15;
   const int MI = min(MT, (a.Cout - co0 + 15) >> 4);
-  const int NI = a.CCw >> 4;
-  const int ngx = a.CCw >> 3;
+  // 16-channel input tiles of this chunk holding real channels (the last
+  // chunk of a padded count stages and multiplies only those)
+  const int NI = min(a.CCw, a.Cin - cc * a.CCw + 15) >> 4;
+  const int ngx = 2 * NI;
   const int tiles_x = (W + kWgTW - 1) / kWgTW, tiles_y = (H + kWgTH - 1) / kWgTH;
   const int T = a.B * tiles_x * tiles_y;
   // this lane's transpose-read offsets: pixel n16 / 4 of its k-group, channel quad n16 % 4
