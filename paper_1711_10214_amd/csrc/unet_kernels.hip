@@ -239,40 +239,40 @@ __device__ __forceinline__ void route_store(const ConvArgs& a, f32x4 (&acc)[MT][
   const int sub = lane >> 4, n16 = lane & 15;
   const int y = ty0 + wave;
   if constexpr (UP) {
-    // column-pair sums in place for the A tiles (16-channel tiles lie wholly
-    // in A or in B, Ca being a multiple of 16)
+    // column-pair sums (DPP lane swap) of the A tiles, written by the even
+    // lanes of every wave to LDS as [row][A column][channel of the tile]
+    // (16-channel tiles lie wholly in A or in B, Ca being a multiple of 16);
+    // then every thread adds the two rows of an A pixel and stores four of
+    // its channels, consecutive threads taking consecutive channels, then
+    // A columns, so that the stores are contiguous
+    constexpr int XA = 8 * NTL;        // A columns of the tile
+    constexpr int CS = 16 * MT + 4;    // LDS floats per A column of a row
+    const int MA = max(0, min(MI, (R.Ca - co0) >> 4));  // A tiles of this workgroup
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi) {
-      if (mi >= MI || co0 + mi * 16 >= R.Ca) continue;
+      if (mi >= MA) continue;
 #pragma unroll
-      for (int ni = 0; ni < NTL; ++ni)
+      for (int ni = 0; ni < NTL; ++ni) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[mi][ni][i] += lane_pair_swap(acc[mi][ni][i]);
-      if (wave & 1) {
-#pragma unroll
-        for (int ni = 0; ni < NTL; ++ni)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) red[((((wave >> 1) * MT + mi) * NTL + ni) * 4 + i) * 64 + lane] = acc[mi][ni][i];
+        if (!(n16 & 1))
+          *reinterpret_cast<float4*>(red + (wave * XA + ((ni * 16 + n16) >> 1)) * CS + mi * 16 + sub * 4) =
+              make_float4(acc[mi][ni][0], acc[mi][ni][1], acc[mi][ni][2], acc[mi][ni][3]);
       }
     }
     __syncthreads();
-    if (!(wave & 1) && y < H && !(n16 & 1)) {
-      const int Hh = H >> 1, Wh = W >> 1;
-#pragma unroll
-      for (int mi = 0; mi < MT; ++mi) {
-        const int co = co0 + mi * 16 + sub * 4;
-        if (mi >= MI || co0 + mi * 16 >= R.Ca) continue;
-#pragma unroll
-        for (int ni = 0; ni < NTL; ++ni) {
-          const int x = tx0 + ni * 16 + n16;
-          if (x >= W) continue;
-          float t[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) t[i] = acc[mi][ni][i] + red[((((wave >> 1) * MT + mi) * NTL + ni) * 4 + i) * 64 + lane];
-          const long long oa = (((long long)b * Hh + (y >> 1)) * Wh + (x >> 1)) * R.Ca + co;
-          put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, t[0], t[1], t[2], t[3], R.accA != 0);
-        }
-      }
+    const int ng = MA * 4, Hh = H >> 1, Wh = W >> 1;
+    for (int idx = (int)threadIdx.x; idx < 2 * XA * ng; idx += 256) {
+      const int g = idx % ng, rest = idx / ng;
+      const int xa = rest % XA, ya = rest / XA;
+      const int yh = (ty0 >> 1) + ya, xh = (tx0 >> 1) + xa;
+      if (yh >= Hh || xh >= Wh) continue;
+      // (g00 + g01) + (g10 + g11): row 2 ya, then row 2 ya + 1
+      const float4 r0 = *reinterpret_cast<const float4*>(red + ((2 * ya) * XA + xa) * CS + 4 * g);
+      const float4 r1 = *reinterpret_cast<const float4*>(red + ((2 * ya + 1) * XA + xa) * CS + 4 * g);
+      const long long oa = (((long long)b * Hh + yh) * Wh + xh) * R.Ca + co0 + 4 * g;
+      put4(R.gA + oa, R.mA ? R.mA + oa : nullptr, r0.x + r1.x, r0.y + r1.y, r0.z + r1.z, r0.w + r1.w,
+           R.accA != 0);
     }
   }
   if (y >= H) return;
@@ -1135,8 +1135,8 @@ static void conv3_launch(const ConvArgs& a, bool af32, bool outf32, hipStream_t 
   size_t lds = (size_t)(kConvTH + 2) * (16 * NTL + 2) * (a.pk.CC + 8) * sizeof(uint16_t);
   if constexpr (MT == 4) {
     if (ks == 1 && outf32 && a.rt.gA && a.rt.modeA == 1) {
-      // an upsampled route exchanges two waves' MT x NTL x 4 sums per lane
-      lds = std::max(lds, (size_t)2 * MT * NTL * 4 * 64 * sizeof(float));
+      // an upsampled route stages every wave's column-pair sums of its A tiles
+      lds = std::max(lds, (size_t)4 * (8 * NTL) * (16 * MT + 4) * sizeof(float));
       hipLaunchKernelGGL((k_conv3<true, true, MT, NTL, true>), grid, dim3(256), lds, s, a);
       return;
     }
