@@ -27,6 +27,19 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 __host__ __device__ constexpr int fft_pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int fft_padlen(int n) { return n + (n >> 4); }
 
+// True when fft_pad(x + r S) == fft_pad(x) + fft_pad(r S) for every r < R
+// and every x congruent mod 16 to q QS + m (q >= 0, 0 <= m < M): no step r S
+// carries out of x's low four bits.  A butterfly's R padded addresses are
+// then one base plus compile-time offsets, which the LDS instructions take
+// as immediates instead of a shift and two adds per element.
+constexpr bool pad_linear(int S, int R, int QS, int M) {
+  for (int q = 0; q < 16; ++q)
+    for (int m = 0; m < M && m < 16; ++m)
+      for (int r = 0; r < R; ++r)
+        if (((q * QS + m) & 15) + ((r * S) & 15) >= 16) return false;
+  return true;
+}
+
 // Index of logical element i of a buffer written by an FFT of compile-time
 // length N (padded) or by the generic runtime FFT (N == 0, unpadded).
 template <int N>
@@ -162,6 +175,12 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
   constexpr int B = N / R;
   constexpr int TW = P::twoff(PASS);
   constexpr int MAXB = (NBN / R + NT - 1) / NT;
+  // reads x[j + r B], j < B; writes y[jq Ns R + jm + r Ns], jm < Ns
+  constexpr bool RLIN = IO != 1 && pad_linear(B, R, 0, B);
+  constexpr bool WLIN = IO != 2 && IO != 4 && pad_linear(Ns, R, Ns * R, Ns);
+  // one transform whose butterflies split evenly over the NT threads of the
+  // workgroup: every id below is a butterfly, so no lane test is needed
+  constexpr bool FULL = NBN == N && B % NT == 0;
   float2 v[MAXB][R];
   int dst[MAXB], bq[MAXB];
   const int total = B * nb;
@@ -170,16 +189,21 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
   for (int i = 0; i < MAXB; ++i) {
     const int id = tid + i * NT;
     dst[i] = -1;
-    if (id < total) {
-      const int b = id / B;
+    if (FULL || id < total) {
+      // one transform (NBN == N) has b = 0; indices are non-negative, so
+      // unsigned division by the compile-time B and Ns is a shift or mul_hi
+      const int b = NBN == N ? 0 : (int)((unsigned)id / (unsigned)B);
       const int j = id - b * B;
-      const int jq = j / Ns;
+      const int jq = (int)((unsigned)j / (unsigned)Ns);
       const int jm = j - jq * Ns;
       const float2* src = buf + b * bstride;
+      const float2* s0 = src + fft_pad(j);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (IO == 1) v[i][r] = pair_get<N>(src, j + r * B);
+        else if constexpr (IO == 3 && RLIN) v[i][r] = (j + r * B < nvalid) ? s0[fft_pad(r * B)] : make_float2(0.f, 0.f);
         else if constexpr (IO == 3) v[i][r] = (j + r * B < nvalid) ? src[fft_pad(j + r * B)] : make_float2(0.f, 0.f);
+        else if constexpr (RLIN) v[i][r] = s0[fft_pad(r * B)];
         else v[i][r] = src[fft_pad(j + r * B)];
       }
       if constexpr (Ns > 1) {
@@ -194,8 +218,8 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
         }
       }
       dft_r<R, INV>(v[i]);
-      dst[i] = b * bstride;
       bq[i] = jq * Ns * R + jm;
+      dst[i] = b * bstride + (WLIN ? fft_pad(bq[i]) : 0);
     }
   }
   __syncthreads();
@@ -207,13 +231,15 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
   }
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    if (dst[i] >= 0) {
+    if (FULL || dst[i] >= 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (IO == 2) {
           pair_put<N>(buf + dst[i], bq[i] + r * Ns, v[i][r]);
         } else if constexpr (IO == 4) {
           if (bq[i] + r * Ns < nvalid) buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+        } else if constexpr (WLIN) {
+          buf[dst[i] + fft_pad(r * Ns)] = v[i][r];
         } else {
           buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
         }
@@ -284,7 +310,7 @@ struct FftRegsIn {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int t = id + r * B;
-        v[i][r] = (id < B && t < nt) ? src[t] : make_float2(0.f, 0.f);
+        v[i][r] = ((B % NT == 0 || id < B) && t < nt) ? src[t] : make_float2(0.f, 0.f);
       }
     }
   }
@@ -301,10 +327,15 @@ __device__ __forceinline__ void fft_tpl_regs_pass0(float2* buf, FftRegsIn<N, NT>
 #pragma unroll
   for (int i = 0; i < I::MAXB; ++i) {
     const int id = tid + i * NT;
-    if (id < I::B) {
+    if (I::B % NT == 0 || id < I::B) {
       dft_r<I::R, INV>(in.v[i]);
+      constexpr bool LIN = pad_linear(1, I::R, I::R, 1);
+      float2* d0 = buf + fft_pad(id * I::R);
 #pragma unroll
-      for (int r = 0; r < I::R; ++r) buf[fft_pad(id * I::R + r)] = in.v[i][r];
+      for (int r = 0; r < I::R; ++r) {
+        if constexpr (LIN) d0[r] = in.v[i][r];
+        else buf[fft_pad(id * I::R + r)] = in.v[i][r];
+      }
     }
   }
   __syncthreads();
@@ -344,9 +375,11 @@ __device__ __forceinline__ void fft_tpl_passes_to_regs(float2* buf, const float2
 #pragma unroll
   for (int i = 0; i < O::MAXB; ++i) {
     const int id = tid + i * NT;
-    if (id < O::B) {
+    if (O::B % NT == 0 || id < O::B) {
+      constexpr bool LIN = pad_linear(O::B, O::R, 0, O::B);
+      const float2* s0 = buf + fft_pad(id);
 #pragma unroll
-      for (int r = 0; r < O::R; ++r) out.v[i][r] = buf[fft_pad(id + r * O::B)];
+      for (int r = 0; r < O::R; ++r) out.v[i][r] = LIN ? s0[fft_pad(r * O::B)] : buf[fft_pad(id + r * O::B)];
       float2 w1 = twp[TW + id];
       if (INV) w1.y = -w1.y;
       float2 w = w1;
