@@ -40,6 +40,13 @@ constexpr bool pad_linear(int S, int R, int QS, int M) {
   return true;
 }
 
+// fft_pad(x + c) for a constant c >= 0 from p = fft_pad(x) and lo = x & 15:
+// the step adds c + c/16 slots, and one more when x's low four bits carry
+// (a compare against a constant instead of a shift and two adds).
+__device__ __forceinline__ int pad_step(int p, int lo, int c) {
+  return p + c + (c >> 4) + ((c & 15) != 0 && lo >= 16 - (c & 15) ? 1 : 0);
+}
+
 // Index of logical element i of a buffer written by an FFT of compile-time
 // length N (padded) or by the generic runtime FFT (N == 0, unpadded).
 template <int N>
@@ -219,7 +226,14 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
       }
       dft_r<R, INV>(v[i]);
       bq[i] = jq * Ns * R + jm;
-      dst[i] = b * bstride + (WLIN ? fft_pad(bq[i]) : 0);
+      // padded layout: dst is the padded address of bq, and bq keeps only
+      // its low four bits when the steps r Ns need them
+      if constexpr (IO == 2 || IO == 4) {
+        dst[i] = b * bstride;
+      } else {
+        dst[i] = b * bstride + fft_pad(bq[i]);
+        bq[i] &= 15;
+      }
     }
   }
   __syncthreads();
@@ -241,7 +255,7 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
         } else if constexpr (WLIN) {
           buf[dst[i] + fft_pad(r * Ns)] = v[i][r];
         } else {
-          buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];
+          buf[pad_step(dst[i], bq[i], r * Ns)] = v[i][r];
         }
       }
     }
@@ -330,11 +344,11 @@ __device__ __forceinline__ void fft_tpl_regs_pass0(float2* buf, FftRegsIn<N, NT>
     if (I::B % NT == 0 || id < I::B) {
       dft_r<I::R, INV>(in.v[i]);
       constexpr bool LIN = pad_linear(1, I::R, I::R, 1);
-      float2* d0 = buf + fft_pad(id * I::R);
+      const int p0 = fft_pad(id * I::R), lo = (id * I::R) & 15;
 #pragma unroll
       for (int r = 0; r < I::R; ++r) {
-        if constexpr (LIN) d0[r] = in.v[i][r];
-        else buf[fft_pad(id * I::R + r)] = in.v[i][r];
+        if constexpr (LIN) buf[p0 + r] = in.v[i][r];
+        else buf[pad_step(p0, lo, r)] = in.v[i][r];
       }
     }
   }
