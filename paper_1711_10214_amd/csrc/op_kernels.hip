@@ -1108,19 +1108,41 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
       const RowA2 aup = split_a2(PD.c2 * lup2);
       const RowA2 alo = split_a2(PD.c2 * llo2);
       const int jcone_lo = (r == 0) ? cone_first_bin(PD.c2 * llo2) : 0;
+      auto put = [&](int j, float2 au, float2 al) {
+        float2* du = acc + (j - jlo);
+        float2* dl = acc + nband + (j - jlo);
+        if (plain) {
+          *du = cfma(PD.scale, au, *du);
+          *dl = cfma(PD.scale, al, *dl);
+        } else {
+          const float2 cj = bin_factor(G, PD, A.tw, A.wav, j);
+          *du = cadd(*du, cmul(cj, au));
+          *dl = cadd(*dl, cmul(cj, al));
+        }
+      };
+      // rows >= 1 and row 0 run separate loops, so that no tap load is
+      // shared between them: the rows >= 1 loop then reads each 16-byte
+      // pair with one ds_read_b128 at an immediate offset
+      if (r != 0) {
 #pragma unroll 1
-      for (int j = jstart + (int)threadIdx.x; j <= jhi; j += NT) {
-        float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
-        const Taps4 tu = taps4(j, aup);
-        const float4* qu = P4 + (tu.k0 - 3);
-        if (r != 0) {
+        for (int j = jstart + (int)threadIdx.x; j <= jhi; j += NT) {
+          float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
+          const Taps4 tu = taps4(j, aup);
+          const float4* qu = P4 + (tu.k0 - 3);
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
             const float4 q = qu[t];
             au = cfma(tu.w[t], make_float2(q.x, q.y), au);
             al = cfma(tu.w[t], make_float2(q.z, -q.w), al);
           }
-        } else {
+          put(j, au, al);
+        }
+      } else {
+#pragma unroll 1
+        for (int j = jstart + (int)threadIdx.x; j <= jhi; j += NT) {
+          float2 au = make_float2(0.f, 0.f), al = make_float2(0.f, 0.f);
+          const Taps4 tu = taps4(j, aup);
+          const float4* qu = P4 + (tu.k0 - 3);
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
             const float4 q = qu[t];
@@ -1135,16 +1157,7 @@ __device__ __forceinline__ void rows_fwd_item(const RowsArgs& A, const WorkItem&
               al = cfma(tl.w[t], make_float2(q.z, -q.w), al);
             }
           }
-        }
-        float2* du = acc + (j - jlo);
-        float2* dl = acc + nband + (j - jlo);
-        if (plain) {
-          *du = cfma(PD.scale, au, *du);
-          *dl = cfma(PD.scale, al, *dl);
-        } else {
-          const float2 cj = bin_factor(G, PD, A.tw, A.wav, j);
-          *du = cadd(*du, cmul(cj, au));
-          *dl = cadd(*dl, cmul(cj, al));
+          put(j, au, al);
         }
       }
       __syncthreads();
