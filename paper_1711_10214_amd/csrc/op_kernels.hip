@@ -28,6 +28,8 @@
 #include "block_reduce.h"
 #include "fft_tpl.h"
 #include "kernels.h"
+
+#include <type_traits>
 #include "tap_poly.h"
 
 namespace ashrt {
@@ -1436,9 +1438,12 @@ struct ScatterBin4 {
   float2 e1, e2;
 };
 
+// MODE 0: a row r >= 1; 1: row 0's l = 0 half (pass 0); 2: its Nyquist half
+// (pass 1).  A compile-time mode keeps the per-bin selection of the two
+// scattered values out of the bin loop.
+template <int MODE>
 __device__ __forceinline__ ScatterBin4 scatter_bin4(const RowsArgs& A, const GatherDev& G, const PanelDev& PD,
-                                                    bool plain, const float2* bufD, int r, int pass, RowA2 a, int j,
-                                                    int jmax) {
+                                                    bool plain, const float2* bufD, RowA2 a, int j, int jmax) {
   ScatterBin4 b;
   b.k0 = kNoTap;
   b.e1 = b.e2 = make_float2(0.f, 0.f);
@@ -1460,10 +1465,10 @@ __device__ __forceinline__ ScatterBin4 scatter_bin4(const RowsArgs& A, const Gat
     du = cmulconj(du, c);
     dl = cmulconj(dl, c);
   }
-  if (r != 0) {
+  if constexpr (MODE == 0) {
     b.e1 = du;
     b.e2 = cconj(dl);
-  } else if (pass == 0) {
+  } else if constexpr (MODE == 1) {
     b.e1 = du;
     b.e2 = cconj(du);
   } else {
@@ -1521,30 +1526,36 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
       if constexpr (RC > 0) {
         static_assert(RC == 4, "compile-time row kernels use the half-width-4 weight polynomials");
         const RowA2 a = split_a2(a2);
-        for (int ph = 0; ph < 2; ++ph) {
+        auto scatter = [&](auto mode) {
+          constexpr int MODE = decltype(mode)::value;
+          for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll 1
-          for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
-            const ScatterBin4 sb = scatter_bin4(A, G, PD, plain, bufD, r, pass, a, jb + sg * 64 + lane, jhi);
-            if (sb.k0 != kNoTap) {
-              // taps below bin 1 land in the padding that ends bufD (never
-              // read after its transform), taps past N/2-1 in bufM's own
-              // padding (overwritten by its transform), and pair 0 is never
-              // read by the inverse transform
-              float4* q0 = reinterpret_cast<float4*>(bufM) + (sb.k0 - 3);
+            for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
+              const ScatterBin4 sb = scatter_bin4<MODE>(A, G, PD, plain, bufD, a, jb + sg * 64 + lane, jhi);
+              if (sb.k0 != kNoTap) {
+                // taps below bin 1 land in the padding that ends bufD (never
+                // read after its transform), taps past N/2-1 in bufM's own
+                // padding (overwritten by its transform), and pair 0 is never
+                // read by the inverse transform
+                float4* q0 = reinterpret_cast<float4*>(bufM) + (sb.k0 - 3);
 #pragma unroll
-              for (int t = 0; t < 8; ++t) {
-                float4 v = q0[t];
-                v.x = fmaf(sb.w[t], sb.e1.x, v.x);
-                v.y = fmaf(sb.w[t], sb.e1.y, v.y);
-                v.z = fmaf(sb.w[t], sb.e2.x, v.z);
-                v.w = fmaf(sb.w[t], sb.e2.y, v.w);
-                q0[t] = v;
-                __builtin_amdgcn_wave_barrier();
+                for (int t = 0; t < 8; ++t) {
+                  float4 v = q0[t];
+                  v.x = fmaf(sb.w[t], sb.e1.x, v.x);
+                  v.y = fmaf(sb.w[t], sb.e1.y, v.y);
+                  v.z = fmaf(sb.w[t], sb.e2.x, v.z);
+                  v.w = fmaf(sb.w[t], sb.e2.y, v.w);
+                  q0[t] = v;
+                  __builtin_amdgcn_wave_barrier();
+                }
               }
             }
+            __syncthreads();
           }
-          __syncthreads();
-        }
+        };
+        if (r != 0) scatter(std::integral_constant<int, 0>{});
+        else if (pass == 0) scatter(std::integral_constant<int, 1>{});
+        else scatter(std::integral_constant<int, 2>{});
         continue;
       }
       for (int ph = 0; ph < 2; ++ph) {
