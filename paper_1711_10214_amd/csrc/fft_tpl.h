@@ -207,7 +207,18 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
       const float2* s0 = src + fft_pad(j);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if constexpr (IO == 1) v[i][r] = pair_get<N>(src, j + r * B);
+        if constexpr (IO == 1 && R % 2 == 0) {
+          // B R = N and j < B: element j + r B lies below N/2 exactly when
+          // r < R/2, so each read is one of two bases plus a constant
+          // (elements 0 and N/2, for j = 0, read a valid slot and are zeroed)
+          if (r < R / 2) {
+            const float2 x = src[2 * j + 2 * r * B];
+            v[i][r] = (r == 0 && j == 0) ? make_float2(0.f, 0.f) : x;
+          } else {
+            const float2 x = src[2 * (N - j) + 1 - 2 * r * B];
+            v[i][r] = (r == R / 2 && j == 0) ? make_float2(0.f, 0.f) : x;
+          }
+        } else if constexpr (IO == 1) v[i][r] = pair_get<N>(src, j + r * B);
         else if constexpr (IO == 3 && RLIN) v[i][r] = (j + r * B < nvalid) ? s0[fft_pad(r * B)] : make_float2(0.f, 0.f);
         else if constexpr (IO == 3) v[i][r] = (j + r * B < nvalid) ? src[fft_pad(j + r * B)] : make_float2(0.f, 0.f);
         else if constexpr (RLIN) v[i][r] = s0[fft_pad(r * B)];
@@ -248,7 +259,15 @@ __device__ __forceinline__ void tpl_pass(float2* buf, int nb, int bstride, const
     if (FULL || dst[i] >= 0) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if constexpr (IO == 2) {
+        if constexpr (IO == 2 && R % 2 == 0 && Ns * R == N) {
+          // last pass: bq = jm < Ns, so output jm + r Ns lies below N/2
+          // exactly when r < R/2 (outputs 0 and N/2, for jm = 0, are dropped)
+          if (r < R / 2) {
+            if (r != 0 || bq[i] != 0) buf[dst[i] + 2 * bq[i] + 2 * r * Ns] = v[i][r];
+          } else {
+            if (r != R / 2 || bq[i] != 0) buf[dst[i] + 2 * (N - bq[i]) + 1 - 2 * r * Ns] = v[i][r];
+          }
+        } else if constexpr (IO == 2) {
           pair_put<N>(buf + dst[i], bq[i] + r * Ns, v[i][r]);
         } else if constexpr (IO == 4) {
           if (bq[i] + r * Ns < nvalid) buf[dst[i] + fft_pad(bq[i] + r * Ns)] = v[i][r];

@@ -200,9 +200,10 @@ __device__ __forceinline__ Taps4 taps4(int j, RowA2 a) {
   const float u = __builtin_amdgcn_sqrtf(fmaxf(u2, 0.f));
   // exact floor of sqrt(jj - f): k0^2 <= kf < (k0 + 1)^2 with kf = jj - [f > 0]
   const int kf = jj - (a.f > 0.f ? 1 : 0);
+  // (no branch: at most one of the two corrections applies)
   int k0 = (int)u;
-  if ((int)__umul24((unsigned)k0, (unsigned)k0) > kf) --k0;
-  else if ((int)__umul24((unsigned)(k0 + 1), (unsigned)(k0 + 1)) <= kf) ++k0;
+  const int m0 = (int)__umul24((unsigned)k0, (unsigned)k0);
+  k0 += (m0 + 2 * k0 + 1 <= kf ? 1 : 0) - (m0 > kf ? 1 : 0);
   const float rem = (float)(jj - (int)__umul24((unsigned)k0, (unsigned)k0)) - a.f;
   const float dl = rem * __builtin_amdgcn_rcpf(fmaxf(u + (float)k0, 1e-30f));
   const float z = fmaf(2.0f * kTapZScale, dl, -kTapZScale);
