@@ -1527,26 +1527,49 @@ __device__ __forceinline__ void rows_adj_item(const RowsArgs& A, const WorkItem&
       if constexpr (RC > 0) {
         static_assert(RC == 4, "compile-time row kernels use the half-width-4 weight polynomials");
         const RowA2 a = split_a2(a2);
+        // Lanes without taps (bins past jhi) scatter zeros into the last
+        // eight 16-byte slots of bufD's padding (never read after its
+        // transform, N / 16 >= 32 slots), so every lane of a segment runs the
+        // same branch-free read-modify-write sequence.
+        float4* const sink = reinterpret_cast<float4*>(bufM) - 8;
+        auto add = [](float4 v, const ScatterBin4& b, int t) {
+          v.x = fmaf(b.w[t], b.e1.x, v.x);
+          v.y = fmaf(b.w[t], b.e1.y, v.y);
+          v.z = fmaf(b.w[t], b.e2.x, v.z);
+          v.w = fmaf(b.w[t], b.e2.y, v.w);
+          return v;
+        };
         auto scatter = [&](auto mode) {
           constexpr int MODE = decltype(mode)::value;
           for (int ph = 0; ph < 2; ++ph) {
+            // a wave takes its segments two at a time (sg and sg + 2 NW, far
+            // apart in the band, so their model bins are disjoint): the two
+            // read-modify-write chains overlap their LDS latencies
 #pragma unroll 1
-            for (int sg = 2 * wave + ph; sg < nseg; sg += 2 * NW) {
-              const ScatterBin4 sb = scatter_bin4<MODE>(A, G, PD, plain, bufD, a, jb + sg * 64 + lane, jhi);
-              if (sb.k0 != kNoTap) {
-                // taps below bin 1 land in the padding that ends bufD (never
-                // read after its transform), taps past N/2-1 in bufM's own
-                // padding (overwritten by its transform), and pair 0 is never
-                // read by the inverse transform
-                float4* q0 = reinterpret_cast<float4*>(bufM) + (sb.k0 - 3);
+            for (int sg = 2 * wave + ph; sg < nseg; sg += 4 * NW) {
+              // taps below bin 1 land in the padding that ends bufD (never
+              // read after its transform), taps past N/2-1 in bufM's own
+              // padding (overwritten by its transform), and pair 0 is never
+              // read by the inverse transform
+              const ScatterBin4 sa = scatter_bin4<MODE>(A, G, PD, plain, bufD, a, jb + sg * 64 + lane, jhi);
+              float4* qa = sa.k0 != kNoTap ? reinterpret_cast<float4*>(bufM) + (sa.k0 - 3) : sink;
+              const int sg2 = sg + 2 * NW;
+              if (sg2 < nseg) {
+                const ScatterBin4 sb = scatter_bin4<MODE>(A, G, PD, plain, bufD, a, jb + sg2 * 64 + lane, jhi);
+                float4* qb = sb.k0 != kNoTap ? reinterpret_cast<float4*>(bufM) + (sb.k0 - 3) : sink;
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                  float4 v = q0[t];
-                  v.x = fmaf(sb.w[t], sb.e1.x, v.x);
-                  v.y = fmaf(sb.w[t], sb.e1.y, v.y);
-                  v.z = fmaf(sb.w[t], sb.e2.x, v.z);
-                  v.w = fmaf(sb.w[t], sb.e2.y, v.w);
-                  q0[t] = v;
+                  // both reads before either write (the compiler cannot tell
+                  // that qa and qb never alias)
+                  const float4 va = qa[t], vb = qb[t];
+                  qa[t] = add(va, sa, t);
+                  qb[t] = add(vb, sb, t);
+                  __builtin_amdgcn_wave_barrier();
+                }
+              } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                  qa[t] = add(qa[t], sa, t);
                   __builtin_amdgcn_wave_barrier();
                 }
               }
